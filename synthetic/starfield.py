@@ -1,0 +1,268 @@
+"""Seeded synthetic star fields and target images for the DIA kernel fit.
+
+Input generation only: this module renders reference images, draws the
+injected kernels and backgrounds, and forms noisy targets.  It is shared by
+the tests, the benchmark and the smoke check, and holds none of the fit's
+arithmetic: the noiseless target is formed with scipy's own correlation
+routine, never with the oracle or the GPU library.
+
+Recipe (Section 3.1 "Generating artificial images" for the scene, the
+workload table in the design doc for the sizes):
+
+* stars at continuous positions uniform over the frame, fluxes log-uniform
+  between ``flux_min`` and ``flux_max`` (the paper's own F^(-3/2) law is
+  available as ``paper_reference``);
+* an analytic PSF (Gaussian or Moffat) sampled at pixel centres on a stamp of
+  radius 10 FWHM, normalised analytically; a constant sky;
+* the injected kernel is an (elliptical) Gaussian sampled on the m x m grid,
+  centred at (h + dy, h + dx) and scaled to the requested sum (the
+  photometric scale factor, eq. photometric_scale_factor);
+* the noiseless target is the reference cross-correlated with that kernel
+  plus B0 (eq. model_image_delta_basis) on the valid region; the border,
+  which the fit never uses, comes from an edge-replicated reference;
+* noise: Poisson in electrons with gain G, plus Gaussian read noise
+  sigma0 (electrons), both converted to ADU, so the matching CCD noise model
+  (eq. CCDNM, F = 1) has sigma0_adu = sigma0 / G.
+
+All random draws come from ``numpy.random.default_rng`` seeded with
+``SeedSequence([2104, 13715, config, epoch])``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy import signal
+
+FWHM_PER_SIGMA = 2.0 * math.sqrt(2.0 * math.log(2.0))
+
+
+def rng_for(config: int, epoch: int = 0) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([2104, 13715, int(config), int(epoch)]))
+
+
+# --------------------------------------------------------------------------- PSFs
+def gaussian_psf(fwhm: float):
+    s = fwhm / FWHM_PER_SIGMA
+    norm = 1.0 / (2.0 * math.pi * s * s)
+
+    def f(r2):
+        return norm * np.exp(-0.5 * r2 / (s * s))
+
+    return f
+
+
+def moffat_psf(fwhm: float, beta: float = 3.0):
+    alpha = fwhm / (2.0 * math.sqrt(2.0 ** (1.0 / beta) - 1.0))
+    norm = (beta - 1.0) / (math.pi * alpha * alpha)
+    inv_a2 = 1.0 / (alpha * alpha)
+
+    def f(r2):
+        return norm * (1.0 + r2 * inv_a2) ** (-beta)
+
+    return f
+
+
+def render_stars(shape, x, y, flux, psf, radius: int, sky: float = 0.0, chunk: int = 4096):
+    """Sum of flux * psf(|p - star|^2) sampled at pixel centres (x = column, y = row)."""
+    H, W = shape
+    out = np.zeros(H * W, dtype=np.float64)
+    off = np.arange(-radius, radius + 1)
+    dy, dx = np.meshgrid(off, off, indexing="ij")
+    dy = dy.ravel()
+    dx = dx.ravel()
+    for s in range(0, len(x), chunk):
+        xs, ys, fs = x[s:s + chunk], y[s:s + chunk], flux[s:s + chunk]
+        cx = np.rint(xs).astype(np.int64)
+        cy = np.rint(ys).astype(np.int64)
+        px = cx[:, None] + dx[None, :]
+        py = cy[:, None] + dy[None, :]
+        r2 = (px - xs[:, None]) ** 2 + (py - ys[:, None]) ** 2
+        val = fs[:, None] * psf(r2)
+        ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
+        out += np.bincount((py * W + px)[ok], weights=val[ok], minlength=H * W)
+    return out.reshape(H, W) + sky
+
+
+def kernel_gaussian(m: int, fwhm_x: float, fwhm_y: float | None = None, rot_deg: float = 0.0,
+                    dx: float = 0.0, dy: float = 0.0, total: float = 1.0) -> np.ndarray:
+    """(Elliptical) Gaussian on the m x m grid, centred at (h + dy, h + dx), summing to ``total``."""
+    if fwhm_y is None:
+        fwhm_y = fwhm_x
+    h = (m - 1) // 2
+    sx = fwhm_x / FWHM_PER_SIGMA
+    sy = fwhm_y / FWHM_PER_SIGMA
+    a, b = np.meshgrid(np.arange(m), np.arange(m), indexing="ij")
+    u = b - (h + dx)
+    v = a - (h + dy)
+    t = math.radians(rot_deg)
+    ur = math.cos(t) * u + math.sin(t) * v
+    vr = -math.sin(t) * u + math.cos(t) * v
+    k = np.exp(-0.5 * ((ur / sx) ** 2 + (vr / sy) ** 2))
+    return k * (total / k.sum())
+
+
+def correlate_target(R: np.ndarray, K: np.ndarray, B0: float) -> np.ndarray:
+    """Noiseless target on R's full grid: correlation with K plus B0; edge-replicated border."""
+    h = (K.shape[0] - 1) // 2
+    Rp = np.pad(R, h, mode="edge")
+    method = "direct" if R.size * K.size < 4e7 else "fft"
+    return signal.correlate(Rp, K, mode="valid", method=method) + B0
+
+
+def add_ccd_noise(I_nl: np.ndarray, gain: float, sigma0_e: float, rng: np.random.Generator) -> np.ndarray:
+    lam = np.clip(I_nl, 0.0, None) * gain
+    e = rng.poisson(lam).astype(np.float64)
+    e += rng.normal(0.0, sigma0_e, size=I_nl.shape)
+    return e / gain
+
+
+# ----------------------------------------------------------------------- workloads
+@dataclass
+class Pair:
+    """One reference/target pair, float32 images as handed to the fit."""
+    R: np.ndarray
+    I: np.ndarray
+    m: int
+    K_true: np.ndarray
+    B0_true: float
+    sigma0_adu: float
+    gain: float
+    I_noiseless: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+
+@dataclass
+class Epoch:
+    I: np.ndarray
+    row0: int
+    col0: int
+    K_true: np.ndarray
+    B0_true: float
+
+
+@dataclass
+class Batch:
+    R: np.ndarray
+    epochs: list
+    m: int
+    sigma0_adu: float
+    gain: float
+    meta: dict = field(default_factory=dict)
+
+
+def star_field(rng, H, W, n_stars, flux_min, flux_max, psf_kind, fwhm, sky, beta=3.0):
+    x = rng.uniform(0.0, W, n_stars)
+    y = rng.uniform(0.0, H, n_stars)
+    flux = 10.0 ** rng.uniform(math.log10(flux_min), math.log10(flux_max), n_stars)
+    psf = gaussian_psf(fwhm) if psf_kind == "gauss" else moffat_psf(fwhm, beta)
+    radius = int(math.ceil(10 * fwhm))
+    return render_stars((H, W), x, y, flux, psf, radius, sky)
+
+
+def make_pair(H, W, m, *, n_stars, flux_min, flux_max, psf_kind, fwhm, sky, K_true, B0,
+              sigma0_e, gain, noise=True, config=0, epoch=0) -> Pair:
+    rng = rng_for(config, epoch)
+    R = star_field(rng, H, W, n_stars, flux_min, flux_max, psf_kind, fwhm, sky)
+    R32 = R.astype(np.float32)
+    I_nl = correlate_target(R32.astype(np.float64), K_true, B0)
+    I = add_ccd_noise(I_nl, gain, sigma0_e, rng) if noise else I_nl
+    return Pair(R=R32, I=I.astype(np.float32), m=m, K_true=K_true, B0_true=B0,
+                sigma0_adu=sigma0_e / gain, gain=gain, I_noiseless=I_nl,
+                meta=dict(H=H, W=W, n_stars=n_stars, psf=psf_kind, fwhm=fwhm, sky=sky))
+
+
+def config1(noise=True) -> Pair:
+    """128^2, 150 stars (1e2..1e5), Gaussian PSF FWHM 2, sky 100; 9x9 Gaussian kernel FWHM 1.5,
+    offset (+0.3, +0.3), sum 1.1; B0 = 5; sigma0 = 5 e-, G = 1."""
+    K = kernel_gaussian(9, 1.5, dx=0.3, dy=0.3, total=1.1)
+    return make_pair(128, 128, 9, n_stars=150, flux_min=1e2, flux_max=1e5, psf_kind="gauss", fwhm=2.0,
+                     sky=100.0, K_true=K, B0=5.0, sigma0_e=5.0, gain=1.0, noise=noise, config=1)
+
+
+def config2(noise=True, size=1024) -> Pair:
+    """1024^2, 5000 stars (1e2..1e6), Moffat beta 3 FWHM 3, sky 500; 19x19 elliptical Gaussian
+    kernel FWHM 2.2 x 1.8 rotated 30 deg, sum 0.9; B0 = -12; sigma0 = 8 e-, G = 1.5."""
+    K = kernel_gaussian(19, 2.2, 1.8, rot_deg=30.0, total=0.9)
+    n = int(round(5000 * (size / 1024) ** 2))
+    return make_pair(size, size, 19, n_stars=n, flux_min=1e2, flux_max=1e6, psf_kind="moffat", fwhm=3.0,
+                     sky=500.0, K_true=K, B0=-12.0, sigma0_e=8.0, gain=1.5, noise=noise, config=2)
+
+
+def config3(noise=True, size=4096) -> Pair:
+    """4096^2 CCD-sized pair, 80,000 stars, Moffat FWHM 3.5; everything else as config 2."""
+    K = kernel_gaussian(19, 2.2, 1.8, rot_deg=30.0, total=0.9)
+    n = int(round(80000 * (size / 4096) ** 2))
+    return make_pair(size, size, 19, n_stars=n, flux_min=1e2, flux_max=1e6, psf_kind="moffat", fwhm=3.5,
+                     sky=500.0, K_true=K, B0=-12.0, sigma0_e=8.0, gain=1.5, noise=noise, config=3)
+
+
+def crop(pair: Pair, size: int) -> Pair:
+    """Central size x size crop of a pair (the same pixels of R and I)."""
+    H, W = pair.R.shape
+    r0, c0 = (H - size) // 2, (W - size) // 2
+    sl = (slice(r0, r0 + size), slice(c0, c0 + size))
+    return Pair(R=np.ascontiguousarray(pair.R[sl]), I=np.ascontiguousarray(pair.I[sl]), m=pair.m,
+                K_true=pair.K_true, B0_true=pair.B0_true, sigma0_adu=pair.sigma0_adu, gain=pair.gain,
+                I_noiseless=None if pair.I_noiseless is None else pair.I_noiseless[sl],
+                meta=dict(pair.meta, crop=size))
+
+
+def batched(config: int, n_epochs: int, m: int, ref_size: int, n_stars: int, side_range, *,
+            fwhm=3.0, noise=True) -> Batch:
+    """Shared reference star field with per-epoch targets cut from it.
+
+    Each epoch e draws a square side in ``side_range`` (inclusive), a crop offset uniform in
+    [0, ref_size - side], a Gaussian kernel with FWHM ~ U(1.2, 3.0), sum ~ U(0.7, 1.3) and
+    subpixel offset ~ U(-0.5, 0.5)^2, and B0 ~ U(-50, 50)."""
+    rng = rng_for(config, 0)
+    R = star_field(rng, ref_size, ref_size, n_stars, 1e2, 1e6, "moffat", fwhm, 500.0).astype(np.float32)
+    R64 = R.astype(np.float64)
+    gain, sigma0_e = 1.5, 8.0
+    epochs = []
+    for e in range(n_epochs):
+        er = rng_for(config, e + 1)
+        lo, hi = side_range
+        side = int(er.integers(lo, hi + 1))
+        r0 = int(er.integers(0, ref_size - side + 1))
+        c0 = int(er.integers(0, ref_size - side + 1))
+        K = kernel_gaussian(m, er.uniform(1.2, 3.0), dx=er.uniform(-0.5, 0.5), dy=er.uniform(-0.5, 0.5),
+                            total=er.uniform(0.7, 1.3))
+        B0 = float(er.uniform(-50.0, 50.0))
+        I_nl = correlate_target(R64[r0:r0 + side, c0:c0 + side], K, B0)
+        I = add_ccd_noise(I_nl, gain, sigma0_e, er) if noise else I_nl
+        epochs.append(Epoch(I=I.astype(np.float32), row0=r0, col0=c0, K_true=K, B0_true=B0))
+    return Batch(R=R, epochs=epochs, m=m, sigma0_adu=sigma0_e / gain, gain=gain,
+                 meta=dict(config=config, ref_size=ref_size, n_stars=n_stars, side_range=side_range))
+
+
+def config4(noise=True, n_epochs=64, ref_size=2048, side_range=(512, 2048)) -> Batch:
+    """64 epochs of side U{512..2048} cut from a shared 2048^2 reference (30,000 stars), 17x17 kernels."""
+    n = int(round(30000 * (ref_size / 2048) ** 2))
+    return batched(4, n_epochs, 17, ref_size, n, side_range, noise=noise)
+
+
+def config5(noise=True, n_epochs=256, ref_size=2048) -> Batch:
+    """256 epochs at 2048^2 against one shared 2048^2 reference (40,000 stars), 25x25 kernels."""
+    n = int(round(40000 * (ref_size / 2048) ** 2))
+    return batched(5, n_epochs, 25, ref_size, n, (ref_size, ref_size), noise=noise)
+
+
+def paper_reference(size: int = 142, seed: int = 0, phi_R: float | None = None) -> np.ndarray:
+    """Noiseless reference following Section 3.1 steps (i)-(v): Gaussian PSF with standard deviation
+    phi_R ~ U(0.5, 2.5), lg star density per 100x100 px ~ U(0, 3), F^(-3/2) ~ U(1e-9, 10^-4.5),
+    the brightest star moved to the centre, sky ~ U(10, 1000)."""
+    rng = rng_for(0, 1000 + seed)
+    if phi_R is None:
+        phi_R = rng.uniform(0.5, 2.5)
+    lg_rho = rng.uniform(0.0, 3.0)
+    n = max(1, int(round(10.0 ** lg_rho * (size / 100.0) ** 2)))
+    x = rng.uniform(0.0, size, n)
+    y = rng.uniform(0.0, size, n)
+    f = rng.uniform(1e-9, 10 ** -4.5, n) ** (-2.0 / 3.0)
+    k = int(np.argmax(f))
+    x[k] = y[k] = size / 2.0
+    fwhm = phi_R * FWHM_PER_SIGMA
+    return render_stars((size, size), x, y, f, gaussian_psf(fwhm), int(math.ceil(10 * fwhm)),
+                        rng.uniform(10.0, 1000.0))

@@ -1,0 +1,457 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties one oracle function to a library routine, a closed form, a
+finite difference, brute force on tiny inputs, or a value/behaviour the paper
+prints (tests/golden/paper_values.json).  CPU only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.ndimage
+import scipy.signal
+import scipy.special
+import scipy.stats
+
+import oracle
+from synthetic import starfield as sf
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+
+RHOS = ["gauss", "huber", "cauchy"]
+VARS = ["weights", "ccd_data", "ccd_model", "emccd_data", "emccd_model"]
+
+
+def tiny_problem(seed=0, H=12, W=11, m=3):
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(50.0, 400.0, (H, W))
+    theta = np.concatenate([rng.uniform(-0.1, 0.4, m * m), [rng.uniform(-5, 5)]])
+    I = rng.uniform(20.0, 500.0, (H, W))
+    return R, I, theta
+
+
+def brute_design(R, m):
+    """Design matrix by explicit Python loops: row (i, j), column (a, b) -> R[i+a, j+b]; last column 1."""
+    H, W = R.shape
+    rows = []
+    for i in range(H - m + 1):
+        for j in range(W - m + 1):
+            rows.append([R[i + a, j + b] for a in range(m) for b in range(m)] + [1.0])
+    return np.array(rows)
+
+
+def make_obj(rho, var, H, W, rng, with_mask=False):
+    obj = oracle.Objective(rho=rho, var=var, sigma0=3.0, gain=1.7, excess=2.0, var_floor=1.0,
+                           c=1.345 if rho == "huber" else 2.3849)
+    if var == "weights":
+        obj.weights = rng.uniform(0.01, 0.2, (H, W))
+    obj.flat = rng.uniform(0.8, 1.2, (H, W))
+    if with_mask:
+        obj.mask = (rng.uniform(size=(H, W)) > 0.2).astype(np.uint8)
+    return obj
+
+
+# --------------------------------------------------------------------- model / correlation
+@pytest.mark.parametrize("m", [1, 3, 5])
+def test_model_matches_brute_design_and_scipy(m):
+    R, _, theta = tiny_problem(1, 12, 11, m)
+    M = oracle.model(R, theta, m)
+    X = brute_design(R, m)
+    np.testing.assert_allclose(M.ravel(), X @ theta, rtol=1e-13, atol=1e-10)
+    K = theta[:m * m].reshape(m, m)
+    ref = scipy.signal.correlate2d(R, K, mode="valid") + theta[-1]
+    np.testing.assert_allclose(M, ref, rtol=1e-13, atol=1e-10)
+
+
+def test_valid_pixel_count_matches_paper():
+    g = GOLD["valid_pixels_142_m19"]
+    assert oracle.n_data(142, 142, 19) == g["value"]
+    R = np.zeros((142, 142))
+    assert oracle.model(R, np.zeros(19 * 19 + 1), 19).size == g["value"]
+
+
+def test_correlation_convention_pinned_by_shift():
+    # Sec. 3.4 (iii): target = reference shifted by +1 in x and y -> identity kernel at (-1, -1).
+    m = 5
+    h = 2
+    R = np.random.default_rng(3).uniform(0, 100, (20, 20))
+    I = np.zeros_like(R)
+    I[1:, 1:] = R[:-1, :-1]
+    off = GOLD["e2_iii_kernel_offset"]["value"]
+    theta = np.zeros(m * m + 1)
+    theta[(h + off[0]) * m + (h + off[1])] = 1.0
+    M = oracle.model(R, theta, m)
+    np.testing.assert_array_equal(M, oracle.valid(I, m))
+
+
+# --------------------------------------------------------------------- loss shapes
+def test_huber_rho_is_scipy_huber():
+    z = np.linspace(-6, 6, 1001)
+    for c in (0.5, 1.345, 3.0):
+        r, p, d = oracle.rho_psi_dpsi("huber", z, c)
+        np.testing.assert_allclose(r, scipy.special.huber(c, z), rtol=1e-14, atol=1e-14)
+
+
+def test_cauchy_rho_is_scaled_cauchy_logpdf():
+    z = np.linspace(-30, 30, 1001)
+    c = 2.3849
+    r, _, _ = oracle.rho_psi_dpsi("cauchy", z, c)
+    ref = -(c * c / 2.0) * (scipy.stats.cauchy.logpdf(z, scale=c) + math.log(math.pi * c))
+    np.testing.assert_allclose(r, ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("rho", RHOS)
+def test_psi_and_dpsi_are_derivatives(rho):
+    z = np.concatenate([np.linspace(-8, -1.4, 50), np.linspace(-1.3, 1.3, 50), np.linspace(1.4, 8, 50)])
+    c = 1.345 if rho == "huber" else 2.3849
+    e = 1e-6
+    r, p, d = oracle.rho_psi_dpsi(rho, z, c)
+    rp, pp, _ = oracle.rho_psi_dpsi(rho, z + e, c)
+    rm, pm, _ = oracle.rho_psi_dpsi(rho, z - e, c)
+    np.testing.assert_allclose(p, (rp - rm) / (2 * e), rtol=1e-7, atol=1e-7)
+    np.testing.assert_allclose(d, (pp - pm) / (2 * e), rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("rho", ["huber", "cauchy"])
+def test_robust_losses_reduce_to_gauss_for_large_c(rho):
+    z = np.linspace(-5, 5, 101)
+    g = oracle.rho_psi_dpsi("gauss", z, 1.0)
+    r = oracle.rho_psi_dpsi(rho, z, 1e7)
+    for a, b in zip(g, r):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-9)
+
+
+@pytest.mark.parametrize("var", ["ccd_data", "ccd_model", "emccd_data", "emccd_model"])
+def test_gauss_loss_is_negative_log_likelihood(var):
+    # eq. loglikelihood: -ln p = 1/2 chi^2 + sum ln sigma + N/2 ln 2 pi, checked with scipy's normal logpdf.
+    rng = np.random.default_rng(5)
+    R, I, theta = tiny_problem(5, 14, 13, 3)
+    obj = make_obj("gauss", var, *R.shape, rng)
+    Iv = oracle.valid(I, 3)
+    M = oracle.model(R, theta, 3)
+    X = M if obj.model_sigma else Iv
+    F = oracle.valid(obj.flat, 3)
+    if var.startswith("ccd"):
+        v = obj.sigma0 ** 2 / F ** 2 + np.maximum(X, 0) / (obj.gain * F)
+    else:
+        v = np.maximum(obj.excess * np.maximum(X, 0) / (obj.gain * F), obj.var_floor)
+    nll = -np.sum(scipy.stats.norm.logpdf(Iv, loc=M, scale=np.sqrt(v)))
+    L, _ = oracle.loss_grad(R, I, theta, 3, obj)
+    const = 0.5 * Iv.size * math.log(2 * math.pi)
+    if not obj.model_sigma:
+        const += np.sum(0.5 * np.log(v))
+    assert abs((L + const) - nll) <= 1e-11 * abs(nll)
+
+
+def test_ccd_variance_matches_generator_noise():
+    # MFV (Sec. 3.2, eq. MFV) at the true parameters is ~1 when the noise model is right.
+    p = sf.config1()
+    obj = oracle.Objective(rho="gauss", var="ccd_model", sigma0=p.sigma0_adu, gain=p.gain)
+    theta = np.concatenate([p.K_true.ravel(), [p.B0_true]])
+    M = oracle.model(p.R, theta, 9)
+    F = np.ones(M.shape)
+    Iv = oracle.valid(p.I.astype(np.float64), 9)
+    v, _ = oracle.oracle._variance(obj, M, F)
+    z = (Iv - M) / np.sqrt(v)
+    assert abs(np.mean(z)) < 4 / math.sqrt(z.size)
+    assert abs(np.var(z) - 1.0) < 4 * math.sqrt(2.0 / z.size)
+
+
+# --------------------------------------------------------------------- gradient and curvature
+@pytest.mark.parametrize("rho", RHOS)
+@pytest.mark.parametrize("var", VARS)
+def test_grad_matches_central_differences_and_brute_design(rho, var):
+    rng = np.random.default_rng(RHOS.index(rho) * 10 + VARS.index(var))
+    m = 3
+    R, I, theta = tiny_problem(7, 12, 11, m)
+    obj = make_obj(rho, var, *R.shape, rng, with_mask=True)
+    L, g = oracle.loss_grad(R, I, theta, m, obj)
+    e = 1e-6
+    fd = np.empty_like(g)
+    for k in range(g.size):
+        tp = theta.copy(); tp[k] += e
+        tm = theta.copy(); tm[k] -= e
+        fd[k] = (oracle.loss_grad(R, I, tp, m, obj)[0] - oracle.loss_grad(R, I, tm, m, obj)[0]) / (2 * e)
+    np.testing.assert_allclose(g, fd, rtol=2e-6, atol=2e-6 * np.abs(g).max())
+    # brute force: grad = X^T l'(M)
+    X = brute_design(R, m)
+    M = oracle.model(R, theta, m)
+    _, gp, _ = oracle.pixel_terms(obj, oracle.valid(I, m), M, m)
+    np.testing.assert_allclose(g, X.T @ gp.ravel(), rtol=1e-12, atol=1e-12 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("rho", RHOS)
+@pytest.mark.parametrize("var", VARS)
+def test_pixel_curvature_matches_difference_of_slope(rho, var):
+    rng = np.random.default_rng(11)
+    m = 3
+    R, I, theta = tiny_problem(9, 12, 11, m)
+    obj = make_obj(rho, var, *R.shape, rng)
+    Iv = oracle.valid(I, m)
+    M = oracle.model(R, theta, m)
+    e = 1e-4
+    l, g, h = oracle.pixel_terms(obj, Iv, M, m)
+    lp, gp, _ = oracle.pixel_terms(obj, Iv, M + e, m)
+    lm, gm, _ = oracle.pixel_terms(obj, Iv, M - e, m)
+    np.testing.assert_allclose(g, (lp - lm) / (2 * e), rtol=1e-6, atol=1e-9)
+    # skip pixels whose +-e interval straddles a kink (Huber |z| = c)
+    smooth = np.abs(((gp - g) - (g - gm)) / e) < 1e-3 * np.maximum(np.abs(h), 1e-6) + 1e-9
+    np.testing.assert_allclose(h[smooth], ((gp - gm) / (2 * e))[smooth], rtol=1e-5, atol=1e-12)
+
+
+def test_constant_reference_couples_kernel_and_background_gradients():
+    # R = c0 everywhere: every dL/dK_ab equals c0 * dL/dB0.
+    m = 5
+    R = np.full((16, 15), 7.25)
+    _, I, theta = tiny_problem(2, 16, 15, m)
+    obj = oracle.Objective(rho="huber", var="ccd_model", sigma0=4.0, gain=1.2)
+    _, g = oracle.loss_grad(R, I, theta, m, obj)
+    np.testing.assert_allclose(g[:-1], 7.25 * g[-1], rtol=1e-12)
+
+
+# --------------------------------------------------------------------- linear solve (B08 step)
+def test_normal_matrix_and_cholesky_match_lstsq():
+    m = 3
+    R, I, _ = tiny_problem(4, 13, 12, m)
+    w = np.random.default_rng(4).uniform(0.1, 2.0, (13 - m + 1, 12 - m + 1))
+    X = brute_design(R, m)
+    A, b = oracle.normal_matrix(R, m, w, oracle.valid(I, m))
+    np.testing.assert_allclose(A, X.T @ (w.ravel()[:, None] * X), rtol=1e-12)
+    theta = oracle.solve_chi2(R, I, m, w)
+    sw = np.sqrt(w.ravel())
+    ref = np.linalg.lstsq(sw[:, None] * X, sw * oracle.valid(I, m).ravel(), rcond=None)[0]
+    np.testing.assert_allclose(theta, ref, rtol=1e-9, atol=1e-11)
+
+
+def _recover(R, I, m, B0):
+    w = np.ones((R.shape[0] - m + 1, R.shape[1] - m + 1))
+    return oracle.solve_chi2(R, I, m, w)
+
+
+@pytest.fixture(scope="module")
+def paper_ref():
+    return sf.paper_reference(142, seed=3, phi_R=1.2).astype(np.float32).astype(np.float64)
+
+
+def _check_recovery(theta, K_true, B0, m):
+    K = theta[:m * m]
+    assert np.linalg.norm(K - K_true.ravel()) <= 1e-9 * np.linalg.norm(K_true)
+    P, Ptrue = K.sum(), K_true.sum()
+    assert abs(P - Ptrue) / Ptrue <= 1e-10
+    assert abs(theta[-1] - B0) / abs(B0) <= 1e-9
+
+
+def test_e2_i_self_difference(paper_ref):
+    m, B0 = 19, 17.5
+    I = paper_ref + B0
+    K = np.zeros((m, m)); K[9, 9] = 1.0
+    _check_recovery(_recover(paper_ref, I, m, B0), K, B0, m)
+
+
+def test_e2_ii_gaussian_kernel(paper_ref):
+    m, B0 = 19, 17.5
+    a = np.arange(m) - 9
+    K = np.exp(-0.5 * (a[:, None] ** 2 + a[None, :] ** 2) / 1.5 ** 2)
+    K /= K.sum()
+    I = np.pad(scipy.signal.correlate2d(paper_ref, K, mode="valid"), 9) + B0
+    _check_recovery(_recover(paper_ref, I, m, B0), K, B0, m)
+
+
+def test_e2_iii_integer_shift(paper_ref):
+    m, B0 = 19, 17.5
+    I = np.zeros_like(paper_ref)
+    I[1:, 1:] = paper_ref[:-1, :-1]
+    I += B0
+    K = np.zeros((m, m)); K[9 - 1, 9 - 1] = 1.0
+    _check_recovery(_recover(paper_ref, I, m, B0), K, B0, m)
+
+
+def test_e2_iv_half_pixel_cubic_spline_shift(paper_ref):
+    m, B0 = 19, 17.5
+    I = scipy.ndimage.shift(paper_ref, (0.5, 0.5), order=3, prefilter=False, mode="nearest") + B0
+    g = GOLD["e2_iv_bspline_weights_x48"]
+    beta = np.array(g["value"], float) / 48.0
+    K = np.zeros((m, m))
+    for ia, oa in enumerate(g["offsets"]):
+        for ib, ob in enumerate(g["offsets"]):
+            K[9 + oa, 9 + ob] = beta[ia] * beta[ib]
+    _check_recovery(_recover(paper_ref, I, m, B0), K, B0, m)
+
+
+def test_injected_scale_recovered_on_noiseless_config1():
+    p = sf.config1(noise=False)
+    obj = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
+    theta = oracle.solve(p.R, p.I_noiseless, 9, obj)
+    assert abs(oracle.photometric_scale(theta, 9) - 1.1) <= 1e-9
+    assert abs(theta[-1] - 5.0) <= 1e-8
+    np.testing.assert_allclose(theta[:81], p.K_true.ravel(), atol=1e-10)
+
+
+def test_reference_offset_invariant():
+    # R -> R - s leaves K unchanged and moves B0 to B0 + s * sum K.
+    p = sf.config1()
+    obj = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
+    R = p.R.astype(np.float64)
+    t1 = oracle.solve(R, p.I, 9, obj)
+    s = 100.0
+    t2 = oracle.solve(R - s, p.I, 9, obj)
+    np.testing.assert_allclose(t2[:81], t1[:81], rtol=1e-8, atol=1e-11)
+    assert abs(t2[81] - (t1[81] + s * t1[:81].sum())) <= 1e-8 * abs(t2[81])
+
+
+# --------------------------------------------------------------------- non-quadratic solver
+@pytest.mark.parametrize("rho", ["huber", "cauchy"])
+def test_robust_fit_recovers_noiseless_truth(rho):
+    p = sf.config1(noise=False)
+    obj = oracle.Objective(rho=rho, var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain,
+                           c=1.345 if rho == "huber" else 2.3849)
+    theta = oracle.solve(p.R, p.I_noiseless, 9, obj,
+                         theta0=oracle.init_theta(p.I_noiseless, 9, "flat"))
+    np.testing.assert_allclose(theta[:81], p.K_true.ravel(), atol=1e-9)
+    assert abs(theta[81] - 5.0) <= 1e-7
+
+
+def test_huber_large_c_equals_chi2_solution():
+    p = sf.config1()
+    base = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
+    hub = oracle.Objective(rho="huber", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain, c=1e6)
+    t0 = oracle.solve(p.R, p.I, 9, base)
+    t1 = oracle.solve(p.R, p.I, 9, hub, theta0=oracle.init_theta(p.I, 9))
+    np.testing.assert_allclose(t1, t0, rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("rho,var", [("gauss", "ccd_model"), ("huber", "ccd_data"), ("cauchy", "ccd_data"),
+                                     ("huber", "emccd_model")])
+def test_robust_solution_is_stationary_with_pd_hessian(rho, var):
+    p = sf.config1()
+    obj = oracle.Objective(rho=rho, var=var, sigma0=p.sigma0_adu, gain=p.gain, excess=2.0,
+                           c=1.345 if rho == "huber" else 2.3849)
+    theta = oracle.solve(p.R, p.I, 9, obj)
+    _, g = oracle.loss_grad(p.R, p.I, theta, 9, obj)
+    # gradient scale: sum_p |l'_p| |X_pj| at the flat start
+    t0 = oracle.init_theta(p.I, 9)
+    _, g0 = oracle.loss_grad(p.R, p.I, t0, 9, obj)
+    assert np.abs(g).max() <= 1e-9 * np.abs(g0).max()
+    H = oracle.hessian(p.R, p.I, theta, 9, obj)
+    assert np.linalg.eigvalsh(H).min() > 0
+
+
+# --------------------------------------------------------------------- clipping loop
+def test_clipping_masks_cosmic_rays_and_recovers_clean_fit():
+    p = sf.config1()
+    obj = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
+    clean, _, _ = oracle.fit_clipped(p.R, p.I, 9, obj, kappa=3.0, max_outer=3)
+    rng = np.random.default_rng(0)
+    I = p.I.astype(np.float64).copy()
+    hits = [(int(rng.integers(10, 118)), int(rng.integers(10, 118))) for _ in range(12)]
+    for (i, j) in hits:
+        I[i, j] += 50.0 * math.sqrt(p.sigma0_adu ** 2 + max(I[i, j], 0) / p.gain)
+    theta, mask, n = oracle.fit_clipped(p.R, I, 9, obj, kappa=3.0, max_outer=3)
+    assert n == 3
+    assert all(mask[i, j] == 0 for (i, j) in hits)
+    K, K0 = theta[:81], clean[:81]
+    assert np.linalg.norm(K - K0) / np.linalg.norm(K0) < 1e-2
+    theta_clean_on_hits, _, _ = oracle.fit_clipped(p.R, p.I, 9, oracle.Objective(
+        rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain, mask=mask), kappa=3.0, max_outer=3)
+    assert np.all(np.isfinite(theta_clean_on_hits))
+
+
+# --------------------------------------------------------------------- optimiser pieces and init
+def test_adam_first_step_is_lr_times_sign():
+    rng = np.random.default_rng(1)
+    g = rng.normal(size=20) * 10 ** rng.uniform(-3, 3, 20)
+    th = rng.normal(size=20)
+    lr = np.full(20, 1e-3)
+    t1, m1, v1 = oracle.adam_step(th, g, np.zeros(20), np.zeros(20), 1, lr, eps=0.0)
+    np.testing.assert_allclose(t1 - th, -lr * np.sign(g), rtol=1e-12)
+    # constant gradient: every bias-corrected step has size lr
+    for t in range(2, 30):
+        t2, m1, v1 = oracle.adam_step(t1, g, m1, v1, t, lr, eps=0.0)
+        np.testing.assert_allclose(t2 - t1, -lr * np.sign(g), rtol=1e-12)
+        t1 = t2
+
+
+def test_init_theta():
+    I = np.arange(1.0, 101.0).reshape(10, 10)
+    t = oracle.init_theta(I, 5, "flat")
+    assert abs(t[:25].sum() - 1.0) < 1e-15 and np.all(t[:25] == t[0])
+    assert t[25] == 50.5
+    t = oracle.init_theta(I, 5, "gauss", 1.3)
+    assert abs(t[:25].sum() - 1.0) < 1e-15 and np.argmax(t[:25]) == 12
+
+
+def test_huber_constant_large_c_limit():
+    # Sec. 2.4: for large c, Q -> (N/2) ln 2 pi
+    n = 15376
+    assert abs(oracle.huber_constant(40.0, n) - 0.5 * n * math.log(2 * math.pi)) < 1e-9 * n
+
+
+def test_generator_gaussian_width_rule():
+    # eq. truetargetPSF: a Gaussian PSF of sd phi_R correlated with a Gaussian kernel of sd phi_K
+    # is a Gaussian of sd sqrt(phi_R^2 + phi_K^2) (second moments add).
+    phi_R, phi_K = 1.3, 1.5
+    R = sf.render_stars((61, 61), np.array([30.0]), np.array([30.0]), np.array([1.0]),
+                        sf.gaussian_psf(phi_R * sf.FWHM_PER_SIGMA), 25)
+    K = sf.kernel_gaussian(21, phi_K * sf.FWHM_PER_SIGMA)
+    T = sf.correlate_target(R, K, 0.0)
+    y, x = np.mgrid[0:61, 0:61]
+    var = np.sum(T * (x - 30.0) ** 2) / np.sum(T)
+    assert abs(var - (phi_R ** 2 + phi_K ** 2)) < 1e-3
+
+
+def _mfv(obj, I, M, m):
+    F = np.ones(M.shape) if obj.flat is None else oracle.valid(obj.flat, m)
+    v, _ = oracle.oracle._variance(obj, M, F)
+    z = (oracle.valid(I, m) - M) / np.sqrt(v)
+    return np.mean(z), np.var(z), z.size
+
+
+def test_ccd_flat_field_variance_by_simulation():
+    # eq. CCDNM: a detector that sees F*S with read noise sigma0 (ADU) and gain G, divided by the flat,
+    # has variance sigma0^2/F^2 + S/(G F).  Simulated here pixel by pixel.
+    rng = np.random.default_rng(21)
+    H = W = 160
+    m = 3
+    S = rng.uniform(50, 3000, (H, W))
+    F = rng.uniform(0.6, 1.4, (H, W))
+    G, s0 = 1.7, 6.0
+    raw = rng.poisson(F * S * G) / G + rng.normal(0, s0, (H, W))
+    I = raw / F
+    theta = np.zeros(m * m + 1); theta[4] = 1.0
+    obj = oracle.Objective(var="ccd_model", sigma0=s0, gain=G, flat=F, var_floor=0.0)
+    mu, var, n = _mfv(obj, I, oracle.model(S, theta, m), m)
+    assert abs(mu) < 4 / math.sqrt(n) and abs(var - 1) < 4 * math.sqrt(2 / n)
+
+
+def test_emccd_variance_by_simulation():
+    # eq. EMCCDNM with E = 2, G_Total = 25.8/300: photo-electrons ~ Poisson, the EM register multiplies
+    # each by an exponential gain (mean 300), 25.8 EM-electrons per ADU, then the flat is divided out.
+    rng = np.random.default_rng(22)
+    H = W = 160
+    m = 3
+    S = rng.uniform(200, 5000, (H, W))
+    F = rng.uniform(0.7, 1.3, (H, W))
+    gt = GOLD["emccd_gain_total"]["value"]
+    n_phot = rng.poisson(F * S * gt)
+    em = rng.gamma(np.maximum(n_phot, 1), 300.0) * (n_phot > 0)
+    I = em / 25.8 / F
+    theta = np.zeros(m * m + 1); theta[4] = 1.0
+    obj = oracle.Objective(var="emccd_model", gain=gt, excess=GOLD["emccd_excess_E"]["value"], flat=F,
+                           var_floor=0.0)
+    mu, var, n = _mfv(obj, I, oracle.model(S, theta, m), m)
+    assert abs(mu) < 4 / math.sqrt(n) and abs(var - 1) < 0.05
+
+
+def test_mask_equals_zero_weight():
+    rng = np.random.default_rng(8)
+    m = 3
+    R, I, theta = tiny_problem(8, 12, 11, m)
+    w = rng.uniform(0.01, 0.2, R.shape)
+    mask = (rng.uniform(size=R.shape) > 0.3).astype(np.uint8)
+    for rho in RHOS:
+        a = oracle.loss_grad(R, I, theta, m, oracle.Objective(rho=rho, var="weights", weights=w, mask=mask))
+        b = oracle.loss_grad(R, I, theta, m, oracle.Objective(rho=rho, var="weights", weights=w * mask))
+        assert abs(a[0] - b[0]) <= 1e-12 * abs(a[0])
+        np.testing.assert_allclose(a[1], b[1], rtol=1e-12, atol=1e-12 * np.abs(a[1]).max())
