@@ -1,0 +1,183 @@
+/*
+ * dia.h — C ABI of the MI355X (gfx950) DIA kernel-fit library, libdia.so.
+ *
+ * The library fits the model image of Hitchcock et al. (PyTorchDIA),
+ * Section 2.1, eq. (model_image_delta_basis):
+ *
+ *     M_ij = sum_{a,b} K_ab R_{(i+a)(j+b)} + B0,      a, b = 0 .. m-1,
+ *
+ * to a target image I on the same pixel grid, by minimising a scalar
+ * objective (Section 2.3 eq. loss, Section 2.4 eq. huber_nll, or a Cauchy
+ * drop-in) with Adam followed by L-BFGS (Section 2.3, Section 2.6, the
+ * algorithm of Section 2.7).  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Images are row-major float32: element (r, c) is data[r * ld + c], ld >= cols.
+ * - R and I have the same rows and cols.  Only "valid" target pixels enter
+ *   the fit (Section 2.1: pixels closer than half a kernel to an edge are
+ *   excluded): valid output (i, j), 0 <= i <= rows-m, 0 <= j <= cols-m, is
+ *   target pixel (i + h, j + h) with h = (m - 1) / 2.
+ * - theta is m*m + 1 floats: K row-major (K[a*m + b], a = row offset,
+ *   b = column offset, the kernel centre at a = b = h), then B0.
+ * - m is odd, 1 <= m <= DIA_MAX_M.
+ * - Array arguments are DEVICE pointers owned by the caller, except where a
+ *   comment says "host".  Option and result structs are host memory.
+ * - stream is a hipStream_t (NULL = the default stream).
+ * - The library allocates no device memory: callers pass a workspace of at
+ *   least dia_workspace_size() bytes, 256-byte aligned.  Its contents need no
+ *   initialisation and are scratch after the call.  Two calls that overlap in
+ *   time must not share a workspace.
+ * - Return value: 0 success, > 0 warning, < 0 error.  Arguments are checked
+ *   before anything is enqueued, so an argument error has no side effects.
+ *   No C++ exception crosses this interface.
+ * - Reductions run in a fixed order (no float atomics): identical calls give
+ *   bitwise-identical results.
+ */
+#ifndef DIA_H
+#define DIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIA_MAX_M 49
+
+/* status codes */
+#define DIA_OK 0
+#define DIA_W_NOT_CONVERGED 1   /* iteration cap hit; theta holds the last accepted iterate      */
+#define DIA_E_ARG (-1)          /* NULL pointer, unknown enum, option out of range                */
+#define DIA_E_SIZE (-2)         /* m even, < 1 or > DIA_MAX_M; image smaller than m; ld < cols    */
+#define DIA_E_WORKSPACE (-3)    /* workspace NULL, misaligned or smaller than dia_workspace_size  */
+#define DIA_E_HIP (-4)          /* a HIP runtime call failed                                      */
+#define DIA_E_NONFINITE (-5)    /* the loss or gradient became NaN or infinite                    */
+
+/* An image in device memory. */
+typedef struct {
+    const float* data;
+    int32_t rows, cols;
+    int64_t ld; /* elements between row starts, >= cols */
+} dia_image;
+
+/* Loss shape rho(z), z = (I - M) / sigma:
+ *   GAUSS  : z^2 / 2                            (eq. chi_squared, eq. loss)
+ *   HUBER  : z^2/2 if |z| <= c else c(|z| - c/2) (eq. huber_loss, eq. huber_nll)
+ *   CAUCHY : (c^2/2) ln(1 + z^2/c^2)             (a wide-tailed drop-in, Section 2.4) */
+enum { DIA_RHO_GAUSS = 0, DIA_RHO_HUBER = 1, DIA_RHO_CAUCHY = 2 };
+
+/* Source of the pixel variance sigma^2 (F = flat field, 1 if none):
+ *   WEIGHTS     : sigma^2 = 1 / weights                                    fixed
+ *   CCD_DATA    : max(sigma0^2/F^2 + max(I,0)/(G F), var_floor)            fixed  (eq. CCDNM on I)
+ *   CCD_MODEL   : max(sigma0^2/F^2 + max(M,0)/(G F), var_floor)            (eq. CCDNM)
+ *   EMCCD_DATA  : max(E max(I,0)/(G F), var_floor)                         fixed  (eq. EMCCDNM on I)
+ *   EMCCD_MODEL : max(E max(M,0)/(G F), var_floor)                         (eq. EMCCDNM)
+ * When sigma depends on the model, each pixel adds ln sigma (eq. loss,
+ * eq. huber_nll); for fixed sigma that term is a constant and is left out. */
+enum { DIA_VAR_WEIGHTS = 0, DIA_VAR_CCD_DATA = 1, DIA_VAR_CCD_MODEL = 2,
+       DIA_VAR_EMCCD_DATA = 3, DIA_VAR_EMCCD_MODEL = 4 };
+
+typedef struct {
+    int32_t rho;       /* DIA_RHO_*                                             */
+    int32_t var;       /* DIA_VAR_*                                             */
+    double sigma0;     /* read noise, ADU (CCD)                                 */
+    double gain;       /* G, e-/ADU (CCD) or G_Total (EMCCD), > 0               */
+    double excess;     /* E, the EMCCD excess noise factor                       */
+    double var_floor;  /* lower bound on sigma^2, ADU^2, >= 0                    */
+    double c;          /* Huber or Cauchy scale, > 0                             */
+    /* Optional arrays laid out like the target (same rows, cols and ld).       */
+    const float* weights;  /* 1/sigma^2; required for DIA_VAR_WEIGHTS, else NULL */
+    const float* flat;     /* master flat F; NULL means F = 1                    */
+    const uint8_t* mask;   /* nonzero = pixel used; NULL means every valid pixel */
+} dia_objective;
+
+/* Operations for dia_workspace_size. */
+enum { DIA_OP_MODEL = 0, DIA_OP_LOSS_GRAD = 1, DIA_OP_FIT = 2, DIA_OP_FIT_CLIPPED = 3 };
+
+/* Workspace bytes that dia_loss_grad (DIA_OP_LOSS_GRAD) or dia_fit
+ * (DIA_OP_FIT; DIA_OP_FIT_CLIPPED when opts->max_outer > 1) need for an image
+ * of rows x cols with leading dimension ld and an m x m kernel.
+ * Returns DIA_E_ARG / DIA_E_SIZE on bad input. */
+int dia_workspace_size(int32_t op, int32_t rows, int32_t cols, int64_t ld, int32_t m, size_t* bytes /*host*/);
+
+/* Model image, eq. (model_image_delta_basis), on the valid region:
+ * M[i * ldM + j], i < rows-m+1, j < cols-m+1, ldM >= cols-m+1.
+ * Asynchronous on stream; needs no workspace. */
+int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM, void* stream);
+
+/* One fused forward + objective + backward pass (the residual is never
+ * written to memory):
+ *   *loss   = L(theta)  summed over valid, unmasked pixels, FP64      (device double[1])
+ *   grad[k] = dL/dK_k = sum_p g_p R_(p + k),  grad[m*m] = dL/dB0 = sum_p g_p,
+ *             g_p = d l_p / d M_p                                      (device float[m*m+1])
+ * Asynchronous on stream. */
+int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m,
+                  double* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel initialisation (Section 2.6): FLAT = 1/m^2 everywhere; GAUSS = a
+ * symmetric Gaussian of standard deviation init_phi, normalised to sum 1;
+ * USER = theta as passed in.  FLAT and GAUSS set B0 = median of I. */
+enum { DIA_INIT_FLAT = 0, DIA_INIT_GAUSS = 1, DIA_INIT_USER = 2 };
+
+typedef struct {
+    int32_t init;          /* DIA_INIT_*                                                   */
+    double init_phi;       /* Gaussian init standard deviation, pixels                     */
+    double lr_K, lr_B0;    /* Adam learning rates (paper: 1e-3 and 1, 10 or 100)           */
+    double beta1, beta2, eps;  /* Adam moments (Kingma & Ba defaults)                      */
+    double tol_switch;     /* hand over to L-BFGS when |dL|/|L| < tol_switch (paper 1e-6)   */
+    double tol_change;     /* stop when |dL|/|L| < tol_change over an accepted L-BFGS step  */
+    double tol_grad;       /* stop when max|grad| <= tol_grad * max|grad at start|          */
+    int32_t history;       /* L-BFGS memory, 1..32                                         */
+    int32_t max_adam;      /* Adam steps before the switch is forced                       */
+    int32_t max_lbfgs;     /* accepted L-BFGS steps before DIA_W_NOT_CONVERGED             */
+    int32_t max_eval;      /* total objective evaluations before DIA_W_NOT_CONVERGED       */
+    int32_t max_outer;     /* fits in the reweight/clip loop (1 = a single fit)            */
+    double clip_kappa;     /* clip |z| > clip_kappa between fits; 0 = no clipping          */
+    int32_t poll_every;    /* graph replays between host checks of the done flag          */
+} dia_fit_opts;
+
+/* Fill opts with the paper's settings (Section 2.6): flat init, lr_K 1e-3,
+ * lr_B0 10, tol_switch 1e-6, L-BFGS lr 1 with history 10, tol_change 1e-10,
+ * tol_grad 1e-9, one outer fit. */
+void dia_fit_opts_default(dia_fit_opts* opts /*host*/);
+
+typedef struct {
+    double loss;      /* final L(theta), FP64 reduction                 */
+    double P;         /* photometric scale factor sum K, FP64 (eq. photometric_scale_factor) */
+    double B0;
+    int32_t n_eval;   /* objective evaluations, all outer fits          */
+    int32_t n_adam;   /* Adam steps                                     */
+    int32_t n_lbfgs;  /* accepted L-BFGS steps                          */
+    int32_t n_outer;  /* fits run by the reweight/clip loop             */
+    int64_t n_masked; /* valid pixels excluded by mask and clipping     */
+    int32_t stop;     /* why the last fit stopped: 1 rel. change, 2 gradient, 3 line search at
+                         precision limit, 4 iteration cap                                          */
+    int32_t status;   /* same as the return value                       */
+} dia_fit_result;
+
+/* Full fit from the chosen initialisation to the stopping rule; theta
+ * (device float[m*m+1]) is the start when opts->init == DIA_INIT_USER and
+ * receives the fit.  With opts->max_outer > 1 the B08-style loop of
+ * Sections 2.1 and 2.4 runs: the first fit uses obj as given (its var must
+ * be CCD_* or EMCCD_*), later fits use sigma^2 = v(M_prev) held fixed and,
+ * if clip_kappa > 0, drop pixels with |I - M_prev| / sigma > clip_kappa
+ * (masks accumulate); the loop ends early when the mask stops changing.
+ * Optimiser state lives in the workspace; each optimiser step is a captured
+ * hipGraph replay with no host synchronisation.  Returns after the work on
+ * stream has completed.  res (host) may be NULL. */
+int dia_fit(dia_image R, dia_image I, const dia_objective* obj, int32_t m, const dia_fit_opts* opts,
+            float* theta, dia_fit_result* res, void* ws, size_t ws_bytes, void* stream);
+
+/* Name of a status code (static string). */
+const char* dia_status_string(int status);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int dia_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIA_H */

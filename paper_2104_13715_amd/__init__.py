@@ -1,0 +1,288 @@
+"""MI355X DIA kernel fit: Python binding of libdia.so (argument marshalling only).
+
+Every numerical step runs in the library's HIP kernels; torch supplies device
+memory and the current stream.  The names follow the C ABI in include/dia.h:
+
+* ``model(R, theta, m)``                       eq. model_image_delta_basis on the valid region
+* ``loss_grad(R, I, theta, m, objective)``     fused forward + objective + backward
+* ``fit(R, I, m, objective, **opts)``           Adam then L-BFGS on the device
+* ``DIALoss.apply(theta, R, I, m, objective)``  autograd wrapper around ``loss_grad``
+
+If libdia.so has not been built this module raises ImportError: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdia.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libdia.so not found at {LIB_PATH}; build it with `python -m paper_2104_13715_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------------------------- constants (dia.h)
+MAX_M = 49
+OK, W_NOT_CONVERGED = 0, 1
+E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_NONFINITE = -1, -2, -3, -4, -5
+RHO = {"gauss": 0, "huber": 1, "cauchy": 2}
+VAR = {"weights": 0, "ccd_data": 1, "ccd_model": 2, "emccd_data": 3, "emccd_model": 4}
+OP_MODEL, OP_LOSS_GRAD, OP_FIT, OP_FIT_CLIPPED = 0, 1, 2, 3
+INIT = {"flat": 0, "gauss": 1, "user": 2}
+STOP = {0: "none", 1: "rel_change", 2: "gradient", 3: "line_search", 4: "cap"}
+
+
+class _Image(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("ld", ctypes.c_int64)]
+
+
+class _Objective(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_int32), ("var", ctypes.c_int32), ("sigma0", ctypes.c_double),
+                ("gain", ctypes.c_double), ("excess", ctypes.c_double), ("var_floor", ctypes.c_double),
+                ("c", ctypes.c_double), ("weights", ctypes.c_void_p), ("flat", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p)]
+
+
+class _FitOpts(ctypes.Structure):
+    _fields_ = [("init", ctypes.c_int32), ("init_phi", ctypes.c_double), ("lr_K", ctypes.c_double),
+                ("lr_B0", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double), ("tol_switch", ctypes.c_double), ("tol_change", ctypes.c_double),
+                ("tol_grad", ctypes.c_double), ("history", ctypes.c_int32), ("max_adam", ctypes.c_int32),
+                ("max_lbfgs", ctypes.c_int32), ("max_eval", ctypes.c_int32), ("max_outer", ctypes.c_int32),
+                ("clip_kappa", ctypes.c_double), ("poll_every", ctypes.c_int32)]
+
+
+class _FitResult(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double), ("P", ctypes.c_double), ("B0", ctypes.c_double),
+                ("n_eval", ctypes.c_int32), ("n_adam", ctypes.c_int32), ("n_lbfgs", ctypes.c_int32),
+                ("n_outer", ctypes.c_int32), ("n_masked", ctypes.c_int64), ("stop", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_lib.dia_version.restype = ctypes.c_int
+_lib.dia_status_string.argtypes = [ctypes.c_int]
+_lib.dia_status_string.restype = ctypes.c_char_p
+_lib.dia_workspace_size.argtypes = [_i32, _i32, _i32, _i64, _i32, ctypes.POINTER(_sz)]
+_lib.dia_model.argtypes = [_Image, _vp, _i32, _vp, _i64, _vp]
+_lib.dia_loss_grad.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.dia_fit_opts_default.argtypes = [ctypes.POINTER(_FitOpts)]
+_lib.dia_fit_opts_default.restype = None
+_lib.dia_fit.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _i32, ctypes.POINTER(_FitOpts), _vp,
+                         ctypes.POINTER(_FitResult), _vp, _sz, _vp]
+for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_fit"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad",
+           "dia_fit_opts_default", "dia_fit")
+
+
+class DIAError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+        self.status = status
+
+
+def version() -> int:
+    return _lib.dia_version()
+
+
+def status_string(status: int) -> str:
+    return _lib.dia_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise DIAError(status, where)
+    return status
+
+
+# ----------------------------------------------------------------------------- marshalling helpers
+def _image(t: torch.Tensor, name: str) -> _Image:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.dim() != 2 or not t.is_cuda:
+        raise TypeError(f"{name} must be a 2-D float32 CUDA tensor")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+    return _Image(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0))
+
+
+def _like_target(t: Optional[torch.Tensor], I: torch.Tensor, dtype, name: str):
+    if t is None:
+        return None
+    if t.dtype != dtype or t.shape != I.shape or t.stride() != I.stride() or t.device != I.device:
+        raise ValueError(f"{name} must be a {dtype} tensor laid out like the target (same shape and strides)")
+    return t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+@dataclass
+class Objective:
+    """rho in {'gauss', 'huber', 'cauchy'}; var in {'weights', 'ccd_data', 'ccd_model', 'emccd_data',
+    'emccd_model'} (see include/dia.h).  weights / flat / mask are tensors laid out like the target."""
+    rho: str = "gauss"
+    var: str = "ccd_data"
+    sigma0: float = 0.0
+    gain: float = 1.0
+    excess: float = 2.0
+    var_floor: float = 1.0
+    c: float = 1.345
+    weights: Optional[torch.Tensor] = None
+    flat: Optional[torch.Tensor] = None
+    mask: Optional[torch.Tensor] = None
+
+    def _c(self, I: torch.Tensor) -> _Objective:
+        return _Objective(RHO[self.rho], VAR[self.var], float(self.sigma0), float(self.gain), float(self.excess),
+                          float(self.var_floor), float(self.c),
+                          _like_target(self.weights, I, torch.float32, "weights"),
+                          _like_target(self.flat, I, torch.float32, "flat"),
+                          _like_target(self.mask, I, torch.uint8, "mask"))
+
+
+def workspace_size(op: int, rows: int, cols: int, ld: int, m: int) -> int:
+    n = _sz(0)
+    _check(_lib.dia_workspace_size(op, rows, cols, ld, m, ctypes.byref(n)), "dia_workspace_size")
+    return int(n.value)
+
+
+class Workspace:
+    """A 256-byte aligned device buffer (torch-owned) reused across calls of one size or less."""
+
+    def __init__(self, device):
+        self.device = torch.device(device)
+        self.buf = None
+        self.nbytes = 0
+
+    def get(self, nbytes: int):
+        if nbytes == 0:
+            return None, 0
+        if self.buf is None or self.nbytes < nbytes:
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self.nbytes = nbytes
+        p = self.buf.data_ptr()
+        return p + (-p) % 256, nbytes
+
+
+def _theta(theta: torch.Tensor, m: int, device) -> torch.Tensor:
+    if theta.dtype != torch.float32 or theta.numel() != m * m + 1 or not theta.is_contiguous():
+        raise ValueError("theta must be a contiguous float32 tensor of m*m + 1 values")
+    if theta.device != device:
+        raise ValueError("theta must live on the images' device")
+    return theta
+
+
+# ----------------------------------------------------------------------------- entry points
+def model(R: torch.Tensor, theta: torch.Tensor, m: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Valid model image (rows-m+1, cols-m+1), eq. model_image_delta_basis."""
+    Ri = _image(R, "R")
+    theta = _theta(theta, m, R.device)
+    if out is None:
+        out = torch.empty((max(R.shape[0] - m + 1, 1), max(R.shape[1] - m + 1, 1)), dtype=torch.float32,
+                          device=R.device)
+    _check(_lib.dia_model(Ri, theta.data_ptr(), m, out.data_ptr(), out.stride(0), _stream(R.device)), "dia_model")
+    return out
+
+
+def loss_grad(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
+              workspace: Optional[Workspace] = None, loss: Optional[torch.Tensor] = None,
+              grad: Optional[torch.Tensor] = None):
+    """(loss float64[1], grad float32[m*m+1]) of the objective at theta, one fused pass."""
+    Ri, Ii = _image(R, "R"), _image(I, "I")
+    theta = _theta(theta, m, R.device)
+    obj = objective._c(I)
+    ws = workspace or Workspace(R.device)
+    nbytes = workspace_size(OP_LOSS_GRAD, I.shape[0], I.shape[1], I.stride(0), m)
+    p, nb = ws.get(nbytes)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=R.device)
+    if grad is None:
+        grad = torch.empty(m * m + 1, dtype=torch.float32, device=R.device)
+    _check(_lib.dia_loss_grad(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(), grad.data_ptr(),
+                              p, nb, _stream(R.device)), "dia_loss_grad")
+    return loss, grad
+
+
+@dataclass
+class FitResult:
+    theta: torch.Tensor
+    loss: float
+    P: float
+    B0: float
+    n_eval: int
+    n_adam: int
+    n_lbfgs: int
+    n_outer: int
+    n_masked: int
+    stop: str
+    status: int
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def K(self) -> torch.Tensor:
+        m = int(round((self.theta.numel() - 1) ** 0.5))
+        return self.theta[:m * m].view(m, m)
+
+
+def fit_options(**kw) -> _FitOpts:
+    o = _FitOpts()
+    _lib.dia_fit_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "init":
+            v = INIT[v] if isinstance(v, str) else int(v)
+        if not hasattr(o, k):
+            raise TypeError(f"unknown fit option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def fit(R: torch.Tensor, I: torch.Tensor, m: int, objective: Objective, theta: Optional[torch.Tensor] = None,
+        workspace: Optional[Workspace] = None, **opts) -> FitResult:
+    """Fit K and B0 (Adam then L-BFGS on the device); returns after the fit has finished."""
+    Ri, Ii = _image(R, "R"), _image(I, "I")
+    if theta is not None:
+        opts.setdefault("init", "user")
+        theta = _theta(theta, m, R.device)
+    else:
+        theta = torch.empty(m * m + 1, dtype=torch.float32, device=R.device)
+    o = fit_options(**opts)
+    obj = objective._c(I)
+    ws = workspace or Workspace(R.device)
+    op = OP_FIT_CLIPPED if o.max_outer > 1 else OP_FIT
+    p, nb = ws.get(workspace_size(op, I.shape[0], I.shape[1], I.stride(0), m))
+    res = _FitResult()
+    st = _lib.dia_fit(Ri, Ii, ctypes.byref(obj), m, ctypes.byref(o), theta.data_ptr(), ctypes.byref(res), p, nb,
+                      _stream(R.device))
+    _check(st, "dia_fit")
+    return FitResult(theta=theta, loss=res.loss, P=res.P, B0=res.B0, n_eval=res.n_eval, n_adam=res.n_adam,
+                     n_lbfgs=res.n_lbfgs, n_outer=res.n_outer, n_masked=int(res.n_masked),
+                     stop=STOP.get(res.stop, str(res.stop)), status=st)
+
+
+class DIALoss(torch.autograd.Function):
+    """L(theta) as a 0-d float64 tensor whose backward is the fused hand-written gradient.
+
+    forward runs one ``dia_loss_grad`` pass and keeps the gradient; backward scales it by the
+    incoming gradient, so no second pass over the images is needed."""
+
+    @staticmethod
+    def forward(ctx, theta, R, I, m, objective, workspace=None):
+        t = theta.detach().to(torch.float32).contiguous()
+        loss, grad = loss_grad(R, I, t, m, objective, workspace)
+        ctx.save_for_backward(grad)
+        ctx.theta_dtype = theta.dtype
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, gout):
+        (grad,) = ctx.saved_tensors
+        g = (grad.to(torch.float64) * gout.to(torch.float64)).to(ctx.theta_dtype)
+        return g, None, None, None, None, None

@@ -1,0 +1,582 @@
+// Cross-workgroup reduction, the on-device optimiser (Adam then L-BFGS,
+// Sections 2.3 and 2.6), median initialisation and fit finalisation.
+//
+// The reduce kernel adds the per-workgroup partial rows of the tiled kernel in
+// FP64 in a fixed order (64 columns per workgroup).  In fit mode the last
+// workgroup to finish (device-scope counter) runs one optimiser step with the
+// full gradient, so one optimiser iteration is exactly two launches and the
+// host never reads anything back between iterations.
+#include "fit_state.h"
+
+namespace dia {
+
+// ---------------------------------------------------------------------------- block helpers
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Sum over the 256 threads of the workgroup, same value returned to all threads.
+__device__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kReduceThreads / 64; ++w) s += sh[w];
+    return s;
+}
+
+__device__ double block_max(double v, double* sh) {
+    v = wave_max(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = sh[0];
+    for (int w = 1; w < kReduceThreads / 64; ++w) s = fmax(s, sh[w]);
+    return s;
+}
+
+__device__ double dot(const double* a, const double* b, int n, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) s += a[i] * b[i];
+    return block_sum(s, sh);
+}
+
+__device__ double max_abs(const double* a, int n, double* sh) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) s = fmax(s, fabs(a[i]));
+    return block_max(s, sh);
+}
+
+// ---------------------------------------------------------------------------- L-BFGS pieces
+// Store the curvature pair (s, y) when s.y > 0 (Nocedal & Wright, Chapter 7.2).
+__device__ void push_pair(FitState* st, const FitVecs& v, const double* s, const double* y, int n, int H,
+                          double* sh) {
+    const double sy = dot(s, y, n, sh);
+    const double ss = dot(s, s, n, sh);
+    const double yy = dot(y, y, n, sh);
+    if (!(sy > 1e-12 * sqrt(ss * yy)) || !(sy > 0.0)) return;
+    const int slot = st->hist_head;
+    double* Sd = v.S + (long long)slot * v.ld;
+    double* Yd = v.Y + (long long)slot * v.ld;
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+        Sd[i] = s[i];
+        Yd[i] = y[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        v.rh[slot] = 1.0 / sy;
+        st->hist_head = (slot + 1) % H;
+        st->hist_n = st->hist_n < H ? st->hist_n + 1 : H;
+    }
+    __syncthreads();
+}
+
+// d = -H_k g by the two-loop recursion, H_0 = gamma I with gamma = s.y / y.y of the newest pair.
+__device__ void lbfgs_direction(FitState* st, const FitVecs& v, const double* g, int n, int H, double* sh) {
+    double* d = v.d;
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) d[i] = g[i];
+    __syncthreads();
+    const int cnt = st->hist_n, head = st->hist_head;
+    for (int k = 0; k < cnt; ++k) {
+        const int idx = (head - 1 - k + H) % H;
+        const double a = v.rh[idx] * dot(v.S + (long long)idx * v.ld, d, n, sh);
+        if (threadIdx.x == 0) v.al[idx] = a;
+        const double* Yk = v.Y + (long long)idx * v.ld;
+        for (int i = threadIdx.x; i < n; i += kReduceThreads) d[i] -= a * Yk[i];
+        __syncthreads();
+    }
+    double gamma;
+    if (cnt > 0) {
+        const int nw = (head - 1 + H) % H;
+        const double* Yn = v.Y + (long long)nw * v.ld;
+        gamma = 1.0 / (v.rh[nw] * dot(Yn, Yn, n, sh));
+    } else {
+        double l1 = 0.0;
+        for (int i = threadIdx.x; i < n; i += kReduceThreads) l1 += fabs(g[i]);
+        l1 = block_sum(l1, sh);
+        gamma = l1 > 0.0 ? fmin(1.0, 1.0 / l1) : 1.0;
+    }
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) d[i] *= gamma;
+    __syncthreads();
+    for (int k = cnt - 1; k >= 0; --k) {
+        const int idx = (head - 1 - k + H) % H;
+        const double b = v.rh[idx] * dot(v.Y + (long long)idx * v.ld, d, n, sh);
+        const double* Sk = v.S + (long long)idx * v.ld;
+        const double coef = v.al[idx] - b;
+        for (int i = threadIdx.x; i < n; i += kReduceThreads) d[i] += coef * Sk[i];
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) d[i] = -d[i];
+    __syncthreads();
+}
+
+__device__ void set_trial(FitState* st, const FitVecs& v, int n) {
+    // xt = x + alpha d; theta_eval = float(xt)
+    const double al = st->alpha;
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+        const double xv = v.x[i] + al * v.d[i];
+        v.xt[i] = xv;
+        v.theta_eval[i] = (float)xv;
+    }
+    __syncthreads();
+}
+
+__device__ void finish(FitState* st, int stop, int status) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->stop = stop;
+        st->status = status;
+        st->phase = PH_DONE;
+        st->done = 1;
+    }
+    __syncthreads();
+}
+
+// Start the L-BFGS phase (or a new search direction) from the accepted point x with gradient g.
+__device__ void new_direction(FitState* st, const FitVecs& v, const FitOptsDev& o, int n, double* sh) {
+    const int H = o.history;
+    lbfgs_direction(st, v, v.g, n, H, sh);
+    double gtd = dot(v.g, v.d, n, sh);
+    if (!(gtd < 0.0)) {  // not a descent direction: drop the history, use the scaled gradient
+        if (threadIdx.x == 0) {
+            st->hist_n = 0;
+            st->hist_head = 0;
+        }
+        __syncthreads();
+        lbfgs_direction(st, v, v.g, n, H, sh);
+        gtd = dot(v.g, v.d, n, sh);
+    }
+    if (threadIdx.x == 0) {
+        st->gtd = gtd;
+        st->alpha = 1.0;
+        st->ls_iter = 0;
+        st->phase = PH_LSEARCH;
+    }
+    __syncthreads();
+    set_trial(st, v, n);
+}
+
+__device__ void adam_update(FitState* st, const FitVecs& v, const FitOptsDev& o, int n) {
+    const int t = st->adam_t + 1;
+    const double bc1 = 1.0 - pow(o.beta1, (double)t);
+    const double bc2 = 1.0 - pow(o.beta2, (double)t);
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+        const double gi = v.g[i];
+        const double m1 = o.beta1 * v.m1[i] + (1.0 - o.beta1) * gi;
+        const double v1 = o.beta2 * v.v1[i] + (1.0 - o.beta2) * gi * gi;
+        v.m1[i] = m1;
+        v.v1[i] = v1;
+        v.xp[i] = v.x[i];
+        v.gp[i] = gi;
+        const double lr = (i == n - 1) ? o.lr_B0 : o.lr_K;
+        const double xn = v.x[i] - lr * (m1 / bc1) / (sqrt(v1 / bc2) + o.eps);
+        v.x[i] = xn;
+        v.theta_eval[i] = (float)xn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->adam_t = t;
+        st->n_adam += 1;
+    }
+    __syncthreads();
+}
+
+// One optimiser step, run by a single workgroup once the full gradient gt (and loss gt[n]) is known.
+__device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
+    FitState* st = ra.st;
+    const FitVecs& v = ra.v;
+    const FitOptsDev& o = ra.o;
+    const int n = ra.n;
+    const double* gt = ra.gt;
+    const double Lt = gt[n];
+
+    // non-finite loss or gradient ends the fit
+    int bad = 0;
+    for (int i = threadIdx.x; i <= n; i += kReduceThreads) bad |= !isfinite(gt[i]);
+    if (block_max((double)bad, sh) > 0.0) {
+        finish(st, STOP_NONE, DIA_E_NONFINITE);
+        return;
+    }
+    if (threadIdx.x == 0) st->n_eval += 1;
+    __syncthreads();
+    const int phase = st->phase;
+
+    if (phase == PH_INIT || phase == PH_ADAM) {
+        const double Lprev = st->L;
+        if (phase == PH_INIT) {
+            const double gm = max_abs(gt, n, sh);
+            if (threadIdx.x == 0) st->gmax0 = gm;
+        } else {
+            // curvature pair from the last Adam step: s = x - xp, y = gt - gp (xd, d as scratch)
+            for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+                v.xt[i] = v.x[i] - v.xp[i];
+                v.d[i] = gt[i] - v.gp[i];
+            }
+            __syncthreads();
+            push_pair(st, v, v.xt, v.d, n, o.history, sh);
+        }
+        for (int i = threadIdx.x; i < n; i += kReduceThreads) v.g[i] = gt[i];
+        __syncthreads();
+        if (threadIdx.x == 0) st->L = Lt;
+        __syncthreads();
+        const double rel = fabs(Lprev - Lt) / fmax(fabs(Lprev), 1e-300);
+        const bool switch_now = (phase == PH_ADAM && (rel < o.tol_switch || st->n_adam >= o.max_adam)) ||
+                                (phase == PH_INIT && o.skip_adam);
+        if (!switch_now) {
+            adam_update(st, v, o, n);
+        } else {
+            const double gm = max_abs(v.g, n, sh);
+            if (gm <= o.tol_grad * st->gmax0) {
+                finish(st, STOP_GRAD, DIA_OK);
+                return;
+            }
+            new_direction(st, v, o, n, sh);
+        }
+    } else if (phase == PH_LSEARCH) {
+        const double L0 = st->L;
+        const double alpha = st->alpha;
+        if (Lt <= L0 + 1e-4 * alpha * st->gtd) {
+            // accept: s = xt - x, y = gt - g
+            for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+                v.d[i] = v.xt[i] - v.x[i];
+                v.m1[i] = gt[i] - v.g[i];  // m1 is free in this phase
+            }
+            __syncthreads();
+            push_pair(st, v, v.d, v.m1, n, o.history, sh);
+            for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+                v.x[i] = v.xt[i];
+                v.g[i] = gt[i];
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                st->L = Lt;
+                st->n_lbfgs += 1;
+            }
+            __syncthreads();
+            const double rel = (L0 - Lt) / fmax(fabs(L0), 1e-300);
+            const double gm = max_abs(v.g, n, sh);
+            if (gm <= o.tol_grad * st->gmax0) {
+                finish(st, STOP_GRAD, DIA_OK);
+                return;
+            }
+            if (rel < o.tol_change) {
+                finish(st, STOP_CHANGE, DIA_OK);
+                return;
+            }
+            if (st->n_lbfgs >= o.max_lbfgs) {
+                finish(st, STOP_CAP, DIA_W_NOT_CONVERGED);
+                return;
+            }
+            new_direction(st, v, o, n, sh);
+        } else {
+            // backtrack: minimiser of the quadratic through L0, slope gtd and Lt, kept in [0.1, 0.5] alpha
+            const int it = st->ls_iter + 1;
+            if (it >= 40) {
+                finish(st, STOP_LINESEARCH, DIA_OK);
+                return;
+            }
+            const double gtd = st->gtd;
+            double an = -gtd * alpha * alpha / (2.0 * (Lt - L0 - gtd * alpha));
+            if (!(an >= 0.1 * alpha)) an = 0.1 * alpha;
+            if (an > 0.5 * alpha) an = 0.5 * alpha;
+            if (threadIdx.x == 0) {
+                st->alpha = an;
+                st->ls_iter = it;
+            }
+            __syncthreads();
+            set_trial(st, v, n);
+        }
+    }
+    if (st->phase != PH_DONE && st->n_eval >= o.max_eval) finish(st, STOP_CAP, DIA_W_NOT_CONVERGED);
+}
+
+// ---------------------------------------------------------------------------- reduce kernel
+__global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
+    __shared__ double red[4][kReduceCols];
+    __shared__ double sh[16];
+    __shared__ int last;
+    if (ra.done != nullptr && *ra.done != 0) return;
+    const int tid = threadIdx.x;
+    const int col = blockIdx.x * kReduceCols + (tid & (kReduceCols - 1));
+    const int ph = tid / kReduceCols;
+    double s = 0.0;
+    if (col < ra.npp)
+        for (int b = ph; b < ra.nblk; b += 4) s += ra.partial[(long long)b * ra.npp + col];
+    red[ph][tid & (kReduceCols - 1)] = s;
+    __syncthreads();
+    if (ph == 0 && col < ra.npp) {
+        const double tot = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+        ra.gt[col] = tot;
+        if (ra.out_grad != nullptr && col < ra.n) ra.out_grad[col] = (float)tot;
+        if (ra.out_loss != nullptr && col == ra.n) ra.out_loss[0] = tot;
+    }
+    if (ra.st == nullptr) return;
+
+    // last workgroup runs the optimiser step
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const int prev = atomicAdd(&ra.st->counter, 1);
+        last = (prev == (int)gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    optimiser_step(ra, sh);
+    if (tid == 0) ra.st->counter = 0;
+}
+
+hipError_t launch_reduce(const ReduceArgs& ra, hipStream_t s) {
+    const int grid = (ra.npp + kReduceCols - 1) / kReduceCols;
+    hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(kReduceThreads), 0, s, ra);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- median (radix select)
+__device__ __forceinline__ unsigned f2key(float f) {
+    const unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key2f(unsigned k) {
+    const unsigned u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+__global__ __launch_bounds__(256) void select_init_kernel(SelectState* sel, long long npix) {
+    const int t = threadIdx.x;
+    if (t < 2) {
+        sel->prefix[t] = 0u;
+        sel->mask[t] = 0u;
+        sel->k[t] = (t == 0) ? (npix - 1) / 2 : npix / 2;
+    }
+    sel->hist[0][t] = 0u;
+    sel->hist[1][t] = 0u;
+}
+
+__global__ __launch_bounds__(256) void select_hist_kernel(const float* img, int rows, int cols, long long ld,
+                                                          SelectState* sel, int shift) {
+    __shared__ unsigned h[2][256];
+    h[0][threadIdx.x] = 0u;
+    h[1][threadIdx.x] = 0u;
+    __syncthreads();
+    const unsigned p0 = sel->prefix[0], m0 = sel->mask[0], p1 = sel->prefix[1], m1 = sel->mask[1];
+    const long long npix = (long long)rows * cols;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < npix;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long r = idx / cols, c = idx - r * cols;
+        const unsigned key = f2key(img[r * ld + c]);
+        const unsigned bin = (key >> shift) & 255u;
+        if ((key & m0) == p0) atomicAdd(&h[0][bin], 1u);
+        if ((key & m1) == p1) atomicAdd(&h[1][bin], 1u);
+    }
+    __syncthreads();
+    if (h[0][threadIdx.x]) atomicAdd(&sel->hist[0][threadIdx.x], h[0][threadIdx.x]);
+    if (h[1][threadIdx.x]) atomicAdd(&sel->hist[1][threadIdx.x], h[1][threadIdx.x]);
+}
+
+__global__ void select_pick_kernel(SelectState* sel, int shift) {
+    const int w = threadIdx.x;  // 2 threads: one per rank
+    if (w < 2) {
+        long long cum = 0;
+        const long long k = sel->k[w];
+        int bin = 255;
+        for (int b = 0; b < 256; ++b) {
+            const long long c = sel->hist[w][b];
+            if (cum + c > k) {
+                bin = b;
+                break;
+            }
+            cum += c;
+        }
+        sel->prefix[w] |= (unsigned)bin << shift;
+        sel->mask[w] |= 255u << shift;
+        sel->k[w] = k - cum;
+        for (int b = 0; b < 256; ++b) sel->hist[w][b] = 0u;
+    }
+}
+
+hipError_t launch_median(const float* img, int rows, int cols, long long ld, SelectState* sel, hipStream_t s) {
+    const long long npix = (long long)rows * cols;
+    hipLaunchKernelGGL(select_init_kernel, dim3(1), dim3(256), 0, s, sel, npix);
+    long long blocks = (npix + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(select_hist_kernel, dim3((int)blocks), dim3(256), 0, s, img, rows, cols, ld, sel, shift);
+        hipLaunchKernelGGL(select_pick_kernel, dim3(1), dim3(64), 0, s, sel, shift);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- fit init / finalize
+__global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st, FitVecs v, int m, int init_kind,
+                                                                  double phi, const float* theta_user,
+                                                                  const SelectState* sel) {
+    __shared__ double sh[16];
+    const int n = m * m + 1;
+    const int h = (m - 1) / 2;
+    double ksum = 1.0;
+    if (init_kind == DIA_INIT_GAUSS) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < m * m; i += kReduceThreads) {
+            const double da = (double)(i / m - h), db = (double)(i % m - h);
+            s += exp(-0.5 * (da * da + db * db) / (phi * phi));
+        }
+        ksum = block_sum(s, sh);
+    }
+    double B0 = 0.0;
+    if (init_kind != DIA_INIT_USER) {
+        const double lo = (double)key2f(sel->prefix[0]);
+        const double hi = (double)key2f(sel->prefix[1]);
+        B0 = 0.5 * (lo + hi);
+    }
+    for (int i = threadIdx.x; i < v.ld; i += kReduceThreads) {
+        double x = 0.0;
+        if (i < n) {
+            if (init_kind == DIA_INIT_USER) {
+                x = (double)theta_user[i];
+            } else if (i == n - 1) {
+                x = B0;
+            } else if (init_kind == DIA_INIT_FLAT) {
+                x = 1.0 / (double)(m * m);
+            } else {
+                const double da = (double)(i / m - h), db = (double)(i % m - h);
+                x = exp(-0.5 * (da * da + db * db) / (phi * phi)) / ksum;
+            }
+        }
+        v.x[i] = x;
+        v.xt[i] = x;
+        v.g[i] = 0.0;
+        v.d[i] = 0.0;
+        v.m1[i] = 0.0;
+        v.v1[i] = 0.0;
+        v.xp[i] = x;
+        v.gp[i] = 0.0;
+        v.theta_eval[i] = (float)x;
+    }
+    if (threadIdx.x == 0) {
+        FitState z = {};
+        z.phase = PH_INIT;
+        z.alpha = 1.0;
+        *st = z;
+    }
+}
+
+hipError_t launch_init_fit(FitState* st, FitVecs v, int m, int init_kind, double phi, const float* theta_user,
+                           const SelectState* sel, hipStream_t s) {
+    hipLaunchKernelGGL(init_fit_kernel, dim3(1), dim3(kReduceThreads), 0, s, st, v, m, init_kind, phi, theta_user,
+                       sel);
+    return hipGetLastError();
+}
+
+// Restart the optimiser from the current x (a warm start for the next outer fit); the L-BFGS
+// curvature pairs are kept, the objective having changed only through the weights and mask.
+__global__ __launch_bounds__(kReduceThreads) void restart_fit_kernel(FitState* st, FitVecs v, int n) {
+    const int hist_n = st->hist_n, hist_head = st->hist_head;
+    __syncthreads();
+    for (int i = threadIdx.x; i < v.ld; i += kReduceThreads) {
+        const double x = v.x[i];
+        v.xt[i] = x;
+        v.g[i] = 0.0;
+        v.d[i] = 0.0;
+        v.m1[i] = 0.0;
+        v.v1[i] = 0.0;
+        v.xp[i] = x;
+        v.gp[i] = 0.0;
+        v.theta_eval[i] = (float)x;
+    }
+    if (threadIdx.x == 0) {
+        FitState z = {};
+        z.phase = PH_INIT;
+        z.alpha = 1.0;
+        z.hist_n = hist_n;
+        z.hist_head = hist_head;
+        *st = z;
+    }
+}
+
+hipError_t launch_restart_fit(FitState* st, FitVecs v, int n, hipStream_t s) {
+    hipLaunchKernelGGL(restart_fit_kernel, dim3(1), dim3(kReduceThreads), 0, s, st, v, n);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kReduceThreads) void finalize_kernel(FitState* st, FitVecs v, int m, float* theta_out) {
+    __shared__ double sh[16];
+    const int n = m * m + 1;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+        const float f = (float)v.x[i];
+        theta_out[i] = f;
+        if (i < m * m) s += (double)f;
+    }
+    const double P = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        st->out_P = P;
+        st->out_B0 = (double)(float)v.x[n - 1];
+        st->out_loss = st->L;
+    }
+}
+
+hipError_t launch_finalize(FitState* st, FitVecs v, int m, float* theta_out, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kReduceThreads), 0, s, st, v, m, theta_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- mask helpers
+__global__ void fill_mask_kernel(uint8_t* dst, const uint8_t* src, int rows, int cols, long long ld) {
+    const long long npix = (long long)rows * cols;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < npix;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long r = idx / cols, c = idx - r * cols;
+        dst[r * ld + c] = src ? (uint8_t)(src[r * ld + c] != 0) : (uint8_t)1;
+    }
+}
+
+hipError_t launch_fill_mask(uint8_t* dst, const uint8_t* src, int rows, int cols, long long ld, hipStream_t s) {
+    long long blocks = ((long long)rows * cols + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_mask_kernel, dim3((int)blocks), dim3(256), 0, s, dst, src, rows, cols, ld);
+    return hipGetLastError();
+}
+
+__global__ void count_masked_kernel(const uint8_t* mask, int rows, int cols, long long ld, int m, int* count) {
+    const int h = (m - 1) / 2;
+    const int Hv = rows - m + 1, Wv = cols - m + 1;
+    const long long npix = (long long)Hv * Wv;
+    int c = 0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < npix;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long r = idx / Wv, cc = idx - r * Wv;
+        c += (mask[(r + h) * ld + cc + h] == 0);
+    }
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+hipError_t launch_count_masked(const uint8_t* mask, int rows, int cols, long long ld, int m, int* count,
+                               hipStream_t s) {
+    long long blocks = ((long long)rows * cols + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(count_masked_kernel, dim3((int)blocks), dim3(256), 0, s, mask, rows, cols, ld, m, count);
+    return hipGetLastError();
+}
+
+__global__ void zero_ints_kernel(int* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace dia

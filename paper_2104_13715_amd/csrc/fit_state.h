@@ -1,0 +1,74 @@
+// Device-side optimiser state of one fit and the kernels that drive it.
+#pragma once
+
+#include "dia_common.h"
+
+namespace dia {
+
+constexpr int kMaxHistory = 32;
+constexpr int kReduceThreads = 256;
+constexpr int kReduceCols = 64;  // partial columns per reduce workgroup
+
+enum FitPhase { PH_INIT = 0, PH_ADAM = 1, PH_LSEARCH = 2, PH_DONE = 3 };
+enum StopReason { STOP_NONE = 0, STOP_CHANGE = 1, STOP_GRAD = 2, STOP_LINESEARCH = 3, STOP_CAP = 4 };
+
+struct FitOptsDev {
+    double lr_K, lr_B0, beta1, beta2, eps;
+    double tol_switch, tol_change, tol_grad;
+    int history, max_adam, max_lbfgs, max_eval;
+    int skip_adam;  // warm restart: go straight to L-BFGS with the kept curvature pairs
+};
+
+// Lives in the workspace; read back by the host after a fit.
+struct FitState {
+    int phase, done, status, stop;
+    int n_eval, n_adam, n_lbfgs, ls_iter;
+    int hist_n, hist_head, counter, adam_t;
+    double L;        // loss at the current point (Adam) or the accepted point (L-BFGS)
+    double alpha;    // line-search step
+    double gtd;      // g . d at the accepted point
+    double gmax0;    // max |grad| at the first evaluation
+    double out_loss, out_P, out_B0;
+    double pad[5];
+};
+
+// Pointers into the workspace for one fit (n = m*m + 1 parameters).
+struct FitVecs {
+    double *x, *g, *d, *xt, *m1, *v1, *xp, *gp;
+    double *S, *Y, *rh, *al;  // L-BFGS history: S[kMaxHistory][ld], Y[kMaxHistory][ld]
+    float* theta_eval;        // float copy of the point being evaluated (read by the tile kernel)
+    int ld;                   // padded vector length
+};
+
+// Radix-select state for the two middle ranks of the median.
+struct SelectState {
+    unsigned prefix[2], mask[2];
+    long long k[2];
+    unsigned hist[2][256];
+};
+
+struct ReduceArgs {
+    const double* partial;  // [nblk][npp]
+    int nblk, npp;          // npp = n + 1 (gradient, then loss)
+    double* gt;             // reduced gradient and loss (FP64)
+    double* out_loss;       // loss-grad mode: device double[1]
+    float* out_grad;        // loss-grad mode: device float[n]
+    FitState* st;           // fit mode when non-null
+    FitVecs v;
+    FitOptsDev o;
+    int n, m;
+    const int* done;
+};
+
+hipError_t launch_reduce(const ReduceArgs& ra, hipStream_t s);
+hipError_t launch_median(const float* img, int rows, int cols, long long ld, SelectState* sel, hipStream_t s);
+hipError_t launch_init_fit(FitState* st, FitVecs v, int m, int init_kind, double phi, const float* theta_user,
+                           const SelectState* sel, hipStream_t s);
+hipError_t launch_restart_fit(FitState* st, FitVecs v, int n, hipStream_t s);
+hipError_t launch_finalize(FitState* st, FitVecs v, int m, float* theta_out, hipStream_t s);
+hipError_t launch_fill_mask(uint8_t* dst, const uint8_t* src, int rows, int cols, long long ld, hipStream_t s);
+hipError_t launch_count_masked(const uint8_t* mask, int rows, int cols, long long ld, int m, int* count,
+                               hipStream_t s);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
+
+}  // namespace dia

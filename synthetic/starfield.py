@@ -46,9 +46,10 @@ def rng_for(config: int, epoch: int = 0) -> np.random.Generator:
 def gaussian_psf(fwhm: float):
     s = fwhm / FWHM_PER_SIGMA
     norm = 1.0 / (2.0 * math.pi * s * s)
+    k = -0.5 / (s * s)
 
     def f(r2):
-        return norm * np.exp(-0.5 * r2 / (s * s))
+        return norm * np.exp(k * r2)
 
     return f
 
@@ -59,30 +60,36 @@ def moffat_psf(fwhm: float, beta: float = 3.0):
     inv_a2 = 1.0 / (alpha * alpha)
 
     def f(r2):
-        return norm * (1.0 + r2 * inv_a2) ** (-beta)
+        t = 1.0 / (1.0 + r2 * inv_a2)
+        if beta == 3.0:
+            return norm * (t * t * t)
+        return norm * t ** beta
 
     return f
 
 
-def render_stars(shape, x, y, flux, psf, radius: int, sky: float = 0.0, chunk: int = 4096):
-    """Sum of flux * psf(|p - star|^2) sampled at pixel centres (x = column, y = row)."""
+def render_stars(shape, x, y, flux, psf, radius: int, sky: float = 0.0, chunk: int = 2048):
+    """Sum of flux * psf(|p - star|^2) sampled at pixel centres (x = column, y = row), stamps of the
+    given radius, plus a constant sky.  Rendered on a canvas padded by the radius, then cropped."""
     H, W = shape
-    out = np.zeros(H * W, dtype=np.float64)
-    off = np.arange(-radius, radius + 1)
-    dy, dx = np.meshgrid(off, off, indexing="ij")
-    dy = dy.ravel()
-    dx = dx.ravel()
+    Hp, Wp = H + 2 * radius + 1, W + 2 * radius + 1
+    out = np.zeros(Hp * Wp, dtype=np.float64)
+    off = np.arange(-radius, radius + 1, dtype=np.float64)
+    flat_off = (off[:, None] * Wp + off[None, :]).astype(np.int64).ravel()
     for s in range(0, len(x), chunk):
         xs, ys, fs = x[s:s + chunk], y[s:s + chunk], flux[s:s + chunk]
-        cx = np.rint(xs).astype(np.int64)
-        cy = np.rint(ys).astype(np.int64)
-        px = cx[:, None] + dx[None, :]
-        py = cy[:, None] + dy[None, :]
-        r2 = (px - xs[:, None]) ** 2 + (py - ys[:, None]) ** 2
-        val = fs[:, None] * psf(r2)
-        ok = (px >= 0) & (px < W) & (py >= 0) & (py < H)
-        out += np.bincount((py * W + px)[ok], weights=val[ok], minlength=H * W)
-    return out.reshape(H, W) + sky
+        cx = np.rint(xs)
+        cy = np.rint(ys)
+        fx = cx - xs
+        fy = cy - ys
+        ddx = off[None, :] + fx[:, None]                       # (n, 2r+1) column offsets from the star
+        ddy = off[None, :] + fy[:, None]
+        r2 = ddy[:, :, None] ** 2 + ddx[:, None, :] ** 2          # (n, 2r+1, 2r+1)
+        val = fs[:, None] * psf(r2.reshape(len(xs), -1))
+        base = (cy.astype(np.int64) + radius) * Wp + (cx.astype(np.int64) + radius)
+        out += np.bincount((base[:, None] + flat_off[None, :]).ravel(), weights=val.ravel(), minlength=Hp * Wp)
+    img = out.reshape(Hp, Wp)[radius:radius + H, radius:radius + W]
+    return img + sky
 
 
 def kernel_gaussian(m: int, fwhm_x: float, fwhm_y: float | None = None, rot_deg: float = 0.0,

@@ -1,0 +1,279 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (spec bar, FP32 arithmetic on the GPU):
+  gradient  ||d dK|| / ||dK_ref|| <= 1e-5 and |d dB0| / |dB0_ref| <= 1e-5
+  loss      relative 1e-6 (FP32 per-pixel terms, FP64 sum)
+  fit       ||dK|| / ||K_ref|| <= 1e-4, |dP| / P_ref <= 1e-4, |dB0| / max(|B0_ref|, 1) <= 1e-4
+  model     |dM| <= 2e-6 * (sum|K| * max|R| + |B0|)  (m^2-term FP32 sums)
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synthetic import starfield as sf
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+DEV = torch.device("cuda:0")
+
+RHOS = ["gauss", "huber", "cauchy"]
+VARS = ["weights", "ccd_data", "ccd_model", "emccd_data", "emccd_model"]
+
+
+@pytest.fixture(scope="module")
+def dia():
+    import paper_2104_13715_amd as d
+    return d
+
+
+def gpu(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def to_objs(dia, rho, var, sigma0, gain, c=None, weights=None, flat=None, mask=None, excess=2.0, var_floor=1.0):
+    c = c if c is not None else (1.345 if rho == "huber" else 2.3849)
+    o_or = oracle.Objective(rho=rho, var=var, sigma0=sigma0, gain=gain, excess=excess, var_floor=var_floor, c=c,
+                            weights=None if weights is None else weights.astype(np.float64),
+                            flat=None if flat is None else flat.astype(np.float64), mask=mask)
+    o_gpu = dia.Objective(rho=rho, var=var, sigma0=sigma0, gain=gain, excess=excess, var_floor=var_floor, c=c,
+                          weights=None if weights is None else gpu(weights),
+                          flat=None if flat is None else gpu(flat),
+                          mask=None if mask is None else gpu(mask, torch.uint8))
+    return o_or, o_gpu
+
+
+def check_grad(g, g_ref, m, tol=1e-5):
+    dK, dK_ref = g[:m * m], g_ref[:m * m]
+    eK = np.linalg.norm(dK - dK_ref) / np.linalg.norm(dK_ref)
+    eB = abs(g[m * m] - g_ref[m * m]) / abs(g_ref[m * m])
+    assert eK <= tol and eB <= tol, f"grad rel err dK {eK:.3e} dB0 {eB:.3e}"
+    return eK, eB
+
+
+def run_loss_grad(dia, R, I, theta, m, o_gpu):
+    loss, grad = dia.loss_grad(gpu(R), gpu(I), gpu(theta.astype(np.float32)), m, o_gpu)
+    torch.cuda.synchronize()
+    return loss.item(), grad.cpu().double().numpy()
+
+
+def random_problem(seed, H, W, m):
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(50.0, 3000.0, (H, W)).astype(np.float32)
+    K = rng.uniform(0.0, 1.0, (m, m))
+    K /= K.sum()
+    theta = np.concatenate([K.ravel(), [rng.uniform(-20, 20)]]).astype(np.float32)
+    M = oracle.model(R, theta, m)
+    I = R.copy()
+    I[(m - 1) // 2:H - (m - 1) // 2, (m - 1) // 2:W - (m - 1) // 2] = M + rng.normal(0, 10.0, M.shape)
+    # start away from the optimum so the gradient has no cancellation
+    theta0 = theta.astype(np.float64) * rng.uniform(0.7, 1.3, theta.size)
+    return R, I.astype(np.float32), theta0.astype(np.float32), rng
+
+
+# ------------------------------------------------------------------------------ model
+@pytest.mark.parametrize("m,H,W", [(1, 37, 41), (3, 64, 70), (9, 130, 301), (19, 300, 250), (25, 160, 211),
+                                   (49, 120, 260)])
+def test_model_parity(dia, m, H, W):
+    R, _, theta, _ = random_problem(m, H, W, m)
+    M = dia.model(gpu(R), gpu(theta), m).cpu().double().numpy()
+    ref = oracle.model(R, theta, m)
+    scale = np.abs(theta[:m * m]).sum() * np.abs(R).max() + abs(theta[-1])
+    assert M.shape == ref.shape
+    assert np.abs(M - ref).max() <= 2e-6 * scale
+
+
+def test_model_sampled_at_full_ccd_size(dia):
+    rng = np.random.default_rng(5)
+    H = W = 4096
+    m = 19
+    R = (rng.gamma(2.0, 300.0, (H, W))).astype(np.float32)
+    theta = np.concatenate([sf.kernel_gaussian(m, 2.2, 1.8, 30.0, total=0.9).ravel(), [-12.0]]).astype(np.float32)
+    M = dia.model(gpu(R), gpu(theta), m).cpu().double().numpy()
+    idx = [(0, 0), (H - m, W - m), (0, W - m), (H - m, 0)] + [tuple(rng.integers(0, H - m + 1, 2)) for _ in range(200)]
+    scale = np.abs(theta[:m * m]).sum() * np.abs(R).max() + 12.0
+    for (i, j) in idx:
+        ref = oracle.model(R[i:i + m, j:j + m], theta, m)[0, 0]
+        assert abs(M[i, j] - ref) <= 2e-6 * scale
+
+
+# ------------------------------------------------------------------------------ loss and gradient
+@pytest.mark.parametrize("rho", RHOS)
+@pytest.mark.parametrize("var", VARS)
+def test_loss_grad_every_objective(dia, rho, var):
+    m = 5
+    R, I, theta, rng = random_problem(11, 150, 131, m)
+    H, W = I.shape
+    weights = rng.uniform(0.001, 0.02, (H, W)).astype(np.float32) if var == "weights" else None
+    flat = rng.uniform(0.8, 1.2, (H, W)).astype(np.float32)
+    mask = (rng.uniform(size=(H, W)) > 0.1).astype(np.uint8)
+    o_or, o_gpu = to_objs(dia, rho, var, sigma0=6.0, gain=1.5, weights=weights, flat=flat, mask=mask)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    assert abs(L - L_ref) <= 1e-6 * abs(L_ref) + 1e-9 * I.size
+    check_grad(g, g_ref, m)
+
+
+@pytest.mark.parametrize("m,H,W", [(1, 64, 70), (3, 90, 101), (9, 130, 301), (19, 300, 250), (25, 170, 151),
+                                   (33, 140, 160), (49, 150, 170)])
+def test_loss_grad_kernel_sizes_and_ragged_tiles(dia, m, H, W):
+    R, I, theta, _ = random_problem(100 + m, H, W, m)
+    o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", sigma0=8.0, gain=1.5)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    assert abs(L - L_ref) <= 1e-6 * abs(L_ref)
+    check_grad(g, g_ref, m)
+
+
+def test_loss_grad_valid_region_of_one_pixel(dia):
+    m = 9
+    R, I, theta, _ = random_problem(3, 9, 9, m)
+    o_or, o_gpu = to_objs(dia, "huber", "ccd_model", sigma0=5.0, gain=1.0)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    assert abs(L - L_ref) <= 1e-6 * abs(L_ref)
+    np.testing.assert_allclose(g, g_ref, rtol=1e-5, atol=1e-6 * np.abs(g_ref).max())
+
+
+def test_loss_grad_fully_masked_is_zero(dia):
+    m = 5
+    R, I, theta, _ = random_problem(4, 60, 60, m)
+    mask = np.zeros(I.shape, np.uint8)
+    _, o_gpu = to_objs(dia, "gauss", "ccd_data", sigma0=5.0, gain=1.0, mask=mask)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    assert L == 0.0 and np.all(g == 0.0)
+
+
+def test_loss_grad_strided_views(dia):
+    m = 9
+    R, I, theta, _ = random_problem(6, 200, 220, m)
+    Rbig = torch.zeros((200, 256), dtype=torch.float32, device=DEV)
+    Ibig = torch.zeros((200, 240), dtype=torch.float32, device=DEV)
+    Rbig[:, :220] = gpu(R)
+    Ibig[:, :220] = gpu(I)
+    o_or, o_gpu = to_objs(dia, "cauchy", "ccd_data", sigma0=5.0, gain=1.0)
+    loss, grad = dia.loss_grad(Rbig[:, :220], Ibig[:, :220], gpu(theta), m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    assert abs(loss.item() - L_ref) <= 1e-6 * abs(L_ref)
+    check_grad(grad.cpu().double().numpy(), g_ref, m)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return sf.config1()
+
+
+@pytest.fixture(scope="module")
+def c3crop():
+    # the central 256^2 crop of the CCD-sized field (same star density and PSF, generated at 1024^2)
+    return sf.crop(sf.config3(size=1024), 256)
+
+
+@pytest.mark.parametrize("where", ["init", "true_perturbed"])
+def test_loss_grad_config1(dia, c1, where):
+    p = c1
+    m = p.m
+    if where == "init":
+        theta = oracle.init_theta(p.I, m, "flat")
+    else:
+        rng = np.random.default_rng(1)
+        theta = np.concatenate([p.K_true.ravel(), [p.B0_true]]) * rng.uniform(0.95, 1.05, m * m + 1)
+    theta = theta.astype(np.float32)
+    o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", p.sigma0_adu, p.gain)
+    L, g = run_loss_grad(dia, p.R, p.I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(p.R, p.I, theta, m, o_or)
+    assert abs(L - L_ref) <= 1e-6 * abs(L_ref)
+    check_grad(g, g_ref, m)
+
+
+@pytest.mark.parametrize("rho,var", [("gauss", "ccd_data"), ("cauchy", "ccd_data"), ("gauss", "ccd_model")])
+def test_loss_grad_ccd_crop(dia, c3crop, rho, var):
+    p = c3crop
+    m = p.m
+    rng = np.random.default_rng(2)
+    theta = (np.concatenate([p.K_true.ravel(), [p.B0_true]]) * rng.uniform(0.9, 1.1, m * m + 1)).astype(np.float32)
+    o_or, o_gpu = to_objs(dia, rho, var, p.sigma0_adu, p.gain)
+    L, g = run_loss_grad(dia, p.R, p.I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(p.R, p.I, theta, m, o_or)
+    assert abs(L - L_ref) <= 1e-6 * abs(L_ref)
+    check_grad(g, g_ref, m)
+
+
+def test_loss_grad_bitwise_repeatable(dia, c1):
+    p = c1
+    theta = oracle.init_theta(p.I, p.m).astype(np.float32)
+    _, o_gpu = to_objs(dia, "huber", "ccd_model", p.sigma0_adu, p.gain)
+    a = run_loss_grad(dia, p.R, p.I, theta, p.m, o_gpu)
+    b = run_loss_grad(dia, p.R, p.I, theta, p.m, o_gpu)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+# ------------------------------------------------------------------------------ fits
+def check_fit(res, th_ref, m, tol=1e-4):
+    th = res.theta.cpu().double().numpy()
+    K, Kr = th[:m * m], th_ref[:m * m]
+    eK = np.linalg.norm(K - Kr) / np.linalg.norm(Kr)
+    eP = abs(K.sum() - Kr.sum()) / abs(Kr.sum())
+    eB = abs(th[-1] - th_ref[-1]) / max(abs(th_ref[-1]), 1.0)
+    msg = f"K {eK:.2e} P {eP:.2e} B0 {eB:.2e} evals {res.n_eval} (adam {res.n_adam}, lbfgs {res.n_lbfgs}) stop {res.stop}"
+    print(msg)
+    assert res.status >= 0
+    assert eK <= tol and eP <= tol and eB <= tol, msg
+    return eK, eP, eB
+
+
+@pytest.mark.parametrize("init", ["flat", "gauss"])
+def test_fit_config1_chi2(dia, c1, init):
+    p = c1
+    o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", p.sigma0_adu, p.gain)
+    res = dia.fit(gpu(p.R), gpu(p.I), p.m, o_gpu, init=init, init_phi=1.0)
+    ref = oracle.solve(p.R, p.I, p.m, o_or)
+    check_fit(res, ref, p.m)
+    assert abs(res.P - ref[:p.m ** 2].sum()) <= 1e-4 * abs(ref[:p.m ** 2].sum())
+
+
+@pytest.mark.parametrize("rho,var", [("gauss", "ccd_model"), ("huber", "ccd_data"), ("cauchy", "ccd_data")])
+def test_fit_config1_other_objectives(dia, c1, rho, var):
+    p = c1
+    o_or, o_gpu = to_objs(dia, rho, var, p.sigma0_adu, p.gain)
+    res = dia.fit(gpu(p.R), gpu(p.I), p.m, o_gpu)
+    ref = oracle.solve(p.R, p.I, p.m, o_or)
+    check_fit(res, ref, p.m)
+
+
+def test_fit_noiseless_recovery(dia):
+    # Sec. 3.4 tests (i) and (ii) on the GPU: FP32 recovers K and B0 far inside 1e-4.
+    R = sf.paper_reference(142, seed=3, phi_R=1.2).astype(np.float32)
+    m = 19
+    a = np.arange(m) - 9
+    K = np.exp(-0.5 * (a[:, None] ** 2 + a[None, :] ** 2) / 1.5 ** 2)
+    K /= K.sum()
+    B0 = 17.5
+    I = (sf.correlate_target(R.astype(np.float64), K, B0)).astype(np.float32)
+    o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", 5.0, 1.0)
+    res = dia.fit(gpu(R), gpu(I), m, o_gpu, init="gauss", init_phi=1.0)
+    th = res.theta.cpu().double().numpy()
+    eP = abs(th[:m * m].sum() - 1.0)
+    eB = abs(th[-1] - B0) / B0
+    print(f"noiseless: eps_P {eP:.2e} eps_B0 {eB:.2e} evals {res.n_eval}")
+    assert eP <= 1e-4 and eB <= 1e-4
+
+
+def test_fit_nonfinite_input_reports_error(dia, c1):
+    p = c1
+    I = p.I.copy()
+    I[40, 50] = np.nan
+    _, o_gpu = to_objs(dia, "gauss", "ccd_data", p.sigma0_adu, p.gain)
+    with pytest.raises(dia.DIAError) as e:
+        dia.fit(gpu(p.R), gpu(I), p.m, o_gpu)
+    assert e.value.status == dia.E_NONFINITE
+
+
+def test_fit_iteration_cap_warns(dia, c1):
+    p = c1
+    _, o_gpu = to_objs(dia, "gauss", "ccd_data", p.sigma0_adu, p.gain)
+    res = dia.fit(gpu(p.R), gpu(p.I), p.m, o_gpu, max_eval=3, poll_every=1)
+    assert res.status == dia.W_NOT_CONVERGED and res.n_eval == 3
