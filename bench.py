@@ -1,0 +1,187 @@
+#!/usr/bin/env python
+"""Benchmark of the DIA kernel fit on one MI355X.
+
+Workload (default): the CCD-sized pair — 4096 x 4096, 80,000 stars, Moffat PSF
+(beta 3, FWHM 3.5 px), fluxes log-uniform 1e2..1e6, sky 500; target = reference
+correlated with a 19 x 19 elliptical Gaussian (FWHM 2.2 x 1.8 px, 30 deg,
+sum 0.9) plus B0 = -12, read noise 8 e-, gain 1.5.  Objective: chi-squared with
+CCD variance from the data.  Inputs are synthetic and seeded; they are
+resident in HBM before timing starts.
+
+A step is one complete fit (flat kernel, B0 = median, Adam then L-BFGS to the
+stopping rule): every optimiser iteration is one fused forward + objective +
+backward pass plus the FP64 reduction and the optimiser update.
+
+Printed (one JSON line): fwd+bwd Gtap/s sustained through the timed fits
+(value), fits/s, evaluations per fit, the fused kernel's roofline fraction
+(its duration measured with HIP events around a burst of back-to-back
+loss/gradient launches on the launch stream), and the FP64 CPU oracle timed on
+a bounded sample of the same pair.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DIA kernel fits/s & fwd+bwd Gtap/s at 4096², m=19; % of roofline vs plain"
+PEAK_FP32_VECTOR_TFLOPS = 157.3  # MI355X published fp32 vector peak (packed FMA)
+
+
+def traffic_from_profile(kernel_sig: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it matches this kernel build."""
+    path = os.path.join(ROOT, "profiles", "traffic_fused_eval_4096_m19.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha") != kernel_sig:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def kernel_source_sig() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dia_common.h", "tile_impl.h"):
+        h.update(open(os.path.join(ROOT, "paper_2104_13715_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--init", default="flat", choices=["flat", "gauss"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=1024, help="valid rows of the oracle's timed sample")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (per-GPU throughput is the "
+              "whole-job value; see DESIGN.md for how the fit would shard)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2104_13715_amd as dia
+    from synthetic import starfield as sf
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pair = sf.config3(size=args.size)
+    m = pair.m
+    print(f"# generated {args.size}^2 pair in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    R = torch.from_numpy(pair.R).to(dev)
+    I = torch.from_numpy(pair.I).to(dev)
+    obj = dia.Objective(rho="gauss", var="ccd_data", sigma0=pair.sigma0_adu, gain=pair.gain)
+    H, W = pair.I.shape
+    P = (H - m + 1) * (W - m + 1)
+    taps_per_eval = 2 * P * m * m  # forward + backward (pixel, tap) products, one FMA each
+    ws = dia.Workspace(dev)
+    torch.cuda.synchronize()
+
+    fit_kw = dict(init=args.init, init_phi=1.0)
+    for _ in range(args.warmup):
+        dia.fit(R, I, m, obj, workspace=ws, **fit_kw)
+        print("# warmup fit done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    # ------------------------------------------------------------------ timed region: K full fits
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_eval = 0
+    results = []
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(args.steps):
+        r = dia.fit(R, I, m, obj, workspace=ws, **fit_kw)
+        n_eval += r.n_eval
+        results.append(r)
+    end.record()
+    torch.cuda.synchronize()
+    t_fit = start.elapsed_time(end) / 1e3
+    print(f"# {args.steps} fits in {t_fit:.3f}s, evals {[r.n_eval for r in results]}", file=sys.stderr, flush=True)
+
+    # ------------------------------------------------------------------ kernel duration: burst of fused passes
+    theta = results[-1].theta.clone()
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    grad = torch.empty(m * m + 1, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        dia.loss_grad(R, I, theta, m, obj, ws, loss, grad)
+    torch.cuda.synchronize()
+    kb, ke = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    kb.record()
+    for _ in range(args.kernel_reps):
+        dia.loss_grad(R, I, theta, m, obj, ws, loss, grad)
+    ke.record()
+    torch.cuda.synchronize()
+    t_launch = kb.elapsed_time(ke) / 1e3 / args.kernel_reps
+    flop_per_launch = 2.0 * taps_per_eval
+    achieved_tflops = flop_per_launch / t_launch / 1e12
+    traffic = traffic_from_profile(kernel_source_sig())
+
+    # ------------------------------------------------------------------ CPU oracle on a bounded sample
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rows = min(args.cpu_rows, H - m + 1) + m - 1
+        oobj = oracle.Objective(rho="gauss", var="ccd_data", sigma0=pair.sigma0_adu, gain=pair.gain)
+        th = theta.cpu().numpy()
+        Rs, Is = pair.R[:rows], pair.I[:rows]
+        oracle.loss_grad(Rs[:m + 8], Is[:m + 8], th, m, oobj)  # load the library first
+        ps = (rows - m + 1) * (W - m + 1)
+        reps, tc = 0, 0.0
+        while tc < 10.0 and reps < 50:
+            t1 = time.time()
+            oracle.loss_grad(Rs, Is, th, m, oobj)
+            tc += time.time() - t1
+            reps += 1
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cpu = {"value": round(reps * 2 * ps * m * m / tc / 1e9, 4), "unit": "Gtap/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{reps} FP64 loss+gradient evaluations (direct loops) of the top {rows - m + 1} valid rows "
+                         f"x {W - m + 1} columns of the same pair, m={m}"}
+
+    gtaps = n_eval * taps_per_eval / t_fit / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(gtaps, 2),
+        "unit": "Gtap/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t_fit / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded star field, resident in HBM)",
+        "config": {"workload": f"single pair {H}x{W}, m={m}, chi2 with CCD data variance, {args.init} init, "
+                               f"Adam->L-BFGS to the stopping rule", "H": H, "W": W, "m": m,
+                   "valid_pixels": P, "objective": "gauss/ccd_data"},
+        "fits_per_s": round(args.steps / t_fit, 3),
+        "evals_per_fit": round(n_eval / args.steps, 1),
+        "eval_us_in_fit": round(1e6 * t_fit / n_eval, 2),
+        "fused_pass_us": round(1e6 * t_launch, 2),
+        "kernel_gtaps": round(taps_per_eval / t_launch / 1e9, 1),
+        "fit_stop": results[-1].stop,
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

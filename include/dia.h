@@ -94,7 +94,7 @@ typedef struct {
 } dia_objective;
 
 /* Operations for dia_workspace_size. */
-enum { DIA_OP_MODEL = 0, DIA_OP_LOSS_GRAD = 1, DIA_OP_FIT = 2, DIA_OP_FIT_CLIPPED = 3 };
+enum { DIA_OP_MODEL = 0, DIA_OP_LOSS_GRAD = 1, DIA_OP_FIT = 2, DIA_OP_FIT_CLIPPED = 3, DIA_OP_HESSIAN = 4 };
 
 /* Workspace bytes that dia_loss_grad (DIA_OP_LOSS_GRAD) or dia_fit
  * (DIA_OP_FIT; DIA_OP_FIT_CLIPPED when opts->max_outer > 1) need for an image
@@ -116,6 +116,19 @@ int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM,
 int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m,
                   double* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
 
+/* Observed Fisher information (Section 2.5): the Hessian of L at theta,
+ *   H[i * n + j] = d2L / dtheta_i dtheta_j,   n = m*m + 1,
+ * FP64, row-major, parameters in theta's order (kernel taps row by row, then
+ * B0); device double[n * n].  Since M is affine in theta,
+ *   H = sum_p (d2 l_p / dM_p^2) x_p x_p^T,  x_p = (R_(p + k) for every tap k, 1),
+ * computed exactly (including the derivative of the variance when it
+ * depends on the model).  When L is a negative log-likelihood, H^-1 is the
+ * asymptotic covariance of the fitted parameters and sqrt(H^-1[m*m][m*m])
+ * the standard error of B0.  Workspace: DIA_OP_HESSIAN.  Asynchronous on
+ * stream. */
+int dia_hessian(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m, double* H,
+                void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel initialisation (Section 2.6): FLAT = 1/m^2 everywhere; GAUSS = a
  * symmetric Gaussian of standard deviation init_phi, normalised to sum 1;
  * USER = theta as passed in.  FLAT and GAUSS set B0 = median of I. */
@@ -136,11 +149,23 @@ typedef struct {
     int32_t max_outer;     /* fits in the reweight/clip loop (1 = a single fit)            */
     double clip_kappa;     /* clip |z| > clip_kappa between fits; 0 = no clipping          */
     int32_t poll_every;    /* graph replays between host checks of the done flag          */
+    int32_t max_newton;    /* exact-Hessian Newton steps after each fit (0 = none)         */
 } dia_fit_opts;
 
 /* Fill opts with the paper's settings (Section 2.6): flat init, lr_K 1e-3,
  * lr_B0 10, tol_switch 1e-6, L-BFGS lr 1 with history 10, tol_change 1e-10,
- * tol_grad 1e-9, one outer fit. */
+ * tol_grad 1e-9, one outer fit; then up to 8 Newton steps.
+ *
+ * The Newton polish is an addition to the paper's optimiser: at m ~ 19 the
+ * normal matrix of the problem has a condition number near 1e10, so the
+ * first-order optimisers stop on the paper's rule well before the kernel's
+ * weak directions have converged.  Each Newton step solves H d = -g with the
+ * FP64 Hessian H = sum_p h_p x_p x_p^T (x_p the pixel's design row, h_p the
+ * per-pixel curvature: exact for a Gaussian objective with fixed variance,
+ * the Gauss-Newton / IRLS weight otherwise) by Cholesky, with a backtracking
+ * line search on the loss; it stops when the Newton decrement -g.d is below
+ * the FP64 resolution of the loss or the step below the FP32 resolution of
+ * theta. */
 void dia_fit_opts_default(dia_fit_opts* opts /*host*/);
 
 typedef struct {
@@ -153,8 +178,10 @@ typedef struct {
     int32_t n_outer;  /* fits run by the reweight/clip loop             */
     int64_t n_masked; /* valid pixels excluded by mask and clipping     */
     int32_t stop;     /* why the last fit stopped: 1 rel. change, 2 gradient, 3 line search at
-                         precision limit, 4 iteration cap                                          */
+                         precision limit, 4 iteration cap, 5 Newton decrement negligible            */
     int32_t status;   /* same as the return value                       */
+    int32_t n_newton; /* accepted Newton steps, all outer fits          */
+    int32_t n_hessian; /* Hessians formed by the Newton polish          */
 } dia_fit_result;
 
 /* Full fit from the chosen initialisation to the stopping rule; theta
@@ -169,6 +196,56 @@ typedef struct {
  * stream has completed.  res (host) may be NULL. */
 int dia_fit(dia_image R, dia_image I, const dia_objective* obj, int32_t m, const dia_fit_opts* opts,
             float* theta, dia_fit_result* res, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched fits: many epochs of uneven size against one shared reference.
+ * Every epoch is its own independent fit (its own theta, loss and optimiser
+ * state, same objective scalars and options); all epochs advance together,
+ * one persistent launch per optimiser iteration, and an epoch that has
+ * converged drops out of the work queue.  The tile shape is chosen per
+ * kernel size and image-size class by a timing autotuner (process-wide
+ * cache; DIA_TILE_VARIANT=k pins variant k, DIA_AUTOTUNE_CACHE=<file> keeps
+ * the choices across processes) — the analogue of the convolution-algorithm
+ * benchmark cache mentioned in the paper's Section 5.3.
+ * ------------------------------------------------------------------------ */
+
+/* One epoch: a target and the position of its pixel (0, 0) in the shared reference. */
+typedef struct {
+    const float* I;            /* target, device                                         */
+    int32_t rows, cols;
+    int64_t ld;
+    int32_t ref_row0, ref_col0; /* target pixel (r, c) sits on reference pixel (r + ref_row0, c + ref_col0) */
+    const float* weights;      /* optional arrays laid out like this target (see dia_objective) */
+    const float* flat;
+    const uint8_t* mask;
+} dia_epoch;
+
+/* Arithmetic of the batched contraction.
+ *   FP32   : FP32 direct correlation on the vector ALUs (the plain form).
+ *   BF16X3 : forward and dL/dK as implicit GEMMs over the epochs on BF16 matrix
+ *            cores, each FP32 operand split x = hi + lo (both bf16) and the
+ *            product taken as hi*hi + hi*lo + lo*hi with FP32 accumulation;
+ *            needs every epoch to have the same size and reference offset. */
+enum { DIA_PREC_FP32 = 0, DIA_PREC_BF16X3 = 1 };
+
+/* Workspace bytes for dia_loss_grad_batched (fit = 0) or dia_fit_batched (fit = 1). */
+int dia_batched_workspace_size(dia_image R, const dia_epoch* epochs /*host[n]*/, int32_t n, int32_t m,
+                               int32_t precision, int32_t fit, size_t* bytes /*host*/);
+
+/* Per-epoch loss and gradient at theta[e] (device float[n][m*m+1]):
+ * loss[e] (device double[n]), grad[e*(m*m+1) + k] (device float[n][m*m+1]).
+ * Asynchronous on stream. */
+int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs /*host[n]*/, int32_t n, int32_t m,
+                          const dia_objective* obj, int32_t precision, const float* theta, double* loss,
+                          float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Fit every epoch (see dia_fit; opts->max_outer must be 1).  theta is device
+ * float[n][m*m+1] (start values when opts->init == DIA_INIT_USER, fits on
+ * return); res is host dia_fit_result[n] or NULL.  Returns the most severe
+ * status over the epochs; res[e].status holds each epoch's own. */
+int dia_fit_batched(dia_image R, const dia_epoch* epochs /*host[n]*/, int32_t n, int32_t m,
+                    const dia_objective* obj, const dia_fit_opts* opts, int32_t precision, float* theta,
+                    dia_fit_result* res, void* ws, size_t ws_bytes, void* stream);
 
 /* Name of a status code (static string). */
 const char* dia_status_string(int status);

@@ -33,9 +33,9 @@ OK, W_NOT_CONVERGED = 0, 1
 E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_NONFINITE = -1, -2, -3, -4, -5
 RHO = {"gauss": 0, "huber": 1, "cauchy": 2}
 VAR = {"weights": 0, "ccd_data": 1, "ccd_model": 2, "emccd_data": 3, "emccd_model": 4}
-OP_MODEL, OP_LOSS_GRAD, OP_FIT, OP_FIT_CLIPPED = 0, 1, 2, 3
+OP_MODEL, OP_LOSS_GRAD, OP_FIT, OP_FIT_CLIPPED, OP_HESSIAN = 0, 1, 2, 3, 4
 INIT = {"flat": 0, "gauss": 1, "user": 2}
-STOP = {0: "none", 1: "rel_change", 2: "gradient", 3: "line_search", 4: "cap"}
+STOP = {0: "none", 1: "rel_change", 2: "gradient", 3: "line_search", 4: "cap", 5: "newton"}
 
 
 class _Image(ctypes.Structure):
@@ -50,20 +50,26 @@ class _Objective(ctypes.Structure):
                 ("mask", ctypes.c_void_p)]
 
 
+class _Epoch(ctypes.Structure):
+    _fields_ = [("I", ctypes.c_void_p), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32), ("ld", ctypes.c_int64),
+                ("ref_row0", ctypes.c_int32), ("ref_col0", ctypes.c_int32), ("weights", ctypes.c_void_p),
+                ("flat", ctypes.c_void_p), ("mask", ctypes.c_void_p)]
+
+
 class _FitOpts(ctypes.Structure):
     _fields_ = [("init", ctypes.c_int32), ("init_phi", ctypes.c_double), ("lr_K", ctypes.c_double),
                 ("lr_B0", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
                 ("eps", ctypes.c_double), ("tol_switch", ctypes.c_double), ("tol_change", ctypes.c_double),
                 ("tol_grad", ctypes.c_double), ("history", ctypes.c_int32), ("max_adam", ctypes.c_int32),
                 ("max_lbfgs", ctypes.c_int32), ("max_eval", ctypes.c_int32), ("max_outer", ctypes.c_int32),
-                ("clip_kappa", ctypes.c_double), ("poll_every", ctypes.c_int32)]
+                ("clip_kappa", ctypes.c_double), ("poll_every", ctypes.c_int32), ("max_newton", ctypes.c_int32)]
 
 
 class _FitResult(ctypes.Structure):
     _fields_ = [("loss", ctypes.c_double), ("P", ctypes.c_double), ("B0", ctypes.c_double),
                 ("n_eval", ctypes.c_int32), ("n_adam", ctypes.c_int32), ("n_lbfgs", ctypes.c_int32),
                 ("n_outer", ctypes.c_int32), ("n_masked", ctypes.c_int64), ("stop", ctypes.c_int32),
-                ("status", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("n_newton", ctypes.c_int32), ("n_hessian", ctypes.c_int32)]
 
 
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -73,15 +79,26 @@ _lib.dia_status_string.restype = ctypes.c_char_p
 _lib.dia_workspace_size.argtypes = [_i32, _i32, _i32, _i64, _i32, ctypes.POINTER(_sz)]
 _lib.dia_model.argtypes = [_Image, _vp, _i32, _vp, _i64, _vp]
 _lib.dia_loss_grad.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.dia_hessian.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.dia_fit_opts_default.argtypes = [ctypes.POINTER(_FitOpts)]
 _lib.dia_fit_opts_default.restype = None
 _lib.dia_fit.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _i32, ctypes.POINTER(_FitOpts), _vp,
                          ctypes.POINTER(_FitResult), _vp, _sz, _vp]
-for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_fit"):
+_lib.dia_batched_workspace_size.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, _i32, _i32,
+                                            ctypes.POINTER(_sz)]
+_lib.dia_loss_grad_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, ctypes.POINTER(_Objective), _i32,
+                                       _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.dia_fit_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, ctypes.POINTER(_Objective),
+                                 ctypes.POINTER(_FitOpts), _i32, _vp, ctypes.POINTER(_FitResult), _vp, _sz, _vp]
+for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_hessian", "dia_fit", "dia_batched_workspace_size",
+           "dia_loss_grad_batched", "dia_fit_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad",
-           "dia_fit_opts_default", "dia_fit")
+PREC = {"fp32": 0, "bf16x3": 1}
+
+EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad", "dia_hessian",
+           "dia_fit_opts_default", "dia_fit", "dia_batched_workspace_size", "dia_loss_grad_batched",
+           "dia_fit_batched")
 
 
 class DIAError(RuntimeError):
@@ -211,6 +228,24 @@ def loss_grad(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, obj
     return loss, grad
 
 
+def hessian(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
+            workspace: Optional[Workspace] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Observed Fisher information: the exact FP64 Hessian d2L/dtheta2, (m*m+1) x (m*m+1)."""
+    Ri, Ii = _image(R, "R"), _image(I, "I")
+    theta = _theta(theta, m, R.device)
+    obj = objective._c(I)
+    n = m * m + 1
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device=R.device)
+    if out.dtype != torch.float64 or tuple(out.shape) != (n, n) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float64 tensor of shape (m*m+1, m*m+1)")
+    ws = workspace or Workspace(R.device)
+    p, nb = ws.get(workspace_size(OP_HESSIAN, I.shape[0], I.shape[1], I.stride(0), m))
+    _check(_lib.dia_hessian(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, out.data_ptr(), p, nb,
+                            _stream(R.device)), "dia_hessian")
+    return out
+
+
 @dataclass
 class FitResult:
     theta: torch.Tensor
@@ -224,6 +259,8 @@ class FitResult:
     n_masked: int
     stop: str
     status: int
+    n_newton: int = 0
+    n_hessian: int = 0
     extra: dict = field(default_factory=dict)
 
     @property
@@ -264,7 +301,8 @@ def fit(R: torch.Tensor, I: torch.Tensor, m: int, objective: Objective, theta: O
     _check(st, "dia_fit")
     return FitResult(theta=theta, loss=res.loss, P=res.P, B0=res.B0, n_eval=res.n_eval, n_adam=res.n_adam,
                      n_lbfgs=res.n_lbfgs, n_outer=res.n_outer, n_masked=int(res.n_masked),
-                     stop=STOP.get(res.stop, str(res.stop)), status=st)
+                     stop=STOP.get(res.stop, str(res.stop)), status=st, n_newton=res.n_newton,
+                     n_hessian=res.n_hessian)
 
 
 class DIALoss(torch.autograd.Function):
@@ -286,3 +324,82 @@ class DIALoss(torch.autograd.Function):
         (grad,) = ctx.saved_tensors
         g = (grad.to(torch.float64) * gout.to(torch.float64)).to(ctx.theta_dtype)
         return g, None, None, None, None, None
+
+
+# ----------------------------------------------------------------------------- batched epochs
+@dataclass
+class Epoch:
+    """A target and the reference pixel under its pixel (0, 0); optional arrays laid out like I."""
+    I: torch.Tensor
+    ref_row0: int = 0
+    ref_col0: int = 0
+    weights: Optional[torch.Tensor] = None
+    flat: Optional[torch.Tensor] = None
+    mask: Optional[torch.Tensor] = None
+
+    def _c(self) -> _Epoch:
+        im = _image(self.I, "epoch I")
+        return _Epoch(im.data, im.rows, im.cols, im.ld, int(self.ref_row0), int(self.ref_col0),
+                      _like_target(self.weights, self.I, torch.float32, "weights"),
+                      _like_target(self.flat, self.I, torch.float32, "flat"),
+                      _like_target(self.mask, self.I, torch.uint8, "mask"))
+
+
+def _epochs(epochs):
+    arr = (_Epoch * len(epochs))()
+    for k, e in enumerate(epochs):
+        arr[k] = e._c()
+    return arr
+
+
+def batched_workspace_size(R: torch.Tensor, epochs, m: int, precision: str = "fp32", fit: bool = False) -> int:
+    n = _sz(0)
+    _check(_lib.dia_batched_workspace_size(_image(R, "R"), _epochs(epochs), len(epochs), m, PREC[precision],
+                                           int(fit), ctypes.byref(n)), "dia_batched_workspace_size")
+    return int(n.value)
+
+
+def loss_grad_batched(R: torch.Tensor, epochs, theta: torch.Tensor, m: int, objective: Objective,
+                      precision: str = "fp32", workspace: Optional[Workspace] = None):
+    """Per-epoch (loss float64[n], grad float32[n, m*m+1]) at theta[n, m*m+1]."""
+    n = len(epochs)
+    Ri = _image(R, "R")
+    if theta.dtype != torch.float32 or theta.shape != (n, m * m + 1) or not theta.is_contiguous():
+        raise ValueError("theta must be a contiguous float32 tensor of shape (n_epochs, m*m + 1)")
+    ep = _epochs(epochs)
+    obj = objective._c(R)
+    ws = workspace or Workspace(R.device)
+    p, nb = ws.get(batched_workspace_size(R, epochs, m, precision, False))
+    loss = torch.empty(n, dtype=torch.float64, device=R.device)
+    grad = torch.empty((n, m * m + 1), dtype=torch.float32, device=R.device)
+    _check(_lib.dia_loss_grad_batched(Ri, ep, n, m, ctypes.byref(obj), PREC[precision], theta.data_ptr(),
+                                      loss.data_ptr(), grad.data_ptr(), p, nb, _stream(R.device)),
+           "dia_loss_grad_batched")
+    return loss, grad
+
+
+def fit_batched(R: torch.Tensor, epochs, m: int, objective: Objective, theta: Optional[torch.Tensor] = None,
+                precision: str = "fp32", workspace: Optional[Workspace] = None, **opts):
+    """Fit every epoch; returns (theta float32[n, m*m+1], list of per-epoch FitResult, overall status)."""
+    n = len(epochs)
+    Ri = _image(R, "R")
+    if theta is not None:
+        opts.setdefault("init", "user")
+        if theta.dtype != torch.float32 or theta.shape != (n, m * m + 1) or not theta.is_contiguous():
+            raise ValueError("theta must be a contiguous float32 tensor of shape (n_epochs, m*m + 1)")
+    else:
+        theta = torch.empty((n, m * m + 1), dtype=torch.float32, device=R.device)
+    o = fit_options(**opts)
+    ep = _epochs(epochs)
+    obj = objective._c(R)
+    ws = workspace or Workspace(R.device)
+    p, nb = ws.get(batched_workspace_size(R, epochs, m, precision, True))
+    res = (_FitResult * n)()
+    st = _lib.dia_fit_batched(Ri, ep, n, m, ctypes.byref(obj), ctypes.byref(o), PREC[precision], theta.data_ptr(),
+                              res, p, nb, _stream(R.device))
+    _check(st, "dia_fit_batched")
+    out = [FitResult(theta=theta[k], loss=r.loss, P=r.P, B0=r.B0, n_eval=r.n_eval, n_adam=r.n_adam,
+                     n_lbfgs=r.n_lbfgs, n_outer=r.n_outer, n_masked=int(r.n_masked),
+                     stop=STOP.get(r.stop, str(r.stop)), status=r.status, n_newton=r.n_newton,
+                     n_hessian=r.n_hessian) for k, r in enumerate(res)]
+    return theta, out, st

@@ -16,7 +16,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdia.so")
-SOURCES = ["tile_kernels.hip", "fit_kernels.hip", "batched_kernels.hip", "dia_api.cpp"]
+SOURCES = ["tile_dispatch.cpp", "fit_kernels.hip", "newton_kernels.hip", "bf16x3_kernels.hip", "dia_api.cpp",
+           "batched_api.cpp", "newton_host.cpp"]
+KERNEL_SIZES = list(range(1, 50, 2))  # one translation unit of tiled kernels per odd kernel size
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("DIA_OFFLOAD_ARCH", "gfx950")
@@ -29,9 +31,10 @@ FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, defines, name = job
+    obj = os.path.join(OBJDIR, name + ".o")
+    cmd = [HIPCC, *FLAGS, *defines, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
@@ -39,11 +42,12 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4) -> str:
+def build(jobs: int = 8) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    work = [("tile_inst.hip", [f"-DDIA_INST_M={m}"], f"tile_inst_m{m:02d}") for m in KERNEL_SIZES]
+    work += [(s, [], os.path.splitext(s)[0]) for s in SOURCES]
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(_compile, work))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,6 +64,6 @@ def clean() -> None:
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--jobs", type=int, default=8)
     a = ap.parse_args()
     print(build(a.jobs))

@@ -24,7 +24,7 @@ struct ObjParams {
 };
 
 // What one launch of the tiled kernel does with the forward result.
-enum TileMode { MODE_EVAL = 0, MODE_MODEL = 1, MODE_CLIP = 2 };
+enum TileMode { MODE_EVAL = 0, MODE_MODEL = 1, MODE_CLIP = 2, MODE_CURV = 3 };
 
 struct TileArgs {
     const float* R;
@@ -32,7 +32,8 @@ struct TileArgs {
     const float* I;
     long long ldI;     // also the leading dimension of weights, flat, mask, w_out, mask_out
     int rows, cols;
-    const float* theta;  // K (m*m, row-major) then B0
+    const float* theta;    // K (m*m, row-major) then B0
+    const double* theta64; // MODE_EVAL: the same values widened to FP64 (exactly)
     ObjParams obj;
     double* partial;     // MODE_EVAL: [gridDim.x][m*m + 2]: dL/dK, dL/dB0, loss
     float* out;          // MODE_MODEL: valid model
@@ -42,6 +43,8 @@ struct TileArgs {
     float kappa;         // MODE_CLIP: clip |z| > kappa (0 = keep every pixel)
     int* clip_count;     // MODE_CLIP: pixels newly clipped (integer atomics)
     const int* done;     // if non-null and *done != 0 the launch does nothing
+    double* h_out;       // MODE_CURV: per-pixel curvature d2l/dM2 on the valid region, row stride Wv
+    int curv_exact;      // MODE_CURV: 1 = exact d2l/dM2, 0 = the positive Gauss-Newton / IRLS form
 };
 
 // Geometry of the tiled kernel for an m x m kernel (all compile-time).
@@ -49,8 +52,11 @@ struct TileArgs {
 //    so m * NS threads cover the m x m taps of one tile;
 //  - forward: thread (rg, cs) owns RB output rows x S output columns.
 //  - tile = TY x TX outputs; the reference tile (with its m-1 halo) and the g tile live in LDS.
-template <int M>
+// RBV selects the rows per forward thread (0 = the largest of 4, 2, 1 whose LDS fits the budget);
+// the autotuner chooses among the variants that are compiled.
+template <int M, int RBV = 0>
 struct Geo {
+    static constexpr int kLdsBudget = 60 * 1024;
     static constexpr int S = 8;
     static constexpr int NS = (256 / M) < 32 ? (256 / M) : 32;
     static constexpr int NA = M * NS;                    // active threads
@@ -58,10 +64,43 @@ struct Geo {
     static constexpr int TX = NS * S;
     static constexpr int RW = TX + M - 1;                // reference tile width
     static constexpr int RS = RW + ((RW % 2 == 0) ? 1 : 0);  // odd LDS row stride
-    static constexpr int lds_bytes(int rb) { return 4 * ((M * rb + M - 1) * RS + M * rb * TX); }
-    static constexpr int RB = lds_bytes(4) <= 60 * 1024 ? 4 : (lds_bytes(2) <= 60 * 1024 ? 2 : 1);
+    // FP32 reference tile + FP64 g tile
+    static constexpr int lds_bytes(int rb) { return 4 * (M * rb + M - 1) * RS + 8 * M * rb * TX; }
+    static constexpr int RB_AUTO = lds_bytes(4) <= kLdsBudget ? 4 : (lds_bytes(2) <= kLdsBudget ? 2 : 1);
+    static constexpr int RB = (RBV > 0 && lds_bytes(RBV) <= kLdsBudget) ? RBV : RB_AUTO;
     static constexpr int TY = M * RB;
     static constexpr int RH = TY + M - 1;                // reference tile height
+};
+
+// One epoch of a batched fit as the kernels see it.
+struct EpochDev {
+    const float* R;        // shared reference, already offset to this epoch's crop
+    const float* I;
+    long long ldI;
+    int rows, cols;
+    const float* theta;    // the point being evaluated (m*m + 1 floats)
+    const double* theta64; // the same values widened to FP64
+    const float* weights;
+    const float* flat;
+    const uint8_t* mask;
+    const int* done;       // this epoch's done flag
+    int ntx;               // tiles across the valid region
+    int pad;
+};
+
+// A run of consecutive tiles of one epoch, processed by one workgroup into one partial row.
+struct ChunkDev {
+    int epoch, t_begin, t_end, pad;
+};
+
+struct BatchedArgs {
+    const EpochDev* ep;
+    const ChunkDev* chunks;
+    int n_chunks;
+    long long ldR;
+    ObjParams obj;     // shared scalars; weights / flat / mask come from the epoch
+    double* partial;   // [n_chunks][m*m + 2]
+    int* queue;        // work-queue head (reset by the reduce kernel)
 };
 
 // rho(z) and psi(z) = rho'(z) for the three loss shapes.
@@ -121,6 +160,107 @@ __device__ __forceinline__ void pixel_objective(const ObjParams& o, float Iv, fl
     }
 }
 
+// FP64 forms used by the fused pass (FP32 inputs widen exactly; the model value and the
+// residual I - M are carried in FP64, so the gradient keeps FP64 accuracy).
+__device__ __forceinline__ void rho_psi_d(const ObjParams& o, double z, double& rho, double& psi) {
+    if (o.rho == DIA_RHO_GAUSS) {
+        rho = 0.5 * z * z;
+        psi = z;
+    } else if (o.rho == DIA_RHO_HUBER) {
+        const double c = (double)o.c;
+        const double az = fabs(z);
+        if (az <= c) {
+            rho = 0.5 * z * z;
+            psi = z;
+        } else {
+            rho = c * (az - 0.5 * c);
+            psi = copysign(c, z);
+        }
+    } else {
+        const double c = (double)o.c;
+        const double q = z * z / (c * c);
+        rho = 0.5 * c * c * log1p(q);
+        psi = z / (1.0 + q);
+    }
+}
+
+__device__ __forceinline__ void pixel_objective_d(const ObjParams& o, double Iv, double M, float w, float F,
+                                                  double& l, double& g) {
+    const double r = Iv - M;
+    double rho, psi;
+    if (o.var == DIA_VAR_WEIGHTS) {
+        const double sw = sqrt((double)w);
+        rho_psi_d(o, r * sw, rho, psi);
+        l = rho;
+        g = -psi * sw;
+        return;
+    }
+    const bool model = (o.var == DIA_VAR_CCD_MODEL || o.var == DIA_VAR_EMCCD_MODEL);
+    const double X = model ? M : Iv;
+    const double Fd = (double)F;
+    double raw, slope;
+    if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL) {
+        slope = (double)o.inv_gain / Fd;
+        raw = (double)o.s0sq / (Fd * Fd) + fmax(X, 0.0) * slope;
+    } else {
+        slope = (double)o.excess * (double)o.inv_gain / Fd;
+        raw = fmax(X, 0.0) * slope;
+    }
+    const double v = fmax(raw, (double)o.var_floor);
+    const double inv_s = 1.0 / sqrt(v);
+    rho_psi_d(o, r * inv_s, rho, psi);
+    if (!model) {
+        l = rho;
+        g = -psi * inv_s;
+    } else {
+        const double dv = (X > 0.0 && raw > (double)o.var_floor) ? slope : 0.0;
+        const double inv_v = inv_s * inv_s;
+        l = rho + 0.5 * log(v);
+        g = -psi * inv_s * (1.0 + 0.5 * r * dv * inv_v) + 0.5 * dv * inv_v;
+    }
+}
+
+// Per-pixel curvature h = d2l/dM2 (the Hessian of the loss is X^T diag(h) X because M is affine
+// in theta).  With exact = 0 the positive form used for Newton steps is returned: the Cauchy
+// curvature psi' is replaced by the IRLS weight psi(z)/z and negative values are clipped to 0.
+__device__ __forceinline__ double pixel_curvature_d(const ObjParams& o, double Iv, double M, float w, float F,
+                                                   bool exact) {
+    const double r = Iv - M;
+    auto dpsi = [&](double z) -> double {
+        if (o.rho == DIA_RHO_GAUSS) return 1.0;
+        const double c = (double)o.c;
+        if (o.rho == DIA_RHO_HUBER) return fabs(z) <= c ? 1.0 : 0.0;
+        const double q = 1.0 + z * z / (c * c);
+        return exact ? (2.0 - q) / (q * q) : 1.0 / q;
+    };
+    if (o.var == DIA_VAR_WEIGHTS) {
+        const double sw = sqrt((double)w);
+        return dpsi(r * sw) * (double)w;
+    }
+    const bool model = (o.var == DIA_VAR_CCD_MODEL || o.var == DIA_VAR_EMCCD_MODEL);
+    const double X = model ? M : Iv;
+    const double Fd = (double)F;
+    double raw, slope;
+    if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL) {
+        slope = (double)o.inv_gain / Fd;
+        raw = (double)o.s0sq / (Fd * Fd) + fmax(X, 0.0) * slope;
+    } else {
+        slope = (double)o.excess * (double)o.inv_gain / Fd;
+        raw = fmax(X, 0.0) * slope;
+    }
+    const double v = fmax(raw, (double)o.var_floor);
+    const double sg = sqrt(v);
+    const double z = r / sg;
+    if (!model) return dpsi(z) / v;
+    double rho, psi;
+    rho_psi_d(o, z, rho, psi);
+    const double dv = (X > 0.0 && raw > (double)o.var_floor) ? slope : 0.0;
+    const double z1 = -1.0 / sg - r * dv / (2.0 * v * sg);
+    const double z2 = dv / (v * sg) + 0.75 * r * dv * dv / (v * v * sg);
+    const double h = dpsi(z) * z1 * z1 + psi * z2 - dv * dv / (2.0 * v * v);
+    return exact ? h : fmax(h, 0.0);
+}
+
 // Model variance v(M) (the CCD or EMCCD form of obj.var, evaluated on the model).
 __device__ __forceinline__ float model_variance(const ObjParams& o, float M, float F) {
     if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL)
@@ -128,10 +268,25 @@ __device__ __forceinline__ float model_variance(const ObjParams& o, float M, flo
     return fmaxf(o.excess * fmaxf(M, 0.0f) * o.inv_gain / F, o.var_floor);
 }
 
-// Launchers for the tiled kernel (tile_kernels.hip).  Return hipError_t.
-int tile_grid_tiles(int m, int rows, int cols);       // number of tiles of the valid region
-int tile_block_threads(int m);
-hipError_t launch_tile(int mode, int m, int grid, const TileArgs& a, hipStream_t s);
-int tile_max_blocks_per_cu(int m);
+// Launchers for the tiled kernels (tile_kernels.hip).  Return hipError_t.
+constexpr int kNumVariants = 4;  // tile-shape variants: RB = auto, 1, 2, 4
+int tile_variant_rb(int m, int variant);               // effective RB of a variant (0 = not compiled)
+int tile_dims(int m, int variant, int* ty, int* tx);   // tile height / width of a variant
+int tile_grid_tiles(int m, int rows, int cols, int variant = 0);  // tiles of the valid region
+hipError_t launch_tile(int mode, int m, int grid, const TileArgs& a, hipStream_t s, int variant = 0);
+hipError_t launch_batched_eval(int m, int grid, const BatchedArgs& b, hipStream_t s, int variant = 0);
+
+// Kernel-kernel block of the Hessian, H_KK[t1][t2] = sum_p h_p R_(p+t1) R_(p+t2) (hess_impl.h).
+struct HessArgs {
+    const float* R;
+    long long ldR;
+    const double* h;   // per-pixel curvature, valid region, row stride Wv
+    int rows, cols;
+    double* partial;   // [splits][n_pairblocks][32]
+};
+int hess_pair_blocks(int m);
+int hess_splits(int m, int rows, int cols);
+hipError_t launch_hess(int m, const HessArgs& a, hipStream_t s);
+int tile_max_blocks_per_cu(int m, int variant = 0, bool batched = false);
 
 }  // namespace dia

@@ -119,24 +119,25 @@ __device__ void lbfgs_direction(FitState* st, const FitVecs& v, const double* g,
     __syncthreads();
 }
 
-__device__ void set_trial(FitState* st, const FitVecs& v, int n) {
-    // xt = x + alpha d; theta_eval = float(xt)
+__device__ void write_theta(const FitState* st, const double* u, float* theta, int n, double* sh,
+                            double* theta64);
+
+__device__ void set_trial(FitState* st, const FitVecs& v, int n, double* sh) {
+    // xt = x + alpha d; theta_eval = theta(xt)
     const double al = st->alpha;
-    for (int i = threadIdx.x; i < n; i += kReduceThreads) {
-        const double xv = v.x[i] + al * v.d[i];
-        v.xt[i] = xv;
-        v.theta_eval[i] = (float)xv;
-    }
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) v.xt[i] = v.x[i] + al * v.d[i];
     __syncthreads();
+    write_theta(st, v.xt, v.theta_eval, n, sh, v.theta_eval64);
 }
 
-__device__ void finish(FitState* st, int stop, int status) {
+__device__ void finish(FitState* st, int* n_done, int stop, int status) {
     __syncthreads();
     if (threadIdx.x == 0) {
         st->stop = stop;
         st->status = status;
         st->phase = PH_DONE;
         st->done = 1;
+        if (n_done != nullptr) atomicAdd(n_done, 1);
     }
     __syncthreads();
 }
@@ -162,10 +163,10 @@ __device__ void new_direction(FitState* st, const FitVecs& v, const FitOptsDev& 
         st->phase = PH_LSEARCH;
     }
     __syncthreads();
-    set_trial(st, v, n);
+    set_trial(st, v, n, sh);
 }
 
-__device__ void adam_update(FitState* st, const FitVecs& v, const FitOptsDev& o, int n) {
+__device__ void adam_update(FitState* st, const FitVecs& v, const FitOptsDev& o, int n, double* sh) {
     const int t = st->adam_t + 1;
     const double bc1 = 1.0 - pow(o.beta1, (double)t);
     const double bc2 = 1.0 - pow(o.beta2, (double)t);
@@ -177,15 +178,39 @@ __device__ void adam_update(FitState* st, const FitVecs& v, const FitOptsDev& o,
         v.v1[i] = v1;
         v.xp[i] = v.x[i];
         v.gp[i] = gi;
-        const double lr = (i == n - 1) ? o.lr_B0 : o.lr_K;
-        const double xn = v.x[i] - lr * (m1 / bc1) / (sqrt(v1 / bc2) + o.eps);
-        v.x[i] = xn;
-        v.theta_eval[i] = (float)xn;
+        // kernel steps of lr_K in K are steps of lr_K * c in u
+        const double lr = (i == n - 1) ? o.lr_B0 : o.lr_K * st->ref_scale;
+        v.x[i] = v.x[i] - lr * (m1 / bc1) / (sqrt(v1 / bc2) + o.eps);
     }
     __syncthreads();
+    write_theta(st, v.x, v.theta_eval, n, sh, v.theta_eval64);
     if (threadIdx.x == 0) {
         st->adam_t = t;
         st->n_adam += 1;
+    }
+    __syncthreads();
+}
+
+// The optimiser works in coordinates u = (c K, B0 + s sum K), s and c the mean and RMS spread
+// of the reference.  M = sum K R + B0 = sum (u_K / c)(R - s) + u_B: the constant part of R no
+// longer couples every kernel pixel to B0, and kernel pixels and background have comparable
+// curvature.  The optimum is the same point (the reference-offset invariance of the model).
+__device__ void write_theta(const FitState* st, const double* u, float* theta, int n, double* sh,
+                            double* theta64 = nullptr) {
+    const double c = st->ref_scale, s = st->ref_shift;
+    double ks = 0.0;
+    for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) {
+        const double k = u[i] / c;
+        const float kf = (float)k;
+        theta[i] = kf;
+        if (theta64) theta64[i] = (double)kf;
+        ks += k;
+    }
+    ks = block_sum(ks, sh);
+    if (threadIdx.x == 0) {
+        const float bf = (float)(u[n - 1] - s * ks);
+        theta[n - 1] = bf;
+        if (theta64) theta64[n - 1] = (double)bf;
     }
     __syncthreads();
 }
@@ -196,15 +221,22 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
     const FitVecs& v = ra.v;
     const FitOptsDev& o = ra.o;
     const int n = ra.n;
-    const double* gt = ra.gt;
+    double* gt = ra.gt;
     const double Lt = gt[n];
 
     // non-finite loss or gradient ends the fit
     int bad = 0;
     for (int i = threadIdx.x; i <= n; i += kReduceThreads) bad |= !isfinite(gt[i]);
     if (block_max((double)bad, sh) > 0.0) {
-        finish(st, STOP_NONE, DIA_E_NONFINITE);
+        finish(st, ra.n_done, STOP_NONE, DIA_E_NONFINITE);
         return;
+    }
+    // gradient in u: dL/du_K = (dL/dK - s dL/dB0) / c, dL/du_B = dL/dB0 (in place)
+    {
+        const double gB = gt[n - 1], sft = st->ref_shift, inv_c = 1.0 / st->ref_scale;
+        __syncthreads();
+        for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) gt[i] = (gt[i] - sft * gB) * inv_c;
+        __syncthreads();
     }
     if (threadIdx.x == 0) st->n_eval += 1;
     __syncthreads();
@@ -214,7 +246,10 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
         const double Lprev = st->L;
         if (phase == PH_INIT) {
             const double gm = max_abs(gt, n, sh);
-            if (threadIdx.x == 0) st->gmax0 = gm;
+            if (threadIdx.x == 0) {
+                st->gmax0 = gm;
+                st->phase = PH_ADAM;
+            }
         } else {
             // curvature pair from the last Adam step: s = x - xp, y = gt - gp (xd, d as scratch)
             for (int i = threadIdx.x; i < n; i += kReduceThreads) {
@@ -232,11 +267,11 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
         const bool switch_now = (phase == PH_ADAM && (rel < o.tol_switch || st->n_adam >= o.max_adam)) ||
                                 (phase == PH_INIT && o.skip_adam);
         if (!switch_now) {
-            adam_update(st, v, o, n);
+            adam_update(st, v, o, n, sh);
         } else {
             const double gm = max_abs(v.g, n, sh);
             if (gm <= o.tol_grad * st->gmax0) {
-                finish(st, STOP_GRAD, DIA_OK);
+                finish(st, ra.n_done, STOP_GRAD, DIA_OK);
                 return;
             }
             new_direction(st, v, o, n, sh);
@@ -244,7 +279,16 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
     } else if (phase == PH_LSEARCH) {
         const double L0 = st->L;
         const double alpha = st->alpha;
-        if (Lt <= L0 + 1e-4 * alpha * st->gtd) {
+        // Change of the loss along the step.  Far from the optimum the FP64 sum of the FP32 pixel
+        // terms is exact enough; once |dL| falls below 1e-5 |L| it is dominated by the rounding of
+        // the FP32 model values, and the change is taken from the gradients instead:
+        // L(x + s) - L(x) = (g(x) + g(x + s)) . s / 2, exact for a quadratic objective.
+        double tr = 0.0;
+        for (int i = threadIdx.x; i < n; i += kReduceThreads) tr += (v.g[i] + gt[i]) * (v.xt[i] - v.x[i]);
+        const double dlg = 0.5 * block_sum(tr, sh);
+        const double dll = Lt - L0;
+        const double dL = (fabs(dll) > 1e-5 * fabs(L0)) ? dll : dlg;
+        if (dL <= 1e-4 * alpha * st->gtd) {
             // accept: s = xt - x, y = gt - g
             for (int i = threadIdx.x; i < n; i += kReduceThreads) {
                 v.d[i] = v.xt[i] - v.x[i];
@@ -257,35 +301,38 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
                 v.g[i] = gt[i];
             }
             __syncthreads();
+            const double rel = fabs(dL) / fmax(fabs(L0), 1e-300);
+            const int small = (rel < o.tol_change) ? st->small_steps + 1 : 0;
+            __syncthreads();
             if (threadIdx.x == 0) {
                 st->L = Lt;
                 st->n_lbfgs += 1;
+                st->small_steps = small;
             }
             __syncthreads();
-            const double rel = (L0 - Lt) / fmax(fabs(L0), 1e-300);
             const double gm = max_abs(v.g, n, sh);
             if (gm <= o.tol_grad * st->gmax0) {
-                finish(st, STOP_GRAD, DIA_OK);
+                finish(st, ra.n_done, STOP_GRAD, DIA_OK);
                 return;
             }
-            if (rel < o.tol_change) {
-                finish(st, STOP_CHANGE, DIA_OK);
+            if (small >= 3) {
+                finish(st, ra.n_done, STOP_CHANGE, DIA_OK);
                 return;
             }
             if (st->n_lbfgs >= o.max_lbfgs) {
-                finish(st, STOP_CAP, DIA_W_NOT_CONVERGED);
+                finish(st, ra.n_done, STOP_CAP, DIA_W_NOT_CONVERGED);
                 return;
             }
             new_direction(st, v, o, n, sh);
         } else {
-            // backtrack: minimiser of the quadratic through L0, slope gtd and Lt, kept in [0.1, 0.5] alpha
+            // backtrack: minimiser of the quadratic through L0, slope gtd and L0 + dL, kept in [0.1, 0.5] alpha
             const int it = st->ls_iter + 1;
             if (it >= 40) {
-                finish(st, STOP_LINESEARCH, DIA_OK);
+                finish(st, ra.n_done, STOP_LINESEARCH, DIA_OK);
                 return;
             }
             const double gtd = st->gtd;
-            double an = -gtd * alpha * alpha / (2.0 * (Lt - L0 - gtd * alpha));
+            double an = -gtd * alpha * alpha / (2.0 * (dL - gtd * alpha));
             if (!(an >= 0.1 * alpha)) an = 0.1 * alpha;
             if (an > 0.5 * alpha) an = 0.5 * alpha;
             if (threadIdx.x == 0) {
@@ -293,10 +340,10 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
                 st->ls_iter = it;
             }
             __syncthreads();
-            set_trial(st, v, n);
+            set_trial(st, v, n, sh);
         }
     }
-    if (st->phase != PH_DONE && st->n_eval >= o.max_eval) finish(st, STOP_CAP, DIA_W_NOT_CONVERGED);
+    if (st->phase != PH_DONE && st->n_eval >= o.max_eval) finish(st, ra.n_done, STOP_CAP, DIA_W_NOT_CONVERGED);
 }
 
 // ---------------------------------------------------------------------------- reduce kernel
@@ -338,6 +385,67 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
 hipError_t launch_reduce(const ReduceArgs& ra, hipStream_t s) {
     const int grid = (ra.npp + kReduceCols - 1) / kReduceCols;
     hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(kReduceThreads), 0, s, ra);
+    return hipGetLastError();
+}
+
+// Batched: grid (column blocks, epochs).  Epoch e adds its chunk rows [cbeg[e], cend[e]) in order;
+// in fit mode the last workgroup of each epoch runs that epoch's optimiser step.
+__global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchReduceArgs br) {
+    __shared__ double red[4][kReduceCols];
+    __shared__ double sh[16];
+    __shared__ int last;
+    const int e = blockIdx.y;
+    const int tid = threadIdx.x;
+    if (br.queue != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *br.queue = 0;
+    const long long off = (long long)e * br.stride;
+    FitState* st = br.st ? reinterpret_cast<FitState*>(reinterpret_cast<char*>(br.st) + off) : nullptr;
+    if (st != nullptr && st->done != 0) return;
+    const int col = blockIdx.x * kReduceCols + (tid & (kReduceCols - 1));
+    const int ph = tid / kReduceCols;
+    const int c0 = br.cbeg[e], c1 = br.cend[e];
+    double s = 0.0;
+    if (col < br.npp)
+        for (int c = c0 + ph; c < c1; c += 4) s += br.partial[(long long)c * br.npp + col];
+    red[ph][tid & (kReduceCols - 1)] = s;
+    __syncthreads();
+    double* gt = br.gt + (long long)e * br.npp;
+    if (ph == 0 && col < br.npp) {
+        const double tot = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+        gt[col] = tot;
+        if (br.out_grad != nullptr && col < br.n) br.out_grad[(long long)e * br.n + col] = (float)tot;
+        if (br.out_loss != nullptr && col == br.n) br.out_loss[e] = tot;
+    }
+    if (st == nullptr) return;
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const int prev = atomicAdd(&st->counter, 1);
+        last = (prev == (int)gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    ReduceArgs ra;
+    ra.partial = nullptr;
+    ra.nblk = 0;
+    ra.npp = br.npp;
+    ra.gt = gt;
+    ra.out_loss = nullptr;
+    ra.out_grad = nullptr;
+    ra.st = st;
+    ra.v = offset_vecs(br.v, off);
+    ra.o = br.o;
+    ra.n = br.n;
+    ra.m = br.m;
+    ra.done = nullptr;
+    ra.n_done = br.n_done;
+    optimiser_step(ra, sh);
+    if (tid == 0) st->counter = 0;
+}
+
+hipError_t launch_reduce_batched(const BatchReduceArgs& ra, int n_epochs, hipStream_t s) {
+    const int gx = (ra.npp + kReduceCols - 1) / kReduceCols;
+    hipLaunchKernelGGL(reduce_batched_kernel, dim3(gx, n_epochs), dim3(kReduceThreads), 0, s, ra);
     return hipGetLastError();
 }
 
@@ -417,13 +525,62 @@ hipError_t launch_median(const float* img, int rows, int cols, long long ld, Sel
     return hipGetLastError();
 }
 
+// Sum and sum of squares of the reference, per block (fixed grid), reduced in order by the init kernel.
+__global__ __launch_bounds__(256) void ref_stats_kernel(const float* R, int rows, int cols, long long ld,
+                                                        SelectState* sel) {
+    __shared__ double sh[2][4];
+    const long long npix = (long long)rows * cols;
+    double s1 = 0.0, s2 = 0.0;
+    for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < npix;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long r = idx / cols, c = idx - r * cols;
+        const double x = (double)R[r * ld + c];
+        s1 += x;
+        s2 += x * x;
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = s1;
+        sh[1][threadIdx.x >> 6] = s2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sel->stat_part[2 * blockIdx.x] = ((sh[0][0] + sh[0][1]) + sh[0][2]) + sh[0][3];
+        sel->stat_part[2 * blockIdx.x + 1] = ((sh[1][0] + sh[1][1]) + sh[1][2]) + sh[1][3];
+        if (blockIdx.x == 0) sel->stat_n = npix;
+    }
+}
+
+hipError_t launch_ref_stats(const float* R, int rows, int cols, long long ld, SelectState* sel, hipStream_t s) {
+    hipLaunchKernelGGL(ref_stats_kernel, dim3(kStatBlocks), dim3(256), 0, s, R, rows, cols, ld, sel);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------- fit init / finalize
-__global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st, FitVecs v, int m, int init_kind,
-                                                                  double phi, const float* theta_user,
-                                                                  const SelectState* sel) {
+__global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st0, FitVecs v0, int m, int init_kind,
+                                                                  double phi, const float* theta_user0,
+                                                                  const SelectState* sel0, long long stride) {
     __shared__ double sh[16];
     const int n = m * m + 1;
+    const long long off = (long long)blockIdx.x * stride;
+    FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + off);
+    const FitVecs v = offset_vecs(v0, off);
+    const float* theta_user = theta_user0 ? theta_user0 + (long long)blockIdx.x * n : nullptr;
+    const SelectState* sel = reinterpret_cast<const SelectState*>(reinterpret_cast<const char*>(sel0) + off);
     const int h = (m - 1) / 2;
+
+    // reference statistics: s = mean, c = RMS of (R - s) (1 for a constant reference)
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < kStatBlocks; ++b) {
+        s1 += sel->stat_part[2 * b];
+        s2 += sel->stat_part[2 * b + 1];
+    }
+    const double np = (double)(sel->stat_n > 0 ? sel->stat_n : 1);
+    const double sft = s1 / np;
+    const double var = s2 / np - sft * sft;
+    const double scl = var > 0.0 ? sqrt(var) : 1.0;
+
     double ksum = 1.0;
     if (init_kind == DIA_INIT_GAUSS) {
         double s = 0.0;
@@ -439,6 +596,8 @@ __global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st, 
         const double hi = (double)key2f(sel->prefix[1]);
         B0 = 0.5 * (lo + hi);
     }
+    // theta_0 -> u: u_K = c K, u_B = B0 + s sum K
+    double kt = 0.0;
     for (int i = threadIdx.x; i < v.ld; i += kReduceThreads) {
         double x = 0.0;
         if (i < n) {
@@ -452,37 +611,52 @@ __global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st, 
                 const double da = (double)(i / m - h), db = (double)(i % m - h);
                 x = exp(-0.5 * (da * da + db * db) / (phi * phi)) / ksum;
             }
+            v.theta_eval[i] = (float)x;
+            v.theta_eval64[i] = (double)(float)x;
+            if (i < n - 1) kt += x;
         }
-        v.x[i] = x;
-        v.xt[i] = x;
+        const double u = (i < n - 1) ? scl * x : x;
+        v.x[i] = u;
+        v.xt[i] = u;
         v.g[i] = 0.0;
         v.d[i] = 0.0;
         v.m1[i] = 0.0;
         v.v1[i] = 0.0;
-        v.xp[i] = x;
+        v.xp[i] = u;
         v.gp[i] = 0.0;
-        v.theta_eval[i] = (float)x;
     }
+    kt = block_sum(kt, sh);
     if (threadIdx.x == 0) {
+        v.x[n - 1] += sft * kt;
+        v.xt[n - 1] = v.x[n - 1];
+        v.xp[n - 1] = v.x[n - 1];
         FitState z = {};
         z.phase = PH_INIT;
         z.alpha = 1.0;
+        z.ref_shift = sft;
+        z.ref_scale = scl;
         *st = z;
     }
 }
 
 hipError_t launch_init_fit(FitState* st, FitVecs v, int m, int init_kind, double phi, const float* theta_user,
-                           const SelectState* sel, hipStream_t s) {
-    hipLaunchKernelGGL(init_fit_kernel, dim3(1), dim3(kReduceThreads), 0, s, st, v, m, init_kind, phi, theta_user,
-                       sel);
+                           const SelectState* sel, hipStream_t s, int n_epochs, long long stride) {
+    hipLaunchKernelGGL(init_fit_kernel, dim3(n_epochs), dim3(kReduceThreads), 0, s, st, v, m, init_kind, phi,
+                       theta_user, sel, stride);
     return hipGetLastError();
 }
 
 // Restart the optimiser from the current x (a warm start for the next outer fit); the L-BFGS
 // curvature pairs are kept, the objective having changed only through the weights and mask.
-__global__ __launch_bounds__(kReduceThreads) void restart_fit_kernel(FitState* st, FitVecs v, int n) {
+__global__ __launch_bounds__(kReduceThreads) void restart_fit_kernel(FitState* st0, FitVecs v0, int n,
+                                                                     long long stride) {
+    __shared__ double sh[16];
+    const long long off = (long long)blockIdx.x * stride;
+    FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + off);
+    const FitVecs v = offset_vecs(v0, off);
     const int hist_n = st->hist_n, hist_head = st->hist_head;
-    __syncthreads();
+    const double sft = st->ref_shift, scl = st->ref_scale;
+    write_theta(st, v.x, v.theta_eval, n, sh, v.theta_eval64);
     for (int i = threadIdx.x; i < v.ld; i += kReduceThreads) {
         const double x = v.x[i];
         v.xt[i] = x;
@@ -492,42 +666,47 @@ __global__ __launch_bounds__(kReduceThreads) void restart_fit_kernel(FitState* s
         v.v1[i] = 0.0;
         v.xp[i] = x;
         v.gp[i] = 0.0;
-        v.theta_eval[i] = (float)x;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         FitState z = {};
         z.phase = PH_INIT;
         z.alpha = 1.0;
         z.hist_n = hist_n;
         z.hist_head = hist_head;
+        z.ref_shift = sft;
+        z.ref_scale = scl;
         *st = z;
     }
 }
 
-hipError_t launch_restart_fit(FitState* st, FitVecs v, int n, hipStream_t s) {
-    hipLaunchKernelGGL(restart_fit_kernel, dim3(1), dim3(kReduceThreads), 0, s, st, v, n);
+hipError_t launch_restart_fit(FitState* st, FitVecs v, int n, hipStream_t s, int n_epochs, long long stride) {
+    hipLaunchKernelGGL(restart_fit_kernel, dim3(n_epochs), dim3(kReduceThreads), 0, s, st, v, n, stride);
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kReduceThreads) void finalize_kernel(FitState* st, FitVecs v, int m, float* theta_out) {
+__global__ __launch_bounds__(kReduceThreads) void finalize_kernel(FitState* st0, FitVecs v0, int m, float* theta_out0,
+                                                                  long long stride) {
     __shared__ double sh[16];
     const int n = m * m + 1;
+    const long long off = (long long)blockIdx.x * stride;
+    FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + off);
+    const FitVecs v = offset_vecs(v0, off);
+    float* theta_out = theta_out0 + (long long)blockIdx.x * n;
+    write_theta(st, v.x, theta_out, n, sh, nullptr);
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kReduceThreads) {
-        const float f = (float)v.x[i];
-        theta_out[i] = f;
-        if (i < m * m) s += (double)f;
-    }
+    for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) s += (double)theta_out[i];
     const double P = block_sum(s, sh);
     if (threadIdx.x == 0) {
         st->out_P = P;
-        st->out_B0 = (double)(float)v.x[n - 1];
+        st->out_B0 = (double)theta_out[n - 1];
         st->out_loss = st->L;
     }
 }
 
-hipError_t launch_finalize(FitState* st, FitVecs v, int m, float* theta_out, hipStream_t s) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kReduceThreads), 0, s, st, v, m, theta_out);
+hipError_t launch_finalize(FitState* st, FitVecs v, int m, float* theta_out, hipStream_t s, int n_epochs,
+                           long long stride) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_epochs), dim3(kReduceThreads), 0, s, st, v, m, theta_out, stride);
     return hipGetLastError();
 }
 
@@ -567,6 +746,18 @@ hipError_t launch_count_masked(const uint8_t* mask, int rows, int cols, long lon
     long long blocks = ((long long)rows * cols + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(count_masked_kernel, dim3((int)blocks), dim3(256), 0, s, mask, rows, cols, ld, m, count);
+    return hipGetLastError();
+}
+
+__global__ void widen_kernel(const float* src, double* dst, long long n) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        dst[i] = (double)src[i];
+}
+
+hipError_t launch_widen(const float* src, double* dst, long long n, hipStream_t s) {
+    long long blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(widen_kernel, dim3((int)blocks), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }
 

@@ -1,0 +1,50 @@
+// Exact-Hessian Newton polish of a fit and the observed Fisher information (Section 2.5).
+#pragma once
+
+#include "fit_state.h"
+
+namespace dia {
+
+constexpr int kMaxTheta = DIA_MAX_M * DIA_MAX_M + 1;
+
+hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
+                                hipStream_t s);
+hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, const double* th, double* d, double* info,
+                             hipStream_t s);
+hipError_t launch_newton_trial(const double* th, const double* d, double alpha, float* theta, double* theta64, int n,
+                               hipStream_t s);
+hipError_t launch_set_x(FitState* st, FitVecs v, const double* th, int n, double L, hipStream_t s);
+hipError_t launch_theta_from_x(const FitState* st, FitVecs v, int n, hipStream_t s);
+
+// Workspace of one Newton polish or one Hessian (byte offsets from its start).  part: partial
+// rows of the fused pass for this image (only when the caller has none of its own); H: the
+// n x n matrix (only when the caller does not supply it).
+struct NewtonLayout {
+    size_t h = 0, hpart = 0, H = 0, hv = 0, d = 0, th = 0, info = 0, gt = 0, part = 0, total = 0;
+    int splits = 0, npb = 0;
+    bool has_part = false, has_H = false;
+};
+NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own_H);
+
+// Hessian of the loss at (theta, theta64) into H (n x n row-major, FP64).  exact = 1: d2L itself;
+// exact = 0: the positive Gauss-Newton / IRLS form used for Newton steps.  partial: partial rows
+// with room for the default tile shape's grid.
+int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, const float* theta,
+                 const double* theta64, int exact, double* partial, char* nbase, const NewtonLayout& NL, double* H,
+                 hipStream_t s);
+
+struct NewtonOutcome {
+    int steps = 0;      // accepted Newton steps
+    int evals = 0;      // fused passes spent (loss evaluations and Hessians)
+    int hessians = 0;   // Hessians formed
+    int converged = 0;  // decrement or step below the resolution of the FP32 parameters
+};
+
+// Newton steps from the optimiser point x of a finished fit (st, v) until the Newton decrement is
+// negligible (at most max_steps).  Leaves x and st->L at the result.  quadratic: the Hessian does
+// not depend on theta (Gaussian objective, variance fixed), so it is factored once.
+int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, int grid, int variant,
+                  FitState* st, const FitVecs& v, double* partial, char* nbase, const NewtonLayout& NL,
+                  int max_steps, bool quadratic, hipStream_t s, NewtonOutcome* out);
+
+}  // namespace dia

@@ -1,0 +1,171 @@
+// Host side of the exact-Hessian Newton polish and of the Hessian entry point.
+#include "api_util.h"
+#include "newton.h"
+
+namespace dia {
+
+NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own_H) {
+    NewtonLayout L;
+    const int n = m * m + 1;
+    const long long hv_px = (long long)(rows - m + 1) * (cols - m + 1);
+    L.npb = hess_pair_blocks(m);
+    L.splits = hess_splits(m, rows, cols);
+    L.has_part = own_partial;
+    L.has_H = own_H;
+    size_t off = 0;
+    L.h = off;
+    off = align_up(off + sizeof(double) * (size_t)hv_px);
+    L.hpart = off;
+    off = align_up(off + sizeof(double) * (size_t)L.splits * L.npb * 32);
+    if (own_H) {
+        L.H = off;
+        off = align_up(off + sizeof(double) * (size_t)n * n);
+    }
+    L.hv = off;
+    off = align_up(off + sizeof(double) * (size_t)(n + 1));
+    L.d = off;
+    off = align_up(off + sizeof(double) * (size_t)n);
+    L.th = off;
+    off = align_up(off + sizeof(double) * (size_t)n);
+    L.info = off;
+    off = align_up(off + sizeof(double) * 4);
+    L.gt = off;
+    off = align_up(off + sizeof(double) * (size_t)(n + 1));
+    if (own_partial) {
+        const int nt = max_tiles(m, rows, cols);
+        L.part = off;
+        off = align_up(off + sizeof(double) * (size_t)(nt < kMaxGrid ? nt : kMaxGrid) * (n + 1));
+    }
+    L.total = off;
+    return L;
+}
+
+namespace {
+
+// One fused pass at (theta, theta64) reduced into gt (gradient, then the loss at gt[n]).
+bool eval_into(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, int grid, int variant,
+               const float* theta, const double* theta64, double* partial, double* gt, hipStream_t s) {
+    TileArgs a = base_args(R, I, theta);
+    a.theta64 = theta64;
+    a.obj = obj;
+    a.partial = partial;
+    if (launch_tile(MODE_EVAL, m, grid, a, s, variant) != hipSuccess) return false;
+    ReduceArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.partial = partial;
+    ra.nblk = grid;
+    ra.npp = m * m + 2;
+    ra.gt = gt;
+    ra.n = m * m + 1;
+    ra.m = m;
+    return launch_reduce(ra, s) == hipSuccess;
+}
+
+bool read_back(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s) == hipSuccess &&
+           hipStreamSynchronize(s) == hipSuccess;
+}
+
+}  // namespace
+
+int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, const float* theta,
+                 const double* theta64, int exact, double* partial, char* nbase, const NewtonLayout& NL, double* H,
+                 hipStream_t s) {
+    const int grid0 = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, 0), 0);
+    TileArgs c = base_args(R, I, theta);
+    c.theta64 = theta64;
+    c.obj = obj;
+    c.partial = partial;
+    c.h_out = reinterpret_cast<double*>(nbase + NL.h);
+    c.curv_exact = exact;
+    if (launch_tile(MODE_CURV, m, grid0, c, s) != hipSuccess) return DIA_E_HIP;
+    ReduceArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.partial = partial;
+    ra.nblk = grid0;
+    ra.npp = m * m + 2;
+    ra.gt = reinterpret_cast<double*>(nbase + NL.hv);
+    ra.n = m * m + 1;
+    ra.m = m;
+    if (launch_reduce(ra, s) != hipSuccess) return DIA_E_HIP;
+    HessArgs ha;
+    std::memset(&ha, 0, sizeof(ha));
+    ha.R = R.data;
+    ha.ldR = R.ld;
+    ha.h = reinterpret_cast<const double*>(nbase + NL.h);
+    ha.rows = R.rows;
+    ha.cols = R.cols;
+    ha.partial = reinterpret_cast<double*>(nbase + NL.hpart);
+    if (launch_hess(m, ha, s) != hipSuccess) return DIA_E_HIP;
+    if (launch_hess_assemble(ha.partial, NL.splits, NL.npb, m, reinterpret_cast<const double*>(nbase + NL.hv), H, s) !=
+        hipSuccess)
+        return DIA_E_HIP;
+    return DIA_OK;
+}
+
+int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, int grid, int variant,
+                  FitState* st, const FitVecs& v, double* partial, char* nbase, const NewtonLayout& NL,
+                  int max_steps, bool quadratic, hipStream_t s, NewtonOutcome* out) {
+    const int n = m * m + 1;
+    double* th = reinterpret_cast<double*>(nbase + NL.th);
+    double* d = reinterpret_cast<double*>(nbase + NL.d);
+    double* H = reinterpret_cast<double*>(nbase + NL.H);
+    double* info = reinterpret_cast<double*>(nbase + NL.info);
+    double* gt = reinterpret_cast<double*>(nbase + NL.gt);
+    *out = NewtonOutcome();
+    if (!NL.has_H) return DIA_E_ARG;
+    if (launch_theta_from_x(st, v, n, s) != hipSuccess) return DIA_E_HIP;
+    if (hipMemcpyAsync(th, v.theta_eval64, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return DIA_E_HIP;
+    if (!eval_into(R, I, obj, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s)) return DIA_E_HIP;
+    ++out->evals;
+    double L = 0.0;
+    if (!read_back(&L, gt + n, sizeof(double), s)) return DIA_E_HIP;
+    if (!std::isfinite(L)) return DIA_E_NONFINITE;
+    for (int it = 0; it < max_steps; ++it) {
+        const bool factor = (it == 0) || !quadratic;
+        if (factor) {
+            const int rc = hessian_into(R, I, obj, m, v.theta_eval, v.theta_eval64, 0, partial, nbase, NL, H, s);
+            if (rc != DIA_OK) return rc;
+            ++out->evals;
+            ++out->hessians;
+        }
+        if (launch_chol_solve(H, n, factor ? 1 : 0, gt, th, d, info, s) != hipSuccess) return DIA_E_HIP;
+        double hinfo[3];
+        if (!read_back(hinfo, info, sizeof(hinfo), s)) return DIA_E_HIP;
+        if (hinfo[0] != 0.0) break;  // not positive definite: keep the current point
+        const double dec = hinfo[1];
+        // negligible predicted decrease, or a step below the FP32 resolution of the parameters
+        if (!(dec > 2e-12 * (std::fabs(L) + 1.0)) || hinfo[2] <= 3e-8) {
+            out->converged = 1;
+            break;
+        }
+        bool accepted = false;
+        double alpha = 1.0;
+        for (int ls = 0; ls < 8; ++ls, alpha *= 0.5) {
+            if (launch_newton_trial(th, d, alpha, v.theta_eval, v.theta_eval64, n, s) != hipSuccess) return DIA_E_HIP;
+            if (!eval_into(R, I, obj, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s))
+                return DIA_E_HIP;
+            ++out->evals;
+            double Lt = 0.0;
+            if (!read_back(&Lt, gt + n, sizeof(double), s)) return DIA_E_HIP;
+            if (std::isfinite(Lt) && Lt <= L - 1e-4 * alpha * dec) {
+                if (hipMemcpyAsync(th, v.theta_eval64, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+                    return DIA_E_HIP;
+                L = Lt;
+                accepted = true;
+                break;
+            }
+        }
+        if (!accepted) {
+            // restore the gradient at the current point for the caller's record
+            if (launch_newton_trial(th, d, 0.0, v.theta_eval, v.theta_eval64, n, s) != hipSuccess) return DIA_E_HIP;
+            break;
+        }
+        ++out->steps;
+    }
+    if (launch_set_x(st, v, th, n, L, s) != hipSuccess) return DIA_E_HIP;
+    return hipStreamSynchronize(s) == hipSuccess ? DIA_OK : DIA_E_HIP;
+}
+
+}  // namespace dia

@@ -1,0 +1,230 @@
+// Exact-Hessian Newton steps (the Newton form of eq. newtonupdate) and the observed
+// Fisher information of Section 2.5, in FP64:
+//   * assemble H from the kernel-kernel pair blocks and the curvature-weighted correlation row;
+//   * factor H = L L^T (left-looking Cholesky in one workgroup; column k of L is kept in row k
+//     of the storage, so every column read is coalesced) and solve H d = -g;
+//   * trial points theta + alpha d written as the FP32 parameters the fused pass evaluates.
+#include <algorithm>
+
+#include "newton.h"
+
+namespace dia {
+
+constexpr int kCholThreads = 1024;
+
+// H[t1][t2] for the kernel taps from the split partials (fixed order), the background row from
+// hv = [sum h R_(p+t) (t < m*m), sum h].
+__global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partial, int splits, int npb, int m,
+                                                            const double* hv, double* H) {
+    const int n = m * m + 1;
+    const int nb1 = (m + 3) / 4, nb2 = (m + 7) / 8;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid < (long long)npb * 32) {
+        const int pb = (int)(gid / 32), k = (int)(gid % 32);
+        const int per_pa = nb1 * nb2;
+        int pa = pb / per_pa;
+        const int bb = pb % per_pa;
+        const int b1 = (bb / nb2) * 4 + k / 8, b2 = (bb % nb2) * 8 + k % 8;
+        int a1 = 0;
+        while (pa >= m - a1) {
+            pa -= m - a1;
+            ++a1;
+        }
+        const int a2 = a1 + pa;
+        if (b1 < m && b2 < m && !(a1 == a2 && b1 > b2)) {
+            double s = 0.0;
+            for (int sp = 0; sp < splits; ++sp) s += partial[((long long)sp * npb + pb) * 32 + k];
+            const int t1 = a1 * m + b1, t2 = a2 * m + b2;
+            H[(long long)t1 * n + t2] = s;
+            H[(long long)t2 * n + t1] = s;
+        }
+    }
+    if (gid < n) {
+        const int t = (int)gid;
+        H[(long long)t * n + (n - 1)] = hv[t];
+        H[(long long)(n - 1) * n + t] = hv[t];
+    }
+}
+
+__device__ double chol_block_sum(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kCholThreads / 64; ++w) s += sh[w];
+    return s;
+}
+
+__device__ double chol_block_max(double v, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kCholThreads / 64; ++w) s = fmax(s, sh[w]);
+    return s;
+}
+
+// A (n x n, row-major, symmetric) -> column k of L stored in row k (A[k*n + i] = L[i][k], i >= k)
+// when factor != 0; then d = -(L L^T)^-1 g.  info[0] = 1 if A was not positive definite,
+// info[1] = -g.d (the Newton decrement squared), info[2] = max|d_i| / max|th_i|.
+__global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int n, int factor, const double* g,
+                                                                  const double* th, double* d, double* info) {
+    __shared__ double col[kMaxTheta];
+    __shared__ double sh[32];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    if (factor) {
+        for (int j = 0; j < n; ++j) {
+            for (int k = tid; k < j; k += kCholThreads) col[k] = A[(long long)k * n + j];
+            __syncthreads();
+            for (int i = j + tid; i < n; i += kCholThreads) {
+                double s = A[(long long)j * n + i];
+                for (int k = 0; k < j; ++k) s -= A[(long long)k * n + i] * col[k];
+                A[(long long)j * n + i] = s;
+            }
+            __syncthreads();
+            const double dj = A[(long long)j * n + j];
+            if (!(dj > 0.0)) {
+                if (tid == 0) bad = 1;
+                break;
+            }
+            const double sq = sqrt(dj);
+            __syncthreads();
+            for (int i = j + tid; i < n; i += kCholThreads)
+                A[(long long)j * n + i] = (i == j) ? sq : A[(long long)j * n + i] / sq;
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (bad) {
+        if (tid == 0) {
+            info[0] = 1.0;
+            info[1] = 0.0;
+            info[2] = 0.0;
+        }
+        return;
+    }
+    // forward: L y = -g (column-oriented), y kept in col[]
+    for (int i = tid; i < n; i += kCholThreads) col[i] = -g[i];
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        const double yk = col[k] / A[(long long)k * n + k];
+        __syncthreads();
+        if (tid == 0) col[k] = yk;
+        for (int i = k + 1 + tid; i < n; i += kCholThreads) col[i] -= A[(long long)k * n + i] * yk;
+        __syncthreads();
+    }
+    // backward: L^T x = y, with L[k][i] = A[i*n + k]
+    for (int k = n - 1; k >= 0; --k) {
+        const double xk = col[k] / A[(long long)k * n + k];
+        __syncthreads();
+        if (tid == 0) col[k] = xk;
+        for (int i = tid; i < k; i += kCholThreads) col[i] -= A[(long long)i * n + k] * xk;
+        __syncthreads();
+    }
+    double dec = 0.0, dmax = 0.0, tmax = 0.0;
+    for (int i = tid; i < n; i += kCholThreads) {
+        d[i] = col[i];
+        dec -= g[i] * col[i];
+        dmax = fmax(dmax, fabs(col[i]));
+        tmax = fmax(tmax, fabs(th[i]));
+    }
+    dec = chol_block_sum(dec, sh);
+    dmax = chol_block_max(dmax, sh);
+    tmax = chol_block_max(tmax, sh);
+    if (tid == 0) {
+        info[0] = 0.0;
+        info[1] = dec;
+        info[2] = tmax > 0.0 ? dmax / tmax : dmax;
+    }
+}
+
+// theta_t = th + alpha d, stored as the FP32 parameters (and their FP64 widening) to evaluate.
+__global__ void newton_trial_kernel(const double* th, const double* d, double alpha, float* theta, double* theta64,
+                                    int n) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) {
+        const float f = (float)(th[i] + alpha * d[i]);
+        theta[i] = f;
+        theta64[i] = (double)f;
+    }
+}
+
+// x = u(theta) (see the optimiser's coordinates) and the loss at that point.
+__global__ __launch_bounds__(256) void set_x_kernel(FitState* st, FitVecs v, const double* th, int n, double L) {
+    __shared__ double sh[8];
+    const double c = st->ref_scale, s = st->ref_shift;
+    double ks = 0.0;
+    for (int i = threadIdx.x; i < n - 1; i += 256) {
+        v.x[i] = c * th[i];
+        ks += th[i];
+    }
+    for (int off = 32; off > 0; off >>= 1) ks += __shfl_xor(ks, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ks;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        v.x[n - 1] = th[n - 1] + s * tot;
+        st->L = L;
+    }
+}
+
+// theta (FP32 and FP64 copies) from the optimiser point x.
+__global__ __launch_bounds__(256) void theta_from_x_kernel(const FitState* st, FitVecs v, int n) {
+    __shared__ double sh[8];
+    const double c = st->ref_scale, s = st->ref_shift;
+    double ks = 0.0;
+    for (int i = threadIdx.x; i < n - 1; i += 256) {
+        const double k = v.x[i] / c;
+        const float kf = (float)k;
+        v.theta_eval[i] = kf;
+        v.theta_eval64[i] = (double)kf;
+        ks += k;
+    }
+    for (int off = 32; off > 0; off >>= 1) ks += __shfl_xor(ks, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ks;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double tot = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        const float bf = (float)(v.x[n - 1] - s * tot);
+        v.theta_eval[n - 1] = bf;
+        v.theta_eval64[n - 1] = (double)bf;
+    }
+}
+
+hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
+                                hipStream_t s) {
+    const long long work = std::max<long long>((long long)npb * 32, m * m + 1);
+    const int blocks = (int)((work + 255) / 256);
+    hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, hv, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, const double* th, double* d, double* info,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(kCholThreads), 0, s, A, n, factor, g, th, d, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_newton_trial(const double* th, const double* d, double alpha, float* theta, double* theta64, int n,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(newton_trial_kernel, dim3((n + 255) / 256), dim3(256), 0, s, th, d, alpha, theta, theta64, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_x(FitState* st, FitVecs v, const double* th, int n, double L, hipStream_t s) {
+    hipLaunchKernelGGL(set_x_kernel, dim3(1), dim3(256), 0, s, st, v, th, n, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_theta_from_x(const FitState* st, FitVecs v, int n, hipStream_t s) {
+    hipLaunchKernelGGL(theta_from_x_kernel, dim3(1), dim3(256), 0, s, st, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace dia

@@ -1,0 +1,134 @@
+// Dispatch of the tiled kernels over the kernel size, and their tile geometry.
+#include "tile_ops.h"
+#include "hess_impl.h"
+
+namespace dia {
+
+#define X(MM) extern template struct TileOps<MM>;
+DIA_FOR_EACH_M(X)
+#undef X
+#define X(MM) extern template struct HessOps<MM>;
+DIA_FOR_EACH_M(X)
+#undef X
+
+template <int M>
+static int variant_rb_m(int v) {
+    if (v < 0 || v >= kNumVariants) return 0;
+    if (v > 0 && !HasVariants<M>::value) return 0;
+    switch (v) {
+        case 0: return Geo<M, 0>::RB;
+        case 1: return Geo<M, 1>::RB;
+        case 2: return Geo<M, 2>::RB;
+        default: return Geo<M, 4>::RB;
+    }
+}
+
+int tile_variant_rb(int m, int variant) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return variant_rb_m<MM>(variant);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return 0;
+    }
+}
+
+int tile_dims(int m, int variant, int* ty, int* tx) {
+    const int rb = tile_variant_rb(m, variant);
+    if (rb == 0) return -1;
+    switch (m) {
+#define X(MM)                      \
+    case MM:                       \
+        *tx = Geo<MM, 0>::TX;      \
+        break;
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return -1;
+    }
+    *ty = m * rb;
+    return 0;
+}
+
+int tile_grid_tiles(int m, int rows, int cols, int variant) {
+    int ty = 0, tx = 0;
+    if (tile_dims(m, variant, &ty, &tx) != 0) return -1;
+    const int Hv = rows - m + 1, Wv = cols - m + 1;
+    return ((Hv + ty - 1) / ty) * ((Wv + tx - 1) / tx);
+}
+
+int tile_max_blocks_per_cu(int m, int variant, bool batched) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return TileOps<MM>::occupancy(variant, batched);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return 1;
+    }
+}
+
+hipError_t launch_tile(int mode, int m, int grid, const TileArgs& a, hipStream_t s, int variant) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return TileOps<MM>::launch(mode, grid, a, s, variant);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+int hess_pair_blocks(int m) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return HessOps<MM>::pair_blocks();
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return 0;
+    }
+}
+
+int hess_splits(int m, int rows, int cols) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return HessOps<MM>::splits(rows, cols);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return 0;
+    }
+}
+
+hipError_t launch_hess(int m, const HessArgs& a, hipStream_t s) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return HessOps<MM>::launch(a, s);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batched_eval(int m, int grid, const BatchedArgs& b, hipStream_t s, int variant) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return TileOps<MM>::launch_batched(grid, b, s, variant);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dia

@@ -1,0 +1,361 @@
+// Tiled direct-correlation kernels for gfx950 (templates; instantiated per kernel size
+// in tile_inst.hip): the fused forward + objective +
+// backward pass of the DIA fit, the model image, the reweight/clip pass, and the
+// batched work-queue form of the fused pass.
+//
+// Per tile (TY x TX valid outputs):
+//   1. the reference tile with its (m-1) halo is staged in LDS once (row-coalesced);
+//   2. forward (eq. model_image_delta_basis): each thread forms RB x 8 model values
+//      in registers, sliding down the LDS rows; kernel taps are wave-uniform and
+//      come through the scalar cache;
+//   3. the per-pixel objective gives l and g = dl/dM in registers (FP64 running
+//      sums of l and g); g goes to an LDS tile — the residual never reaches HBM;
+//   4. backward: dL/dK_ab = sum g_ij R_(i+a)(j+b) — thread (a, strip) correlates the
+//      g tile with the same LDS reference tile into m FP32 accumulators, flushed
+//      into FP64 after every tile.
+// A workgroup reduces its m*m + 2 sums in a fixed order and writes one row of
+// partials; a separate kernel adds the rows in FP64.
+#pragma once
+
+#include "tile_ops.h"
+
+namespace dia {
+
+template <int M, int RBV>
+struct Smem {
+    using G = Geo<M, RBV>;
+    float Rs[G::RH * G::RS];
+    double gs[G::TY * G::TX];
+};
+
+// Kernel tap (ka, b) in FP64: the widened copy in the fused pass, the FP32 value otherwise.
+template <int MODE>
+__device__ __forceinline__ double ktap(const TileArgs& a, int idx) {
+    if (MODE == MODE_EVAL) return a.theta64[idx];
+    return (double)a.theta[idx];
+}
+
+// One tile: stage, forward, per-pixel step, and (MODE_EVAL) backward into dk64.
+// FP32 data (exactly widened), FP64 products and sums: on gfx950 an FP64 FMA issues at the
+// rate of a non-packed FP32 FMA.
+template <int M, int RBV, int MODE>
+__device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0, int tx0, float* Rs, double* gs,
+                                          double (&dk64)[M], double& loss64, double& db064) {
+    using G = Geo<M, RBV>;
+    constexpr int S = G::S, NS = G::NS, NT = G::NT, RB = G::RB;
+    constexpr int TX = G::TX, TY = G::TY, RW = G::RW, RS = G::RS, RH = G::RH;
+    constexpr int SEG = S + M - 1;
+    constexpr int H = (M - 1) / 2;
+    const int tid = threadIdx.x;
+    const int q = tid / NS;   // forward: row group; backward: kernel row a
+    const int cs = tid % NS;  // column strip
+    const bool active = tid < G::NA;
+    const int Hv = a.rows - M + 1, Wv = a.cols - M + 1;
+
+    // 1. stage the reference tile (zero outside the image)
+    for (int idx = tid; idx < RH * RW; idx += NT) {
+        const int r = idx / RW, c = idx - r * RW;
+        const int gr = ty0 + r, gc = tx0 + c;
+        Rs[r * RS + c] = (gr < a.rows && gc < a.cols) ? a.R[(long long)gr * a.ldR + gc] : 0.0f;
+    }
+    __syncthreads();
+
+    if (active) {
+        // 2. forward: acc[i][j] = B0 + sum_{ka,b} K[ka][b] * R[row + i + ka][col + j + b]
+        double acc[RB][S];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < S; ++j) acc[i][j] = B0;
+        const float* rbase = Rs + (q * RB) * RS + cs * S;
+        for (int r = 0; r < RB + M - 1; ++r) {
+            double seg[SEG];
+#pragma unroll
+            for (int k = 0; k < SEG; ++k) seg[k] = (double)rbase[r * RS + k];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int ka = r - i;
+                if (ka >= 0 && ka < M) {
+#pragma unroll
+                    for (int b = 0; b < M; ++b) {
+                        const double kv = ktap<MODE>(a, ka * M + b);
+#pragma unroll
+                        for (int j = 0; j < S; ++j) acc[i][j] = fma(kv, seg[j + b], acc[i][j]);
+                    }
+                }
+            }
+        }
+
+        // 3. per-pixel step
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int ly = q * RB + i;
+            const int oy = ty0 + ly;
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                const int lx = cs * S + j;
+                const int ox = tx0 + lx;
+                const bool valid = (oy < Hv) && (ox < Wv);
+                const long long pix = (long long)(oy + H) * a.ldI + (ox + H);
+                if (MODE == MODE_MODEL) {
+                    if (valid) a.out[(long long)oy * a.ld_out + ox] = (float)acc[i][j];
+                } else if (MODE == MODE_EVAL) {
+                    double g = 0.0;
+                    if (valid) {
+                        const bool use = (a.obj.mask == nullptr) || (a.obj.mask[pix] != 0);
+                        if (use) {
+                            const float w = a.obj.weights ? a.obj.weights[pix] : 1.0f;
+                            const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
+                            double l;
+                            pixel_objective_d(a.obj, (double)a.I[pix], acc[i][j], w, F, l, g);
+                            loss64 += l;
+                            db064 += g;
+                        }
+                    }
+                    gs[ly * TX + lx] = g;
+                } else if (MODE == MODE_CURV) {
+                    double hh = 0.0;
+                    if (valid) {
+                        const bool use = (a.obj.mask == nullptr) || (a.obj.mask[pix] != 0);
+                        if (use) {
+                            const float w = a.obj.weights ? a.obj.weights[pix] : 1.0f;
+                            const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
+                            hh = pixel_curvature_d(a.obj, (double)a.I[pix], acc[i][j], w, F, a.curv_exact != 0);
+                        }
+                        a.h_out[(long long)oy * Wv + ox] = hh;
+                        db064 += hh;
+                    }
+                    gs[ly * TX + lx] = hh;
+                } else {  // MODE_CLIP
+                    if (valid) {
+                        const uint8_t old = a.obj.mask ? a.obj.mask[pix] : (uint8_t)1;
+                        const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
+                        const float Mf = (float)acc[i][j];
+                        const float v = model_variance(a.obj, Mf, F);
+                        const float z = (float)((double)a.I[pix] - acc[i][j]) / sqrtf(v);
+                        const uint8_t keep = (a.kappa > 0.0f && fabsf(z) > a.kappa) ? (uint8_t)0 : old;
+                        a.w_out[pix] = 1.0f / v;
+                        a.mask_out[pix] = keep;
+                        if (old && !keep) atomicAdd(a.clip_count, 1);
+                    }
+                }
+            }
+        }
+    }
+
+    if (MODE == MODE_EVAL || MODE == MODE_CURV) {
+        __syncthreads();
+        if (active) {
+            // 4. backward: dk[b] += sum_i sum_j g[i][j] * R[i + q][j + b] over this strip
+            const double* gb = gs + cs * S;
+            const float* rbase = Rs + q * RS + cs * S;
+            for (int i = 0; i < TY; ++i) {
+                double gv[S];
+#pragma unroll
+                for (int j = 0; j < S; ++j) gv[j] = gb[i * TX + j];
+                double seg[SEG];
+#pragma unroll
+                for (int k = 0; k < SEG; ++k) seg[k] = (double)rbase[i * RS + k];
+#pragma unroll
+                for (int b = 0; b < M; ++b)
+#pragma unroll
+                    for (int j = 0; j < S; ++j) dk64[b] = fma(gv[j], seg[j + b], dk64[b]);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Fixed-order workgroup reduction of the per-thread sums into one partial row:
+// prow[a*m + b] = dL/dK_ab, prow[m*m] = dL/dB0, prow[m*m + 1] = loss.
+template <int M, int RBV>
+__device__ __forceinline__ void write_partials(const double (&dk64)[M], double loss64, double db064, float* Rs,
+                                               double* prow) {
+    using G = Geo<M, RBV>;
+    constexpr int NS = G::NS, NT = G::NT;
+    const int tid = threadIdx.x;
+    const bool active = tid < G::NA;
+    double* red = reinterpret_cast<double*>(Rs);
+    constexpr int CAP = (G::RH * G::RS / 2) / NT;  // kernel columns per round
+    static_assert(CAP >= 1, "LDS too small for the reduction");
+    for (int b0 = 0; b0 < M; b0 += CAP) {
+        const int nbr = (M - b0) < CAP ? (M - b0) : CAP;
+#pragma unroll
+        for (int b = 0; b < M; ++b)
+            if (b >= b0 && b < b0 + CAP) red[(b - b0) * NT + tid] = active ? dk64[b] : 0.0;
+        __syncthreads();
+        for (int o = tid; o < M * nbr; o += NT) {
+            const int ka = o / nbr, kb = o - ka * nbr;
+            double s = 0.0;
+            for (int c = 0; c < NS; ++c) s += red[kb * NT + ka * NS + c];
+            prow[ka * M + b0 + kb] = s;
+        }
+        __syncthreads();
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        loss64 += __shfl_xor(loss64, off);
+        db064 += __shfl_xor(db064, off);
+    }
+    const int lane = tid & 63, wave = tid >> 6;
+    if (lane == 0) {
+        red[2 * wave] = db064;
+        red[2 * wave + 1] = loss64;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double sb = 0.0, sl = 0.0;
+        for (int w = 0; w < NT / 64; ++w) {
+            sb += red[2 * w];
+            sl += red[2 * w + 1];
+        }
+        prow[M * M] = sb;
+        prow[M * M + 1] = sl;
+    }
+    __syncthreads();
+}
+
+// Single pair: a persistent grid walks a static, XCD-aware list of tiles.
+template <int M, int MODE, int RBV>
+__global__ __launch_bounds__((Geo<M, RBV>::NT)) void tile_kernel(TileArgs a) {
+    using G = Geo<M, RBV>;
+    __shared__ Smem<M, RBV> sm;
+    if (a.done != nullptr && *a.done != 0) return;
+
+    const int Hv = a.rows - M + 1, Wv = a.cols - M + 1;
+    const int ntx = (Wv + G::TX - 1) / G::TX, nty = (Hv + G::TY - 1) / G::TY;
+    const int ntiles = ntx * nty;
+
+    // Workgroups are dispatched round-robin over the 8 XCDs, so workgroup b runs on
+    // XCD b % 8; each XCD gets a contiguous band of tiles (neighbouring tiles share
+    // halo rows in that XCD's L2).
+    const int nb = gridDim.x;
+    const int ngrp = nb < 8 ? nb : 8;
+    const int grp = blockIdx.x % ngrp;
+    const int mem = blockIdx.x / ngrp;
+    const int nmem = (nb - grp + ngrp - 1) / ngrp;
+    const int t_begin = (int)((long long)ntiles * grp / ngrp);
+    const int t_end = (int)((long long)ntiles * (grp + 1) / ngrp);
+
+    const double B0 = ktap<MODE>(a, M * M);
+    double dk64[M];
+#pragma unroll
+    for (int b = 0; b < M; ++b) dk64[b] = 0.0;
+    double loss64 = 0.0, db064 = 0.0;
+
+    for (int t = t_begin + mem; t < t_end; t += nmem)
+        tile_body<M, RBV, MODE>(a, B0, (t / ntx) * G::TY, (t % ntx) * G::TX, sm.Rs, sm.gs, dk64, loss64, db064);
+
+    if (MODE == MODE_EVAL || MODE == MODE_CURV)
+        write_partials<M, RBV>(dk64, loss64, db064, sm.Rs, a.partial + (long long)blockIdx.x * (M * M + 2));
+}
+
+// Batched fused pass: a persistent grid pops chunks (runs of tiles of one epoch)
+// from a work queue.  Each chunk has its own partial row, so the result does not
+// depend on which workgroup ran it.  Chunks of converged epochs are skipped.
+template <int M, int RBV>
+__global__ __launch_bounds__((Geo<M, RBV>::NT)) void batched_eval_kernel(BatchedArgs b) {
+    using G = Geo<M, RBV>;
+    __shared__ Smem<M, RBV> sm;
+    __shared__ int chunk_sh;
+    for (;;) {
+        if (threadIdx.x == 0) chunk_sh = atomicAdd(b.queue, 1);
+        __syncthreads();
+        const int c = chunk_sh;
+        __syncthreads();
+        if (c >= b.n_chunks) break;
+        const ChunkDev ch = b.chunks[c];
+        const EpochDev e = b.ep[ch.epoch];
+        if (*e.done != 0) continue;
+        TileArgs a;
+        a.R = e.R;
+        a.ldR = b.ldR;
+        a.I = e.I;
+        a.ldI = e.ldI;
+        a.rows = e.rows;
+        a.cols = e.cols;
+        a.theta = e.theta;
+        a.theta64 = e.theta64;
+        a.obj = b.obj;
+        a.obj.weights = e.weights;
+        a.obj.flat = e.flat;
+        a.obj.mask = e.mask;
+        const double B0 = e.theta64[M * M];
+        double dk64[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) dk64[k] = 0.0;
+        double loss64 = 0.0, db064 = 0.0;
+        for (int t = ch.t_begin; t < ch.t_end; ++t)
+            tile_body<M, RBV, MODE_EVAL>(a, B0, (t / e.ntx) * G::TY, (t % e.ntx) * G::TX, sm.Rs, sm.gs, dk64, loss64,
+                                         db064);
+        write_partials<M, RBV>(dk64, loss64, db064, sm.Rs, b.partial + (long long)c * (M * M + 2));
+    }
+}
+
+// ---------------------------------------------------------------------------- per-size entry points
+template <int M, int RBV>
+static int occupancy_for(bool batched) {
+    int n = 0;
+    hipError_t e = batched
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batched_eval_kernel<M, RBV>, Geo<M, RBV>::NT, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tile_kernel<M, MODE_EVAL, RBV>, Geo<M, RBV>::NT, 0);
+    if (e != hipSuccess) return 1;
+    return n > 0 ? n : 1;
+}
+
+template <int M, int RBV>
+static hipError_t launch_eval_v(int grid, const TileArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((tile_kernel<M, MODE_EVAL, RBV>), dim3(grid), dim3(Geo<M, RBV>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int M, int RBV>
+static hipError_t launch_bv(int grid, const BatchedArgs& b, hipStream_t s) {
+    hipLaunchKernelGGL((batched_eval_kernel<M, RBV>), dim3(grid), dim3(Geo<M, RBV>::NT), 0, s, b);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t TileOps<M>::launch(int mode, int grid, const TileArgs& a, hipStream_t s, int v) {
+    dim3 blk(Geo<M, 0>::NT), grd(grid);
+    if (v == 0 || mode != MODE_EVAL) {
+        if (mode == MODE_EVAL)
+            hipLaunchKernelGGL((tile_kernel<M, MODE_EVAL, 0>), grd, blk, 0, s, a);
+        else if (mode == MODE_CURV)
+            hipLaunchKernelGGL((tile_kernel<M, MODE_CURV, 0>), grd, blk, 0, s, a);
+        else if (mode == MODE_MODEL)
+            hipLaunchKernelGGL((tile_kernel<M, MODE_MODEL, 0>), grd, blk, 0, s, a);
+        else
+            hipLaunchKernelGGL((tile_kernel<M, MODE_CLIP, 0>), grd, blk, 0, s, a);
+        return hipGetLastError();
+    }
+    if constexpr (HasVariants<M>::value) {
+        if (v == 1) return launch_eval_v<M, 1>(grid, a, s);
+        if (v == 2) return launch_eval_v<M, 2>(grid, a, s);
+        return launch_eval_v<M, 4>(grid, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int M>
+hipError_t TileOps<M>::launch_batched(int grid, const BatchedArgs& b, hipStream_t s, int v) {
+    if (v == 0) return launch_bv<M, 0>(grid, b, s);
+    if constexpr (HasVariants<M>::value) {
+        if (v == 1) return launch_bv<M, 1>(grid, b, s);
+        if (v == 2) return launch_bv<M, 2>(grid, b, s);
+        return launch_bv<M, 4>(grid, b, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int M>
+int TileOps<M>::occupancy(int v, bool batched) {
+    if (v == 0) return occupancy_for<M, 0>(batched);
+    if constexpr (HasVariants<M>::value) {
+        if (v == 1) return occupancy_for<M, 1>(batched);
+        if (v == 2) return occupancy_for<M, 2>(batched);
+        return occupancy_for<M, 4>(batched);
+    }
+    return 1;
+}
+
+}  // namespace dia

@@ -1,0 +1,29 @@
+// Per-kernel-size entry points of the tiled kernels.  Each kernel size is compiled in
+// its own translation unit (tile_inst.hip with DIA_INST_M), tile_dispatch.cpp switches.
+#pragma once
+
+#include "dia_common.h"
+
+namespace dia {
+
+// Kernel sizes with every tile-shape variant compiled (the others have the default only).
+template <int M>
+struct HasVariants {
+    static constexpr bool value = (M == 9 || M == 17 || M == 19 || M == 25);
+};
+
+// Variant v -> forward rows per thread requested (0 = automatic); variant 3 asks for 4.
+constexpr int variant_rbv(int v) { return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : 0)); }
+
+template <int M>
+struct TileOps {
+    static hipError_t launch(int mode, int grid, const TileArgs& a, hipStream_t s, int v);
+    static hipError_t launch_batched(int grid, const BatchedArgs& b, hipStream_t s, int v);
+    static int occupancy(int v, bool batched);
+};
+
+#define DIA_FOR_EACH_M(X) \
+    X(1) X(3) X(5) X(7) X(9) X(11) X(13) X(15) X(17) X(19) X(21) X(23) X(25) \
+    X(27) X(29) X(31) X(33) X(35) X(37) X(39) X(41) X(43) X(45) X(47) X(49)
+
+}  // namespace dia
