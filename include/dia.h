@@ -8,8 +8,8 @@
  *
  * to a target image I on the same pixel grid, by minimising a scalar
  * objective (Section 2.3 eq. loss, Section 2.4 eq. huber_nll, or a Cauchy
- * drop-in) with Adam followed by L-BFGS (Section 2.3, Section 2.6, the
- * algorithm of Section 2.7).  Every step runs in hand-written HIP kernels.
+ * drop-in) with Adam followed by L-BFGS (Section 2.3, Section 2.9, the
+ * algorithm of Section 2.10).  Every step runs in hand-written HIP kernels.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -129,7 +129,7 @@ int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const floa
 int dia_hessian(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m, double* H,
                 void* ws, size_t ws_bytes, void* stream);
 
-/* Kernel initialisation (Section 2.6): FLAT = 1/m^2 everywhere; GAUSS = a
+/* Kernel initialisation (Section 2.9): FLAT = 1/m^2 everywhere; GAUSS = a
  * symmetric Gaussian of standard deviation init_phi, normalised to sum 1;
  * USER = theta as passed in.  FLAT and GAUSS set B0 = median of I. */
 enum { DIA_INIT_FLAT = 0, DIA_INIT_GAUSS = 1, DIA_INIT_USER = 2 };
@@ -152,7 +152,7 @@ typedef struct {
     int32_t max_newton;    /* exact-Hessian Newton steps after each fit (0 = none)         */
 } dia_fit_opts;
 
-/* Fill opts with the paper's settings (Section 2.6): flat init, lr_K 1e-3,
+/* Fill opts with the paper's settings (Section 2.9): flat init, lr_K 1e-3,
  * lr_B0 10, tol_switch 1e-6, L-BFGS lr 1 with history 10, tol_change 1e-10,
  * tol_grad 1e-9, one outer fit; then up to 8 Newton steps.
  *

@@ -25,7 +25,7 @@ What it computes, with the passage each part follows:
 * ``fit_clipped``    the B08 outer loop: refit with sigma from the previous model and
                      cumulative |z| > kappa clipping (Sec. 2.1 / Sec. 2.4)
 * ``adam_step``      one bias-corrected Adam update (Sec. 2.3, Kingma & Ba defaults)
-* ``init_theta``     B0 = median(I), flat or Gaussian K (Sec. 2.7)
+* ``init_theta``     B0 = median(I), flat or Gaussian K (Sec. 2.9)
 * ``photometric_scale``  P = sum K (eq. photometric_scale_factor)
 
 Readings where the paper is silent are listed in DESIGN.md ("Readings of the paper").
@@ -430,7 +430,7 @@ def adam_step(theta, grad, m1, v1, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def init_theta(I, m, kind: str = "flat", phi_K: float = 1.0):
-    """Sec. 2.7: B0 = median of the target image; K flat at 1/N_K, or a symmetric Gaussian with
+    """Sec. 2.9: B0 = median of the target image; K flat at 1/N_K, or a symmetric Gaussian with
     standard deviation phi_K normalised to sum 1.  An even count takes the mean of the two middle values."""
     theta = np.empty(m * m + 1)
     if kind == "flat":

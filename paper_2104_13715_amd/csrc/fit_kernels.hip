@@ -1,8 +1,8 @@
 // Cross-workgroup reduction, the on-device optimiser (Adam then L-BFGS,
-// Sections 2.3 and 2.6), median initialisation and fit finalisation.
+// Sections 2.3 and 2.9), median initialisation and fit finalisation.
 //
 // The reduce kernel adds the per-workgroup partial rows of the tiled kernel in
-// FP64 in a fixed order (64 columns per workgroup).  In fit mode the last
+// FP64 in a fixed order (16 columns per workgroup, 16 row phases per column).  In fit mode the last
 // workgroup to finish (device-scope counter) runs one optimiser step with the
 // full gradient, so one optimiser iteration is exactly two launches and the
 // host never reads anything back between iterations.
@@ -347,21 +347,45 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
 }
 
 // ---------------------------------------------------------------------------- reduce kernel
+// Sum of rows r0, r0 + kReducePhases, ... < r1 of one partial column, four loads in flight
+// (fixed order: the four running sums are combined the same way every time).
+__device__ __forceinline__ double column_sum(const double* p, long long npp, int r0, int r1) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int r = r0;
+    for (; r + 3 * kReducePhases < r1; r += 4 * kReducePhases) {
+        s0 += p[(long long)r * npp];
+        s1 += p[(long long)(r + kReducePhases) * npp];
+        s2 += p[(long long)(r + 2 * kReducePhases) * npp];
+        s3 += p[(long long)(r + 3 * kReducePhases) * npp];
+    }
+    for (; r < r1; r += kReducePhases) s0 += p[(long long)r * npp];
+    return (s0 + s1) + (s2 + s3);
+}
+
+// Thread (phase, column): phases split the rows, then thread phase 0 adds the kReducePhases
+// sums in order.
+__device__ __forceinline__ double reduce_columns(const double* partial, int npp, int r0, int r1, int col,
+                                                 double (*red)[kReduceCols]) {
+    const int tid = threadIdx.x;
+    const int ph = tid / kReduceCols, c = tid % kReduceCols;
+    const double s = (col < npp) ? column_sum(partial + col, npp, r0 + ph, r1) : 0.0;
+    red[ph][c] = s;
+    __syncthreads();
+    double tot = 0.0;
+    if (ph == 0)
+        for (int k = 0; k < kReducePhases; ++k) tot += red[k][c];
+    return tot;
+}
+
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
-    __shared__ double red[4][kReduceCols];
+    __shared__ double red[kReducePhases][kReduceCols];
     __shared__ double sh[16];
     __shared__ int last;
     if (ra.done != nullptr && *ra.done != 0) return;
     const int tid = threadIdx.x;
-    const int col = blockIdx.x * kReduceCols + (tid & (kReduceCols - 1));
-    const int ph = tid / kReduceCols;
-    double s = 0.0;
-    if (col < ra.npp)
-        for (int b = ph; b < ra.nblk; b += 4) s += ra.partial[(long long)b * ra.npp + col];
-    red[ph][tid & (kReduceCols - 1)] = s;
-    __syncthreads();
-    if (ph == 0 && col < ra.npp) {
-        const double tot = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    const int col = blockIdx.x * kReduceCols + (tid % kReduceCols);
+    const double tot = reduce_columns(ra.partial, ra.npp, 0, ra.nblk, col, red);
+    if (tid < kReduceCols && col < ra.npp) {
         ra.gt[col] = tot;
         if (ra.out_grad != nullptr && col < ra.n) ra.out_grad[col] = (float)tot;
         if (ra.out_loss != nullptr && col == ra.n) ra.out_loss[0] = tot;
@@ -391,7 +415,7 @@ hipError_t launch_reduce(const ReduceArgs& ra, hipStream_t s) {
 // Batched: grid (column blocks, epochs).  Epoch e adds its chunk rows [cbeg[e], cend[e]) in order;
 // in fit mode the last workgroup of each epoch runs that epoch's optimiser step.
 __global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchReduceArgs br) {
-    __shared__ double red[4][kReduceCols];
+    __shared__ double red[kReducePhases][kReduceCols];
     __shared__ double sh[16];
     __shared__ int last;
     const int e = blockIdx.y;
@@ -400,17 +424,10 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchRed
     const long long off = (long long)e * br.stride;
     FitState* st = br.st ? reinterpret_cast<FitState*>(reinterpret_cast<char*>(br.st) + off) : nullptr;
     if (st != nullptr && st->done != 0) return;
-    const int col = blockIdx.x * kReduceCols + (tid & (kReduceCols - 1));
-    const int ph = tid / kReduceCols;
-    const int c0 = br.cbeg[e], c1 = br.cend[e];
-    double s = 0.0;
-    if (col < br.npp)
-        for (int c = c0 + ph; c < c1; c += 4) s += br.partial[(long long)c * br.npp + col];
-    red[ph][tid & (kReduceCols - 1)] = s;
-    __syncthreads();
+    const int col = blockIdx.x * kReduceCols + (tid % kReduceCols);
+    const double tot = reduce_columns(br.partial, br.npp, br.cbeg[e], br.cend[e], col, red);
     double* gt = br.gt + (long long)e * br.npp;
-    if (ph == 0 && col < br.npp) {
-        const double tot = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+    if (tid < kReduceCols && col < br.npp) {
         gt[col] = tot;
         if (br.out_grad != nullptr && col < br.n) br.out_grad[(long long)e * br.n + col] = (float)tot;
         if (br.out_loss != nullptr && col == br.n) br.out_loss[e] = tot;

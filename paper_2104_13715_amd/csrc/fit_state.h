@@ -7,7 +7,9 @@ namespace dia {
 
 constexpr int kMaxHistory = 32;
 constexpr int kReduceThreads = 256;
-constexpr int kReduceCols = 64;  // partial columns per reduce workgroup
+constexpr int kReduceCols = 16;    // partial columns per reduce workgroup
+constexpr int kReducePhases = 16;  // row phases per column
+static_assert(kReduceCols * kReducePhases == kReduceThreads, "reduce workgroup shape");
 
 enum FitPhase { PH_INIT = 0, PH_ADAM = 1, PH_LSEARCH = 2, PH_DONE = 3 };
 enum StopReason { STOP_NONE = 0, STOP_CHANGE = 1, STOP_GRAD = 2, STOP_LINESEARCH = 3, STOP_CAP = 4, STOP_NEWTON = 5 };
