@@ -65,6 +65,9 @@ def main() -> int:
     ap.add_argument("--init", default="flat", choices=["flat", "gauss"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024, help="valid rows of the oracle's timed sample")
+    ap.add_argument("--profile-kernel", action="store_true",
+                    help="only run --kernel-reps fused passes and a 256 MiB device copy (for hardware-counter runs; "
+                         "the copy calibrates FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -91,6 +94,19 @@ def main() -> int:
     taps_per_eval = 2 * P * m * m  # forward + backward (pixel, tap) products, one FMA each
     ws = dia.Workspace(dev)
     torch.cuda.synchronize()
+
+    if args.profile_kernel:
+        th = torch.from_numpy(np.r_[sf.kernel_gaussian(m, 2.2, 1.8, rot_deg=30.0, total=0.9).ravel(),
+                                    -12.0].astype(np.float32)).to(dev)
+        for _ in range(args.kernel_reps):
+            dia.loss_grad(R, I, th, m, obj, ws)
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kernel": True, "fused_passes": args.kernel_reps, "copy_bytes": 4 * x.numel()}))
+        return 0
 
     fit_kw = dict(init=args.init, init_phi=1.0)
     for _ in range(args.warmup):

@@ -102,12 +102,12 @@ inline ObjParams to_params(const dia_objective& o) {
     ObjParams p;
     p.rho = o.rho;
     p.var = o.var;
-    p.s0sq = (float)(o.sigma0 * o.sigma0);
-    p.inv_gain = o.gain > 0.0 ? (float)(1.0 / o.gain) : 0.0f;
-    p.excess = (float)o.excess;
-    p.var_floor = (float)o.var_floor;
-    p.c = (float)o.c;
-    p.inv_c2 = o.c > 0.0 ? (float)(1.0 / (o.c * o.c)) : 0.0f;
+    p.s0sq = o.sigma0 * o.sigma0;
+    p.inv_gain = o.gain > 0.0 ? 1.0 / o.gain : 0.0;
+    p.excess = o.excess;
+    p.var_floor = o.var_floor;
+    p.c = o.c;
+    p.inv_c2 = o.c > 0.0 ? 1.0 / (o.c * o.c) : 0.0;
     p.weights = o.weights;
     p.flat = o.flat;
     p.mask = o.mask;

@@ -12,12 +12,12 @@ namespace dia {
 struct ObjParams {
     int rho;
     int var;
-    float s0sq;       // sigma0^2
-    float inv_gain;   // 1 / G
-    float excess;     // E
-    float var_floor;  // lower bound on sigma^2
-    float c;          // Huber / Cauchy scale
-    float inv_c2;     // 1 / c^2
+    double s0sq;       // sigma0^2
+    double inv_gain;   // 1 / G
+    double excess;     // E
+    double var_floor;  // lower bound on sigma^2
+    double c;          // Huber / Cauchy scale
+    double inv_c2;     // 1 / c^2
     const float* weights;
     const float* flat;
     const uint8_t* mask;
@@ -109,17 +109,19 @@ __device__ __forceinline__ void rho_psi(const ObjParams& o, float z, float& rho,
         rho = 0.5f * z * z;
         psi = z;
     } else if (o.rho == DIA_RHO_HUBER) {
+        const float c = (float)o.c;
         const float az = fabsf(z);
-        if (az <= o.c) {
+        if (az <= c) {
             rho = 0.5f * z * z;
             psi = z;
         } else {
-            rho = o.c * (az - 0.5f * o.c);
-            psi = copysignf(o.c, z);
+            rho = c * (az - 0.5f * c);
+            psi = copysignf(c, z);
         }
     } else {
-        const float q = z * z * o.inv_c2;
-        rho = 0.5f * o.c * o.c * log1pf(q);
+        const float c = (float)o.c;
+        const float q = z * z * (float)o.inv_c2;
+        rho = 0.5f * c * c * log1pf(q);
         psi = z / (1.0f + q);
     }
 }
@@ -139,21 +141,22 @@ __device__ __forceinline__ void pixel_objective(const ObjParams& o, float Iv, fl
     const bool model = (o.var == DIA_VAR_CCD_MODEL || o.var == DIA_VAR_EMCCD_MODEL);
     const float X = model ? M : Iv;
     float raw, slope;
+    const float floor_v = (float)o.var_floor;
     if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL) {
-        slope = o.inv_gain / F;
-        raw = o.s0sq / (F * F) + fmaxf(X, 0.0f) * slope;
+        slope = (float)o.inv_gain / F;
+        raw = (float)o.s0sq / (F * F) + fmaxf(X, 0.0f) * slope;
     } else {
-        slope = o.excess * o.inv_gain / F;
+        slope = (float)(o.excess * o.inv_gain) / F;
         raw = fmaxf(X, 0.0f) * slope;
     }
-    const float v = fmaxf(raw, o.var_floor);
+    const float v = fmaxf(raw, floor_v);
     const float inv_s = 1.0f / sqrtf(v);
     rho_psi(o, r * inv_s, rho, psi);
     if (!model) {
         l = rho;
         g = -psi * inv_s;
     } else {
-        const float dv = (X > 0.0f && raw > o.var_floor) ? slope : 0.0f;
+        const float dv = (X > 0.0f && raw > floor_v) ? slope : 0.0f;
         const float inv_v = inv_s * inv_s;
         l = rho + 0.5f * logf(v);
         g = -psi * inv_s * (1.0f + 0.5f * r * dv * inv_v) + 0.5f * dv * inv_v;
@@ -167,7 +170,7 @@ __device__ __forceinline__ void rho_psi_d(const ObjParams& o, double z, double& 
         rho = 0.5 * z * z;
         psi = z;
     } else if (o.rho == DIA_RHO_HUBER) {
-        const double c = (double)o.c;
+        const double c = o.c;
         const double az = fabs(z);
         if (az <= c) {
             rho = 0.5 * z * z;
@@ -177,7 +180,7 @@ __device__ __forceinline__ void rho_psi_d(const ObjParams& o, double z, double& 
             psi = copysign(c, z);
         }
     } else {
-        const double c = (double)o.c;
+        const double c = o.c;
         const double q = z * z / (c * c);
         rho = 0.5 * c * c * log1p(q);
         psi = z / (1.0 + q);
@@ -200,20 +203,20 @@ __device__ __forceinline__ void pixel_objective_d(const ObjParams& o, double Iv,
     const double Fd = (double)F;
     double raw, slope;
     if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL) {
-        slope = (double)o.inv_gain / Fd;
-        raw = (double)o.s0sq / (Fd * Fd) + fmax(X, 0.0) * slope;
+        slope = o.inv_gain / Fd;
+        raw = o.s0sq / (Fd * Fd) + fmax(X, 0.0) * slope;
     } else {
-        slope = (double)o.excess * (double)o.inv_gain / Fd;
+        slope = o.excess * o.inv_gain / Fd;
         raw = fmax(X, 0.0) * slope;
     }
-    const double v = fmax(raw, (double)o.var_floor);
+    const double v = fmax(raw, o.var_floor);
     const double inv_s = 1.0 / sqrt(v);
     rho_psi_d(o, r * inv_s, rho, psi);
     if (!model) {
         l = rho;
         g = -psi * inv_s;
     } else {
-        const double dv = (X > 0.0 && raw > (double)o.var_floor) ? slope : 0.0;
+        const double dv = (X > 0.0 && raw > o.var_floor) ? slope : 0.0;
         const double inv_v = inv_s * inv_s;
         l = rho + 0.5 * log(v);
         g = -psi * inv_s * (1.0 + 0.5 * r * dv * inv_v) + 0.5 * dv * inv_v;
@@ -228,7 +231,7 @@ __device__ __forceinline__ double pixel_curvature_d(const ObjParams& o, double I
     const double r = Iv - M;
     auto dpsi = [&](double z) -> double {
         if (o.rho == DIA_RHO_GAUSS) return 1.0;
-        const double c = (double)o.c;
+        const double c = o.c;
         if (o.rho == DIA_RHO_HUBER) return fabs(z) <= c ? 1.0 : 0.0;
         const double q = 1.0 + z * z / (c * c);
         return exact ? (2.0 - q) / (q * q) : 1.0 / q;
@@ -242,19 +245,19 @@ __device__ __forceinline__ double pixel_curvature_d(const ObjParams& o, double I
     const double Fd = (double)F;
     double raw, slope;
     if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL) {
-        slope = (double)o.inv_gain / Fd;
-        raw = (double)o.s0sq / (Fd * Fd) + fmax(X, 0.0) * slope;
+        slope = o.inv_gain / Fd;
+        raw = o.s0sq / (Fd * Fd) + fmax(X, 0.0) * slope;
     } else {
-        slope = (double)o.excess * (double)o.inv_gain / Fd;
+        slope = o.excess * o.inv_gain / Fd;
         raw = fmax(X, 0.0) * slope;
     }
-    const double v = fmax(raw, (double)o.var_floor);
+    const double v = fmax(raw, o.var_floor);
     const double sg = sqrt(v);
     const double z = r / sg;
     if (!model) return dpsi(z) / v;
     double rho, psi;
     rho_psi_d(o, z, rho, psi);
-    const double dv = (X > 0.0 && raw > (double)o.var_floor) ? slope : 0.0;
+    const double dv = (X > 0.0 && raw > o.var_floor) ? slope : 0.0;
     const double z1 = -1.0 / sg - r * dv / (2.0 * v * sg);
     const double z2 = dv / (v * sg) + 0.75 * r * dv * dv / (v * v * sg);
     const double h = dpsi(z) * z1 * z1 + psi * z2 - dv * dv / (2.0 * v * v);
@@ -264,8 +267,8 @@ __device__ __forceinline__ double pixel_curvature_d(const ObjParams& o, double I
 // Model variance v(M) (the CCD or EMCCD form of obj.var, evaluated on the model).
 __device__ __forceinline__ float model_variance(const ObjParams& o, float M, float F) {
     if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL)
-        return fmaxf(o.s0sq / (F * F) + fmaxf(M, 0.0f) * o.inv_gain / F, o.var_floor);
-    return fmaxf(o.excess * fmaxf(M, 0.0f) * o.inv_gain / F, o.var_floor);
+        return fmaxf((float)o.s0sq / (F * F) + fmaxf(M, 0.0f) * (float)o.inv_gain / F, (float)o.var_floor);
+    return fmaxf((float)(o.excess * o.inv_gain) * fmaxf(M, 0.0f) / F, (float)o.var_floor);
 }
 
 // Launchers for the tiled kernels (tile_kernels.hip).  Return hipError_t.
