@@ -52,25 +52,38 @@ struct TileArgs {
 //    so m * NS threads cover the m x m taps of one tile;
 //  - forward: thread (rg, cs) owns RB output rows x S output columns.
 //  - tile = TY x TX outputs; the reference tile (with its m-1 halo) and the g tile live in LDS.
+// LDS layout: every run of 8 columns (one thread's strip) is stored with a pitch of SP floats
+// (reference) or GP doubles (g tile), and the reference row stride RS is 2 mod 64 words.  With
+// plain rows the strips of neighbouring lanes start 8 words apart and pile onto a few banks;
+// with this skew the lanes of a wave read distinct banks (backward, g tile) or at most two-way
+// shared ones (forward).
 // RBV selects the rows per forward thread (0 = the largest of 4, 2, 1 whose LDS fits the budget);
 // the autotuner chooses among the variants that are compiled.
 template <int M, int RBV = 0>
 struct Geo {
-    static constexpr int kLdsBudget = 60 * 1024;
+    static constexpr int kLdsBudget = 80 * 1024;         // two workgroups per CU
     static constexpr int S = 8;
+    static constexpr int SP = 10;                        // reference strip pitch (floats per 8 columns)
+    static constexpr int GP = 9;                         // g strip pitch (doubles per 8 columns)
     static constexpr int NS = (256 / M) < 32 ? (256 / M) : 32;
     static constexpr int NA = M * NS;                    // active threads
     static constexpr int NT = ((NA + 63) / 64) * 64;     // launched threads (whole waves)
     static constexpr int TX = NS * S;
-    static constexpr int RW = TX + M - 1;                // reference tile width
-    static constexpr int RS = RW + ((RW % 2 == 0) ? 1 : 0);  // odd LDS row stride
+    static constexpr int RW = TX + M - 1;                // reference tile width (columns)
+    static constexpr int RS0 = (RW + 7) / 8 * SP;        // words needed per reference row
+    static constexpr int RS = RS0 + ((2 - RS0) % 64 + 64) % 64;  // row stride, = 2 (mod 64)
+    static constexpr int GS = NS * GP;                   // g tile row stride (doubles)
     // FP32 reference tile + FP64 g tile
-    static constexpr int lds_bytes(int rb) { return 4 * (M * rb + M - 1) * RS + 8 * M * rb * TX; }
+    static constexpr int lds_bytes(int rb) { return 4 * (M * rb + M - 1) * RS + 8 * M * rb * GS; }
     static constexpr int RB_AUTO = lds_bytes(4) <= kLdsBudget ? 4 : (lds_bytes(2) <= kLdsBudget ? 2 : 1);
     static constexpr int RB = (RBV > 0 && lds_bytes(RBV) <= kLdsBudget) ? RBV : RB_AUTO;
     static constexpr int TY = M * RB;
     static constexpr int RH = TY + M - 1;                // reference tile height
+    // word offset of column c within a reference row / double offset within a g row
+    static __host__ __device__ constexpr int rcol(int c) { return (c >> 3) * SP + (c & 7); }
+    static __host__ __device__ constexpr int gcol(int c) { return (c >> 3) * GP + (c & 7); }
 };
+static_assert(Geo<49>::lds_bytes(Geo<49>::RB) <= Geo<49>::kLdsBudget, "LDS budget at m = 49");
 
 // One epoch of a batched fit as the kernels see it.
 struct EpochDev {

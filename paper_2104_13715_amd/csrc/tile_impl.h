@@ -25,7 +25,7 @@ template <int M, int RBV>
 struct Smem {
     using G = Geo<M, RBV>;
     float Rs[G::RH * G::RS];
-    double gs[G::TY * G::TX];
+    double gs[G::TY * G::GS];
 };
 
 // Kernel tap (ka, b) in FP64: the widened copy in the fused pass, the FP32 value otherwise.
@@ -43,7 +43,8 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                                           double (&dk64)[M], double& loss64, double& db064) {
     using G = Geo<M, RBV>;
     constexpr int S = G::S, NS = G::NS, NT = G::NT, RB = G::RB;
-    constexpr int TX = G::TX, TY = G::TY, RW = G::RW, RS = G::RS, RH = G::RH;
+    constexpr int TX = G::TX, TY = G::TY, RW = G::RW, RS = G::RS, RH = G::RH, SP = G::SP, GP = G::GP;
+    constexpr int GS = G::GS;
     constexpr int SEG = S + M - 1;
     constexpr int H = (M - 1) / 2;
     const int tid = threadIdx.x;
@@ -56,7 +57,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
     for (int idx = tid; idx < RH * RW; idx += NT) {
         const int r = idx / RW, c = idx - r * RW;
         const int gr = ty0 + r, gc = tx0 + c;
-        Rs[r * RS + c] = (gr < a.rows && gc < a.cols) ? a.R[(long long)gr * a.ldR + gc] : 0.0f;
+        Rs[r * RS + G::rcol(c)] = (gr < a.rows && gc < a.cols) ? a.R[(long long)gr * a.ldR + gc] : 0.0f;
     }
     __syncthreads();
 
@@ -67,11 +68,11 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
         for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int j = 0; j < S; ++j) acc[i][j] = B0;
-        const float* rbase = Rs + (q * RB) * RS + cs * S;
+        const float* rbase = Rs + (q * RB) * RS + cs * SP;
         for (int r = 0; r < RB + M - 1; ++r) {
             double seg[SEG];
 #pragma unroll
-            for (int k = 0; k < SEG; ++k) seg[k] = (double)rbase[r * RS + k];
+            for (int k = 0; k < SEG; ++k) seg[k] = (double)rbase[r * RS + G::rcol(k)];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 const int ka = r - i;
@@ -112,7 +113,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                             db064 += g;
                         }
                     }
-                    gs[ly * TX + lx] = g;
+                    gs[ly * GS + cs * GP + j] = g;
                 } else if (MODE == MODE_CURV) {
                     double hh = 0.0;
                     if (valid) {
@@ -125,7 +126,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                         a.h_out[(long long)oy * Wv + ox] = hh;
                         db064 += hh;
                     }
-                    gs[ly * TX + lx] = hh;
+                    gs[ly * GS + cs * GP + j] = hh;
                 } else {  // MODE_CLIP
                     if (valid) {
                         const uint8_t old = a.obj.mask ? a.obj.mask[pix] : (uint8_t)1;
@@ -147,15 +148,15 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
         __syncthreads();
         if (active) {
             // 4. backward: dk[b] += sum_i sum_j g[i][j] * R[i + q][j + b] over this strip
-            const double* gb = gs + cs * S;
-            const float* rbase = Rs + q * RS + cs * S;
+            const double* gb = gs + cs * GP;
+            const float* rbase = Rs + q * RS + cs * SP;
             for (int i = 0; i < TY; ++i) {
                 double gv[S];
 #pragma unroll
-                for (int j = 0; j < S; ++j) gv[j] = gb[i * TX + j];
+                for (int j = 0; j < S; ++j) gv[j] = gb[i * GS + j];
                 double seg[SEG];
 #pragma unroll
-                for (int k = 0; k < SEG; ++k) seg[k] = (double)rbase[i * RS + k];
+                for (int k = 0; k < SEG; ++k) seg[k] = (double)rbase[i * RS + G::rcol(k)];
 #pragma unroll
                 for (int b = 0; b < M; ++b)
 #pragma unroll
