@@ -324,12 +324,9 @@ int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const floa
     a.theta64 = th64;
     a.obj = to_params(*obj);
     a.partial = reinterpret_cast<double*>(base + L.partial);
-    // one pass: the default tile shape unless a variant is pinned (no timing passes here)
-    int variant = 0;
-    if (const char* pin = std::getenv("DIA_TILE_VARIANT")) {
-        const int vv = std::atoi(pin);
-        if (vv > 0 && vv < kNumVariants && tile_variant_rb(m, vv) != 0) variant = vv;
-    }
+    // the tile shape the fits use for this kernel and image size (timed once per process on the first
+    // call for a size class; the timing passes write only the workspace's partial rows)
+    const int variant = choose_variant(a, m, s);
     const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, variant), variant);
     if (launch_tile(MODE_EVAL, m, grid, a, s, variant) != hipSuccess) return DIA_E_HIP;
     ReduceArgs ra;
