@@ -233,8 +233,10 @@ int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32
         if (hipStreamSynchronize(s) != hipSuccess) return DIA_E_HIP;  // the workspace is free to overwrite
         int* ints = reinterpret_cast<int*>(base + L.ints);
         if (precision == DIA_PREC_BF16X3) {
-            Bf16x3Args g = bf16x3_args(base + L.gemm, R, epochs, n, m, *obj, theta, (long long)L.n * sizeof(float),
-                                       nullptr, 0, reinterpret_cast<double*>(base + L.partial));
+            Bf16x3Args g;
+            const int pc = bf16x3_prepare(base + L.gemm, R, epochs, n, m, *obj, theta, (long long)L.n * sizeof(float),
+                                          reinterpret_cast<double*>(base + L.partial), s, &g);
+            if (pc != DIA_OK) return pc;
             if (bf16x3_launch_eval(g, s) != hipSuccess) return DIA_E_HIP;
             std::vector<int> cb(n), ce(n);
             const int rows_per = bf16x3_partial_rows(m, epochs[0].rows, epochs[0].cols, n) / n;
@@ -335,8 +337,8 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
                 grid = batched_grid(m, variant, n_chunks);
                 b = batched_args(base, L, R, *obj, n_chunks);
             } else {
-                g = bf16x3_args(base + L.gemm, R, epochs, n, m, *obj, v0.theta_eval, (long long)L.stride, done0,
-                                (long long)L.stride, reinterpret_cast<double*>(base + L.partial));
+                TRY(bf16x3_prepare(base + L.gemm, R, epochs, n, m, *obj, v0.theta_eval, (long long)L.stride,
+                                   reinterpret_cast<double*>(base + L.partial), cs, &g) == DIA_OK);
                 std::vector<int> cb(n), ce(n);
                 const int rows_per = bf16x3_partial_rows(m, epochs[0].rows, epochs[0].cols, n) / n;
                 for (int e = 0; e < n; ++e) cb[e] = e * rows_per, ce[e] = (e + 1) * rows_per;

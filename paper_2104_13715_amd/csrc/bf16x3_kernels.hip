@@ -1,27 +1,398 @@
-// Batched split-precision (bf16 x 3) implicit-GEMM evaluation (not built yet: every
-// request for it is rejected at argument checking).
+// Batched split-precision (bf16 x 3) implicit-GEMM evaluation on gfx950 matrix cores.
+//
+// All epochs read the same reference window, so the forward pass of a block of 32 epochs is
+// one GEMM  M[32 epochs x pixels] = K[32 x taps] . X[taps x pixels]  and the backward pass is
+// dK[32 x taps] = G[32 x pixels] . X^T  with X = im2col(R) gathered from an LDS tile and never
+// stored.  Both run on v_mfma_f32_32x32x16_bf16 with every operand split into bf16 hi + lo
+// parts (products hi*hi + hi*lo + lo*hi: about 16 significant bits per operand, 2^-17 relative
+// representation error).  MFMA accumulates one tile in FP32; tile results are added in FP64.
+//
+// Workgroup = 8 waves, one block of 32 epochs, a contiguous range of 16 x 32 pixel tiles.
+//   * K of the block (hi / lo) is laid out in LDS in MFMA A-fragment order once per launch.
+//   * Per tile the reference window (with its m-1 halo) is staged as packed (hi << 16 | lo)
+//     words.  Forward: wave w forms rows 2w, 2w+1 of the tile for all 32 epochs; the B fragment
+//     of a lane is 8 taps of one pixel, read through a table of tap offsets.  The per-pixel objective
+//     (FP32, the same formulas as the fused pass) gives g, split into hi / lo bf16 in LDS.
+//   * Backward: the flattened taps (plus a constant-one column that yields dL/dB0) are cut into
+//     blocks of 32; wave w owns blocks w, w+8, ...; a K step is 16 pixels of one tile row.
+// The lane layouts used (gfx950, 32x32x16): A lane l holds A[l % 32][8 (l / 32) + j],
+// B lane l holds B[8 (l / 32) + j][l % 32], D lane l register r holds
+// D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+#include <algorithm>
+#include <vector>
+
+#include "api_util.h"
 #include "bf16x3.h"
 
 namespace dia {
+namespace {
 
-int bf16x3_partial_rows(int, int, int, int n_ep) { return n_ep; }
-size_t bf16x3_scratch_bytes(int, int) { return 0; }
-int bf16x3_check_epoch(const dia_epoch&, const dia_epoch&, int) { return DIA_E_ARG; }
-Bf16x3Args bf16x3_args(char* scratch, const dia_image& R, const dia_epoch*, int n, int m, const dia_objective&,
-                       const float* theta0, long long theta_stride, const int* done0, long long done_stride,
-                       double* partial) {
-    Bf16x3Args g = {};
-    g.R = R.data;
-    g.n_ep = n;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kEB = 32;             // epochs per block
+constexpr int kWaves = 8;
+constexpr int kTR = 2 * kWaves;     // tile rows (2 per wave)
+constexpr int kTC = 32;             // tile columns (one pixel per lane)
+constexpr int kThreads = 64 * kWaves;
+static_assert(kThreads == 2 * kWaves * 32, "one thread per tile pixel in the objective phase");
+constexpr int kTargetGroups = 256;  // one workgroup per CU on MI355X
+
+template <int M>
+struct BfGeo {
+    static constexpr int T = M * M;
+    static constexpr int TP = (T + 1 + 31) / 32 * 32;  // taps + the B0 column, in blocks of 32
+    static constexpr int NCH = TP / 16;                // forward K steps (16 taps)
+    static constexpr int NTB = TP / 32;                // backward tap blocks
+    static constexpr int TBW = (NTB + kWaves - 1) / kWaves;
+    static constexpr int RH = kTR + M - 1;             // staged reference rows
+    static constexpr int RW = kTC + M - 1 + 8;         // staged columns (+8: padded-tap reads stay inside)
+    static constexpr int RS = RW | 1;                  // row stride (words)
+    static constexpr int PT = kTR * kTC;               // pixels per tile (= threads per workgroup)
+    static constexpr int HALF = (M - 1) / 2;
+};
+
+__device__ __forceinline__ unsigned split_pack(float x) {
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    return ((unsigned)__builtin_bit_cast(unsigned short, h) << 16) | __builtin_bit_cast(unsigned short, l);
+}
+
+// 8 packed (hi << 16 | lo) words -> the hi and lo bf16 fragments
+__device__ __forceinline__ void unpack8(const unsigned (&w)[8], bf16x8& hi, bf16x8& lo) {
+    u32x4 h, l;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        h[k] = (w[2 * k] >> 16) | (w[2 * k + 1] & 0xFFFF0000u);
+        l[k] = (w[2 * k] & 0xFFFFu) | (w[2 * k + 1] << 16);
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
+__device__ __forceinline__ f32x16 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh, const bf16x8& bl,
+                                        f32x16 c) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+    return c;
+}
+
+template <int M>
+struct BfSmem {
+    using G = BfGeo<M>;
+    alignas(16) unsigned short Khi[G::NCH * 2 * kEB * 8];
+    alignas(16) unsigned short Klo[G::NCH * 2 * kEB * 8];
+    alignas(16) unsigned Rw[G::RH * G::RS];
+    // forward results M[epoch][pixel] (float), then g as hi / lo bf16 planes in the same bytes
+    alignas(16) unsigned short Gt[2 * kEB * G::PT];
+    alignas(16) short toff[G::TP];  // word offset of tap t in the staged window (0 for padding taps)
+    const float* Ip[kEB];
+    const float* Wp[kEB];
+    const float* Fp[kEB];
+    const uint8_t* Mp[kEB];
+    float B0[kEB];
+    double lsum[kWaves][kEB];  // per-wave FP64 loss of each epoch
+};
+
+// g planes: element (epoch e, pixel p); 8-pixel groups are rotated by e so that the 32 lanes of
+// a backward A-fragment read (one epoch each, same pixels) hit different banks
+__device__ __forceinline__ int gidx(int e, int p, int pt) { return e * pt + (p ^ ((e & 7) << 3)); }
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
+    using G = BfGeo<M>;
+    __shared__ BfSmem<M> sm;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l32 = lane & 31, q = lane >> 5;
+    const int neb = (g.n_ep + kEB - 1) / kEB;
+    const int eb = blockIdx.x % neb, wi = blockIdx.x / neb;
+    const int Hv = g.rows - M + 1, Wv = g.cols - M + 1;
+    const int ntx = (Wv + kTC - 1) / kTC, nty = (Hv + kTR - 1) / kTR, ntiles = ntx * nty;
+    const int t_begin = (int)((long long)ntiles * wi / g.wpb), t_end = (int)((long long)ntiles * (wi + 1) / g.wpb);
+
+    // K of this block in A-fragment order: (step c, half q, epoch e, j) <- tap 16 c + 8 q + j
+    for (int idx = tid; idx < kEB * G::TP; idx += kThreads) {
+        const int e = idx / G::TP, t = idx - e * G::TP;
+        const int eg = eb * kEB + e;
+        float v = 0.0f;
+        if (eg < g.n_ep && t < G::T)
+            v = reinterpret_cast<const float*>(reinterpret_cast<const char*>(g.theta0) + eg * g.theta_stride)[t];
+        const unsigned p = split_pack(v);
+        const int c = t >> 4, qq = (t >> 3) & 1, j = t & 7;
+        const int at = ((c * 2 + qq) * kEB + e) * 8 + j;
+        sm.Khi[at] = (unsigned short)(p >> 16);
+        sm.Klo[at] = (unsigned short)(p & 0xFFFFu);
+    }
+    if (tid < kEB) {
+        const int eg = eb * kEB + tid;
+        const bool ok = eg < g.n_ep;
+        sm.B0[tid] = ok ? reinterpret_cast<const float*>(reinterpret_cast<const char*>(g.theta0) + eg * g.theta_stride)[G::T]
+                        : 0.0f;
+        sm.Ip[tid] = ok ? g.I[eg] : nullptr;
+        sm.Wp[tid] = ok && g.W ? g.W[eg] : nullptr;
+        sm.Fp[tid] = ok && g.F ? g.F[eg] : nullptr;
+        sm.Mp[tid] = ok && g.Mk ? g.Mk[eg] : nullptr;
+    }
+    for (int t = tid; t < G::TP; t += kThreads) sm.toff[t] = (short)(t < G::T ? (t / M) * G::RS + t % M : 0);
+
+    // backward B-fragment base of each owned tap block: tap n = 32 tb + l32 (clamped inside the tap range)
+    int nb_off[G::TBW];
+#pragma unroll
+    for (int i = 0; i < G::TBW; ++i) {
+        const int n = (w + kWaves * i) * 32 + l32;
+        const int nc = n < G::T ? n : 0;
+        nb_off[i] = (nc / M) * G::RS + nc % M + 8 * q;
+    }
+
+    double dk64[G::TBW][16];
+#pragma unroll
+    for (int i = 0; i < G::TBW; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dk64[i][r] = 0.0;
+    for (int idx = tid; idx < kWaves * kEB; idx += kThreads) (&sm.lsum[0][0])[idx] = 0.0;
+
+    float* Ms = reinterpret_cast<float*>(sm.Gt);
+    unsigned short* Ghi = sm.Gt;
+    unsigned short* Glo = sm.Gt + kEB * G::PT;
+    const int py = tid / kTC, px = tid % kTC;  // the objective phase: one pixel per thread
+
+    for (int t = t_begin; t < t_end; ++t) {
+        const int ty0 = (t / ntx) * kTR, tx0 = (t % ntx) * kTC;
+        // keep the per-epoch tables in LDS (not hoisted into registers across tiles)
+        asm volatile("" ::: "memory");
+        __syncthreads();  // previous tile's readers are done (and, first time, the tables are visible)
+        for (int idx = tid; idx < G::RH * G::RW; idx += kThreads) {
+            const int r = idx / G::RW, c = idx - r * G::RW;
+            const int gr = ty0 + r, gc = tx0 + c;
+            const float v = (gr < g.rows && gc < g.cols) ? g.R[(long long)gr * g.ldR + gc] : 0.0f;
+            sm.Rw[r * G::RS + c] = split_pack(v);
+        }
+        __syncthreads();
+
+        // forward: rows 2w, 2w+1 of the tile, pixel l32, all 32 epochs
+        {
+            f32x16 acc0, acc1;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.0f;
+            const unsigned* pw = sm.Rw + (2 * w) * G::RS + l32;
+#pragma unroll 2
+            for (int c = 0; c < G::NCH; ++c) {
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(sm.Khi + ((c * 2 + q) * kEB + l32) * 8);
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(sm.Klo + ((c * 2 + q) * kEB + l32) * 8);
+                const short* tp = sm.toff + 16 * c + 8 * q;
+                unsigned wv0[8], wv1[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const unsigned* pj = pw + tp[j];
+                    wv0[j] = pj[0];
+                    wv1[j] = pj[G::RS];
+                }
+                bf16x8 bh, bl;
+                unpack8(wv0, bh, bl);
+                acc0 = mfma3(ah, al, bh, bl, acc0);
+                unpack8(wv1, bh, bl);
+                acc1 = mfma3(ah, al, bh, bl, acc1);
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int el = 8 * (r >> 2) + 4 * q + (r & 3);
+                Ms[el * G::PT + (2 * w) * kTC + l32] = acc0[r];
+                Ms[el * G::PT + (2 * w + 1) * kTC + l32] = acc1[r];
+            }
+        }
+        __syncthreads();
+
+        // per-pixel objective (FP32); g as hi / lo bf16 planes
+        {
+            float mv[kEB], lv[kEB];
+#pragma unroll
+            for (int e = 0; e < kEB; ++e) mv[e] = Ms[e * G::PT + tid];
+            __syncthreads();  // every M value is in registers before the planes overwrite them
+            const int y = ty0 + py, x = tx0 + px;
+            const bool valid = (y < Hv) && (x < Wv);
+            const long long pix = (long long)(y + G::HALF) * g.ldI + (x + G::HALF);
+#pragma unroll
+            for (int e = 0; e < kEB; ++e) {
+                float gv = 0.0f;
+                lv[e] = 0.0f;
+                const float* Ie = sm.Ip[e];
+                if (valid && Ie != nullptr) {
+                    const uint8_t* Me = sm.Mp[e];
+                    if (Me == nullptr || Me[pix] != 0) {
+                        const float* We = sm.Wp[e];
+                        const float* Fe = sm.Fp[e];
+                        pixel_objective(g.obj, Ie[pix], mv[e] + sm.B0[e], We ? We[pix] : 1.0f, Fe ? Fe[pix] : 1.0f,
+                                        lv[e], gv);
+                    }
+                }
+                const unsigned p = split_pack(gv);
+                Ghi[gidx(e, tid, G::PT)] = (unsigned short)(p >> 16);
+                Glo[gidx(e, tid, G::PT)] = (unsigned short)(p & 0xFFFFu);
+            }
+            // the wave's 64 pixel losses of every epoch: halving exchange (lane bit k decides which half
+            // of the remaining epochs a lane keeps), then the last pair; lane L ends with epoch (L >> 1) & 31
+#pragma unroll
+            for (int d = 32, n = kEB / 2; d >= 2; d >>= 1, n >>= 1) {
+                const bool up = (lane & d) != 0;
+#pragma unroll
+                for (int i = 0; i < n; ++i) {
+                    const float mine = up ? lv[n + i] : lv[i];
+                    const float other = up ? lv[i] : lv[n + i];
+                    lv[i] = mine + __shfl_xor(other, d);
+                }
+            }
+            const float tot = lv[0] + __shfl_xor(lv[0], 1);
+            if ((lane & 1) == 0) sm.lsum[w][(lane >> 1) & 31] += (double)tot;
+        }
+        __syncthreads();
+
+        // backward: dK[32 epochs x 32 taps] per owned tap block, K steps of 16 pixels
+        {
+            f32x16 accb[G::TBW];
+#pragma unroll
+            for (int i = 0; i < G::TBW; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) accb[i][r] = 0.0f;
+#pragma unroll 2
+            for (int s = 0; s < G::PT / 16; ++s) {
+                const int pofs = s * 16 + 8 * q;  // first pixel of this lane's 8 (tile row s / 2)
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(Ghi + gidx(l32, pofs, G::PT));
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(Glo + gidx(l32, pofs, G::PT));
+                const int rofs = (s >> 1) * G::RS + (s & 1) * 16;
+#pragma unroll
+                for (int i = 0; i < G::TBW; ++i) {
+                    const int tb = w + kWaves * i;
+                    if (tb < G::NTB) {
+                        unsigned wv[8];
+                        const unsigned* pr = sm.Rw + nb_off[i] + rofs;
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) wv[j] = pr[j];
+                        if ((tb + 1) * 32 > G::T) {
+                            const int n = tb * 32 + l32;
+#pragma unroll
+                            for (int j = 0; j < 8; ++j) wv[j] = n < G::T ? wv[j] : (n == G::T ? 0x3F800000u : 0u);
+                        }
+                        bf16x8 bh, bl;
+                        unpack8(wv, bh, bl);
+                        accb[i] = mfma3(ah, al, bh, bl, accb[i]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < G::TBW; ++i)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) dk64[i][r] += (double)accb[i][r];
+        }
+    }
+
+    // partial rows: [dK (m*m), dB0, loss] of (epoch, workgroup)
+    const int npp = G::T + 2;
+#pragma unroll
+    for (int i = 0; i < G::TBW; ++i) {
+        const int tb = w + kWaves * i;
+        const int n = tb * 32 + l32;
+        if (tb < G::NTB && n <= G::T) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int eg = eb * kEB + 8 * (r >> 2) + 4 * q + (r & 3);
+                if (eg < g.n_ep) g.partial[((long long)eg * g.wpb + wi) * npp + n] = dk64[i][r];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < kEB) {
+        const int eg = eb * kEB + tid;
+        double sl = 0.0;
+        for (int k = 0; k < kWaves; ++k) sl += sm.lsum[k][tid];
+        if (eg < g.n_ep) g.partial[((long long)eg * g.wpb + wi) * npp + G::T + 1] = sl;
+    }
+}
+
+int wpb_for(int m, int rows, int cols, int n_ep) {
+    const long long ntiles = (long long)((rows - m + 1 + kTR - 1) / kTR) * ((cols - m + 1 + kTC - 1) / kTC);
+    const int neb = (n_ep + kEB - 1) / kEB;
+    long long w = (kTargetGroups + neb - 1) / neb;
+    if (w > ntiles) w = ntiles;
+    return (int)std::max<long long>(w, 1);
+}
+
+template <int M>
+hipError_t launch_m(const Bf16x3Args& g, hipStream_t s) {
+    const int neb = (g.n_ep + kEB - 1) / kEB;
+    hipLaunchKernelGGL(bf16x3_eval_kernel<M>, dim3(neb * g.wpb), dim3(kThreads), 0, s, g);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool bf16x3_supported(int m) { return m == 9 || m == 17 || m == 19 || m == 25; }
+
+int bf16x3_partial_rows(int m, int rows, int cols, int n_ep) {
+    if (!bf16x3_supported(m) || rows < m || cols < m || n_ep < 1) return n_ep > 0 ? n_ep : 1;
+    return n_ep * wpb_for(m, rows, cols, n_ep);
+}
+
+size_t bf16x3_scratch_bytes(int, int n_ep) { return align_up(4 * sizeof(void*) * (size_t)std::max(n_ep, 1)); }
+
+int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m) {
+    if (!bf16x3_supported(m)) return DIA_E_ARG;
+    if (x.rows != first.rows || x.cols != first.cols || x.ld != first.ld) return DIA_E_SIZE;
+    if (x.ref_row0 != first.ref_row0 || x.ref_col0 != first.ref_col0) return DIA_E_SIZE;
+    return DIA_OK;
+}
+
+int bf16x3_prepare(char* scratch, const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
+                   const float* theta0, long long theta_stride, double* partial, hipStream_t s, Bf16x3Args* out) {
+    std::vector<const void*> ptrs(4 * (size_t)n);
+    bool any_w = false, any_f = false, any_m = false;
+    for (int e = 0; e < n; ++e) {
+        ptrs[e] = ep[e].I;
+        ptrs[n + e] = ep[e].weights;
+        ptrs[2 * n + e] = ep[e].flat;
+        ptrs[3 * n + e] = ep[e].mask;
+        any_w |= ep[e].weights != nullptr;
+        any_f |= ep[e].flat != nullptr;
+        any_m |= ep[e].mask != nullptr;
+    }
+    if (hipMemcpyAsync(scratch, ptrs.data(), sizeof(void*) * ptrs.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return DIA_E_HIP;
+    Bf16x3Args g;
+    std::memset(&g, 0, sizeof(g));
+    const void* const* dp = reinterpret_cast<const void* const*>(scratch);
+    g.R = R.data + (long long)ep[0].ref_row0 * R.ld + ep[0].ref_col0;
+    g.ldR = R.ld;
+    g.rows = ep[0].rows;
+    g.cols = ep[0].cols;
     g.m = m;
+    g.n_ep = n;
+    g.I = reinterpret_cast<const float* const*>(dp);
+    g.W = any_w ? reinterpret_cast<const float* const*>(dp + n) : nullptr;
+    g.F = any_f ? reinterpret_cast<const float* const*>(dp + 2 * n) : nullptr;
+    g.Mk = any_m ? reinterpret_cast<const uint8_t* const*>(dp + 3 * n) : nullptr;
+    g.ldI = ep[0].ld;
     g.theta0 = theta0;
     g.theta_stride = theta_stride;
-    g.done0 = done0;
-    g.done_stride = done_stride;
+    g.obj = to_params(obj);
+    g.obj.weights = nullptr;
+    g.obj.flat = nullptr;
+    g.obj.mask = nullptr;
     g.partial = partial;
-    g.scratch = scratch;
-    return g;
+    g.wpb = wpb_for(m, g.rows, g.cols, n);
+    *out = g;
+    return DIA_OK;
 }
-hipError_t bf16x3_launch_eval(const Bf16x3Args&, hipStream_t) { return hipErrorNotSupported; }
+
+hipError_t bf16x3_launch_eval(const Bf16x3Args& g, hipStream_t s) {
+    switch (g.m) {
+        case 9: return launch_m<9>(g, s);
+        case 17: return launch_m<17>(g, s);
+        case 19: return launch_m<19>(g, s);
+        case 25: return launch_m<25>(g, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 }  // namespace dia
