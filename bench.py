@@ -15,8 +15,11 @@ backward pass plus the FP64 reduction and the optimiser update.
 Printed (one JSON line): fwd+bwd Gtap/s sustained through the timed fits
 (value), fits/s, evaluations per fit, the fused kernel's roofline fraction
 (its duration measured with HIP events around a burst of back-to-back
-loss/gradient launches on the launch stream), and the FP64 CPU oracle timed on
-a bounded sample of the same pair.
+loss/gradient launches on the launch stream), the FP64 CPU oracle timed on
+a bounded sample of the same pair, and ("batched") the split-precision bf16x3
+matrix-core form beside the plain form on a batch of 2048^2 epochs against one
+shared reference (m = 25): fits/s, evaluations per fit and the fraction of the
+BF16 MFMA / FP64 vector peak.
 """
 from __future__ import annotations
 
@@ -33,6 +36,68 @@ METRIC = "DIA kernel fits/s & fwd+bwd Gtap/s at 4096², m=19; % of roofline vs p
 # The fused pass computes in FP64 (FP32 inputs widened exactly).  MI355X FP64 vector peak:
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s.
 PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense
+
+
+def batched_section(args, dia, sf, torch, dev, np):
+    """The batched workload (epochs of 2048^2 against one shared 2048^2 reference, m = 25): one batched fit
+    and a burst of batched loss/gradient evaluations in each precision."""
+    t0 = time.time()
+    b = sf.config5(n_epochs=args.batch_epochs)
+    m = b.m
+    print(f"# generated {args.batch_epochs} x {b.R.shape[0]}^2 batch in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    R = torch.from_numpy(b.R).to(dev)
+    eps = [dia.Epoch(I=torch.from_numpy(e.I).to(dev)) for e in b.epochs]
+    obj = dia.Objective(rho="gauss", var="ccd_data", sigma0=b.sigma0_adu, gain=b.gain)
+    n = len(eps)
+    side = b.R.shape[0]
+    P = (side - m + 1) ** 2
+    flop = 4.0 * P * m * m * n  # forward + backward, one FMA (2 FLOP) per tap, every epoch
+    th = torch.from_numpy(np.stack([np.r_[e.K_true.ravel(), e.B0_true] for e in b.epochs]).astype(np.float32)).to(dev)
+    ws = dia.Workspace(dev)
+    out = {"workload": f"{n} epochs x {side}x{side} against one shared {side}x{side} reference, m={m} "
+                       f"(the 256-epoch split-precision recipe at {n} epochs), chi2 with CCD data variance",
+           "epochs": n}
+    if args.profile_batched:
+        for _ in range(args.kernel_reps):
+            dia.loss_grad_batched(R, eps, th, m, obj, precision=args.profile_batched, workspace=ws)
+        torch.cuda.synchronize()
+        return out
+    for prec in [p for p in args.batch_precisions.split(",") if p]:
+        for _ in range(2):
+            dia.loss_grad_batched(R, eps, th, m, obj, precision=prec, workspace=ws)
+        torch.cuda.synchronize()
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        a.record()
+        for _ in range(reps):
+            dia.loss_grad_batched(R, eps, th, m, obj, precision=prec, workspace=ws)
+        z.record()
+        torch.cuda.synchronize()
+        t_eval = a.elapsed_time(z) / 1e3 / reps
+        torch.cuda.synchronize()
+        a.record()
+        theta, res, st = dia.fit_batched(R, eps, m, obj, precision=prec, workspace=ws)
+        z.record()
+        torch.cuda.synchronize()
+        t_fit = a.elapsed_time(z) / 1e3
+        ev = [r.n_eval for r in res]
+        alg = flop / t_eval / 1e12
+        rec = {"fits_per_s": round(n / t_fit, 3), "fit_s": round(t_fit, 2), "evals_per_fit_max": int(max(ev)),
+               "evals_per_fit_mean": round(float(np.mean(ev)), 1), "eval_ms": round(1e3 * t_eval, 3),
+               "algorithmic_tflops": round(alg, 2), "status": st,
+               "stops": sorted({r.stop for r in res})}
+        if prec == "bf16x3":
+            rec["mfma_tflops"] = round(3 * alg, 2)
+            rec["roofline"] = {"bound": "mfma", "achieved": round(3 * alg, 2), "peak": PEAK_BF16_MFMA_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(3 * alg / PEAK_BF16_MFMA_TFLOPS, 4)}
+        else:
+            rec["roofline"] = {"bound": "alu", "achieved": round(alg, 2), "peak": PEAK_FP64_VECTOR_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(alg / PEAK_FP64_VECTOR_TFLOPS, 4)}
+        out[prec] = rec
+        print(f"# batched {prec}: {rec}", file=sys.stderr, flush=True)
+    return out
 
 
 def traffic_from_profile(kernel_sig: str):
@@ -65,6 +130,11 @@ def main() -> int:
     ap.add_argument("--init", default="flat", choices=["flat", "gauss"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024, help="valid rows of the oracle's timed sample")
+    ap.add_argument("--batch-epochs", type=int, default=32,
+                    help="epochs of the batched split-precision workload (2048^2 each, m = 25); 0 skips it")
+    ap.add_argument("--batch-precisions", default="bf16x3,fp32")
+    ap.add_argument("--profile-batched", default="",
+                    help="only run --kernel-reps batched evaluations in this precision (for hardware-counter runs)")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only run --kernel-reps fused passes and a 256 MiB device copy (for hardware-counter runs; "
                          "the copy calibrates FETCH_SIZE / WRITE_SIZE)")
@@ -82,6 +152,10 @@ def main() -> int:
     from synthetic import starfield as sf
 
     dev = torch.device("cuda:0")
+    if args.profile_batched:
+        batched_section(args, dia, sf, torch, dev, np)
+        print(json.dumps({"profile_batched": args.profile_batched, "evaluations": args.kernel_reps}))
+        return 0
     t0 = time.time()
     pair = sf.config3(size=args.size)
     m = pair.m
@@ -169,6 +243,8 @@ def main() -> int:
                "sample": f"{reps} FP64 loss+gradient evaluations (direct loops) of the top {rows - m + 1} valid rows "
                          f"x {W - m + 1} columns of the same pair, m={m}"}
 
+    batched = batched_section(args, dia, sf, torch, dev, np) if args.batch_epochs > 0 else None
+
     gtaps = n_eval * taps_per_eval / t_fit / 1e9
     line = {
         "metric": METRIC,
@@ -196,6 +272,7 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP64_VECTOR_TFLOPS, 4),
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(line))
     return 0

@@ -144,7 +144,8 @@ typedef struct {
     double tol_grad;       /* stop when max|grad| <= tol_grad * max|grad at start|          */
     int32_t history;       /* L-BFGS memory, 1..32                                         */
     int32_t max_adam;      /* Adam steps before the switch is forced                       */
-    int32_t max_lbfgs;     /* accepted L-BFGS steps before DIA_W_NOT_CONVERGED             */
+    int32_t max_lbfgs;     /* accepted L-BFGS steps (then DIA_W_NOT_CONVERGED unless the
+                              Newton polish below converges)                                */
     int32_t max_eval;      /* total objective evaluations before DIA_W_NOT_CONVERGED       */
     int32_t max_outer;     /* fits in the reweight/clip loop (1 = a single fit)            */
     double clip_kappa;     /* clip |z| > clip_kappa between fits; 0 = no clipping          */
@@ -153,8 +154,9 @@ typedef struct {
 } dia_fit_opts;
 
 /* Fill opts with the paper's settings (Section 2.9): flat init, lr_K 1e-3,
- * lr_B0 10, tol_switch 1e-6, L-BFGS lr 1 with history 10, tol_change 1e-10,
- * tol_grad 1e-9, one outer fit; then up to 8 Newton steps.
+ * lr_B0 10, tol_switch 1e-6, L-BFGS lr 1 with history 10, tol_change 1e-8,
+ * tol_grad 1e-9, at most 5000 Adam and 500 L-BFGS steps, one outer fit; then
+ * up to 8 Newton steps.
  *
  * The Newton polish is an addition to the paper's optimiser: at m ~ 19 the
  * normal matrix of the problem has a condition number near 1e10, so the

@@ -376,11 +376,11 @@ void dia_fit_opts_default(dia_fit_opts* o) {
     o->beta2 = 0.999;
     o->eps = 1e-8;
     o->tol_switch = 1e-6;
-    o->tol_change = 1e-10;
+    o->tol_change = 1e-8;
     o->tol_grad = 1e-9;
     o->history = 10;
     o->max_adam = 5000;
-    o->max_lbfgs = 2000;
+    o->max_lbfgs = 500;
     o->max_eval = 20000;
     o->max_outer = 1;
     o->clip_kappa = 0.0;

@@ -35,15 +35,27 @@ __device__ __forceinline__ double ktap(const TileArgs& a, int idx) {
     return (double)a.theta[idx];
 }
 
-// One tile: stage, forward, per-pixel step, and (MODE_EVAL) backward into dk64.
+// Reference tile (with its m-1 halo) straight from global memory into LDS (zero outside the image).
+template <int M, int RBV>
+__device__ __forceinline__ void stage_tile(const TileArgs& a, int ty0, int tx0, float* Rs) {
+    using G = Geo<M, RBV>;
+    for (int idx = threadIdx.x; idx < G::RH * G::RW; idx += G::NT) {
+        const int r = idx / G::RW, c = idx - r * G::RW;
+        const int gr = ty0 + r, gc = tx0 + c;
+        Rs[r * G::RS + G::rcol(c)] = (gr < a.rows && gc < a.cols) ? a.R[(long long)gr * a.ldR + gc] : 0.0f;
+    }
+}
+
+// One tile whose reference window is already staged in LDS: forward, per-pixel step, and
+// (MODE_EVAL / MODE_CURV) backward into dk64.
 // FP32 data (exactly widened), FP64 products and sums: on gfx950 an FP64 FMA issues at the
 // rate of a non-packed FP32 FMA.
 template <int M, int RBV, int MODE>
 __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0, int tx0, float* Rs, double* gs,
                                           double (&dk64)[M], double& loss64, double& db064) {
     using G = Geo<M, RBV>;
-    constexpr int S = G::S, NS = G::NS, NT = G::NT, RB = G::RB;
-    constexpr int TX = G::TX, TY = G::TY, RW = G::RW, RS = G::RS, RH = G::RH, SP = G::SP, GP = G::GP;
+    constexpr int S = G::S, NS = G::NS, RB = G::RB;
+    constexpr int TY = G::TY, RS = G::RS, SP = G::SP, GP = G::GP;
     constexpr int GS = G::GS;
     constexpr int SEG = S + M - 1;
     constexpr int H = (M - 1) / 2;
@@ -53,17 +65,9 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
     const bool active = tid < G::NA;
     const int Hv = a.rows - M + 1, Wv = a.cols - M + 1;
 
-    // 1. stage the reference tile (zero outside the image)
-    for (int idx = tid; idx < RH * RW; idx += NT) {
-        const int r = idx / RW, c = idx - r * RW;
-        const int gr = ty0 + r, gc = tx0 + c;
-        Rs[r * RS + G::rcol(c)] = (gr < a.rows && gc < a.cols) ? a.R[(long long)gr * a.ldR + gc] : 0.0f;
-    }
-    __syncthreads();
-
     if (active) {
-        // 2. forward: acc[i][j] = B0 + sum_{ka,b} K[ka][b] * R[row + i + ka][col + j + b]
         double acc[RB][S];
+        // 2. forward: acc[i][j] = B0 + sum_{ka,b} K[ka][b] * R[row + i + ka][col + j + b]
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
@@ -243,8 +247,12 @@ __global__ __launch_bounds__((Geo<M, RBV>::NT)) void tile_kernel(TileArgs a) {
     for (int b = 0; b < M; ++b) dk64[b] = 0.0;
     double loss64 = 0.0, db064 = 0.0;
 
-    for (int t = t_begin + mem; t < t_end; t += nmem)
-        tile_body<M, RBV, MODE>(a, B0, (t / ntx) * G::TY, (t % ntx) * G::TX, sm.Rs, sm.gs, dk64, loss64, db064);
+    for (int t = t_begin + mem; t < t_end; t += nmem) {
+        const int ty0 = (t / ntx) * G::TY, tx0 = (t % ntx) * G::TX;
+        stage_tile<M, RBV>(a, ty0, tx0, sm.Rs);
+        __syncthreads();
+        tile_body<M, RBV, MODE>(a, B0, ty0, tx0, sm.Rs, sm.gs, dk64, loss64, db064);
+    }
 
     if (MODE == MODE_EVAL || MODE == MODE_CURV)
         write_partials<M, RBV>(dk64, loss64, db064, sm.Rs, a.partial + (long long)blockIdx.x * (M * M + 2));
@@ -285,9 +293,12 @@ __global__ __launch_bounds__((Geo<M, RBV>::NT)) void batched_eval_kernel(Batched
 #pragma unroll
         for (int k = 0; k < M; ++k) dk64[k] = 0.0;
         double loss64 = 0.0, db064 = 0.0;
-        for (int t = ch.t_begin; t < ch.t_end; ++t)
+        for (int t = ch.t_begin; t < ch.t_end; ++t) {
+            stage_tile<M, RBV>(a, (t / e.ntx) * G::TY, (t % e.ntx) * G::TX, sm.Rs);
+            __syncthreads();
             tile_body<M, RBV, MODE_EVAL>(a, B0, (t / e.ntx) * G::TY, (t % e.ntx) * G::TX, sm.Rs, sm.gs, dk64, loss64,
                                          db064);
+        }
         write_partials<M, RBV>(dk64, loss64, db064, sm.Rs, b.partial + (long long)c * (M * M + 2));
     }
 }
