@@ -43,22 +43,26 @@ def batched_section(args, dia, sf, torch, dev, np):
     """The batched workload (epochs of 2048^2 against one shared 2048^2 reference, m = 25): one batched fit
     and a burst of batched loss/gradient evaluations in each precision."""
     t0 = time.time()
-    b = sf.config5(n_epochs=args.batch_epochs)
+    uneven = args.batch_workload == "uneven"
+    b = sf.config4(n_epochs=args.batch_epochs) if uneven else sf.config5(n_epochs=args.batch_epochs)
     m = b.m
-    print(f"# generated {args.batch_epochs} x {b.R.shape[0]}^2 batch in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
+    print(f"# generated {args.batch_epochs}-epoch batch in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     R = torch.from_numpy(b.R).to(dev)
-    eps = [dia.Epoch(I=torch.from_numpy(e.I).to(dev)) for e in b.epochs]
+    eps = [dia.Epoch(I=torch.from_numpy(e.I).to(dev), ref_row0=e.row0, ref_col0=e.col0) for e in b.epochs]
     obj = dia.Objective(rho="gauss", var="ccd_data", sigma0=b.sigma0_adu, gain=b.gain)
     n = len(eps)
     side = b.R.shape[0]
-    P = (side - m + 1) ** 2
-    flop = 4.0 * P * m * m * n  # forward + backward, one FMA (2 FLOP) per tap, every epoch
+    Ps = [(e.I.shape[0] - m + 1) * (e.I.shape[1] - m + 1) for e in b.epochs]
+    flop = 4.0 * sum(Ps) * m * m  # forward + backward, one FMA (2 FLOP) per tap, every epoch
     th = torch.from_numpy(np.stack([np.r_[e.K_true.ravel(), e.B0_true] for e in b.epochs]).astype(np.float32)).to(dev)
     ws = dia.Workspace(dev)
-    out = {"workload": f"{n} epochs x {side}x{side} against one shared {side}x{side} reference, m={m} "
-                       f"(the 256-epoch split-precision recipe at {n} epochs), chi2 with CCD data variance",
-           "epochs": n}
+    if uneven:
+        wl = (f"{n} epochs of side {min(e.I.shape[0] for e in b.epochs)}..{max(e.I.shape[0] for e in b.epochs)} cut "
+              f"from one shared {side}x{side} reference, m={m}, chi2 with CCD data variance")
+    else:
+        wl = (f"{n} epochs x {side}x{side} against one shared {side}x{side} reference, m={m} "
+              f"(the 256-epoch split-precision recipe at {n} epochs), chi2 with CCD data variance")
+    out = {"workload": wl, "epochs": n, "valid_pixels": int(sum(Ps))}
     if args.profile_batched:
         for _ in range(args.kernel_reps):
             dia.loss_grad_batched(R, eps, th, m, obj, precision=args.profile_batched, workspace=ws)
@@ -133,6 +137,10 @@ def main() -> int:
     ap.add_argument("--batch-epochs", type=int, default=32,
                     help="epochs of the batched split-precision workload (2048^2 each, m = 25); 0 skips it")
     ap.add_argument("--batch-precisions", default="bf16x3,fp32")
+    ap.add_argument("--batch-workload", default="shared", choices=["shared", "uneven"],
+                    help="shared: epochs of 2048^2 on one shared window (m = 25); uneven: sides 512..2048 cut "
+                         "from a shared 2048^2 reference (m = 17, plain form only)")
+    ap.add_argument("--only-batched", action="store_true", help="print the batched section alone")
     ap.add_argument("--profile-batched", default="",
                     help="only run --kernel-reps batched evaluations in this precision (for hardware-counter runs)")
     ap.add_argument("--profile-kernel", action="store_true",
@@ -152,6 +160,9 @@ def main() -> int:
     from synthetic import starfield as sf
 
     dev = torch.device("cuda:0")
+    if args.only_batched:
+        print(json.dumps({"batched": batched_section(args, dia, sf, torch, dev, np)}))
+        return 0
     if args.profile_batched:
         batched_section(args, dia, sf, torch, dev, np)
         print(json.dumps({"profile_batched": args.profile_batched, "evaluations": args.kernel_reps}))

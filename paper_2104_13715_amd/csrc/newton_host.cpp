@@ -131,12 +131,13 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
             ++out->hessians;
         }
         if (launch_chol_solve(H, n, factor ? 1 : 0, gt, th, d, info, s) != hipSuccess) return DIA_E_HIP;
-        double hinfo[3];
+        double hinfo[4];
         if (!read_back(hinfo, info, sizeof(hinfo), s)) return DIA_E_HIP;
         if (hinfo[0] != 0.0) break;  // not positive definite: keep the current point
         const double dec = hinfo[1];
-        // negligible predicted decrease, or a step below the FP32 resolution of the parameters
-        if (!(dec > 2e-12 * (std::fabs(L) + 1.0)) || hinfo[2] <= 3e-8) {
+        // negligible predicted decrease, or a step that moves every parameter by at most two FP32
+        // spacings (the fit is stored in FP32: nothing finer can be represented)
+        if (!(dec > 2e-12 * (std::fabs(L) + 1.0)) || hinfo[2] <= 3e-8 || hinfo[3] <= 2.0) {
             out->converged = 1;
             break;
         }
@@ -158,7 +159,9 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
             }
         }
         if (!accepted) {
-            // restore the gradient at the current point for the caller's record
+            // no trial point lowers the loss: at the resolution of FP32 parameters when the predicted
+            // decrease is already tiny against the loss
+            if (dec <= 1e-10 * (std::fabs(L) + 1.0)) out->converged = 1;
             if (launch_newton_trial(th, d, 0.0, v.theta_eval, v.theta_eval64, n, s) != hipSuccess) return DIA_E_HIP;
             break;
         }

@@ -70,7 +70,8 @@ __device__ double chol_block_max(double v, double* sh) {
 
 // A (n x n, row-major, symmetric) -> column k of L stored in row k (A[k*n + i] = L[i][k], i >= k)
 // when factor != 0; then d = -(L L^T)^-1 g.  info[0] = 1 if A was not positive definite,
-// info[1] = -g.d (the Newton decrement squared), info[2] = max|d_i| / max|th_i|.
+// info[1] = -g.d (the Newton decrement squared), info[2] = max|d_i| / max|th_i|,
+// info[3] = max_i |d_i| / (FP32 spacing at th_i).
 __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int n, int factor, const double* g,
                                                                   const double* th, double* d, double* info) {
     __shared__ double col[kMaxTheta];
@@ -107,6 +108,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int
             info[0] = 1.0;
             info[1] = 0.0;
             info[2] = 0.0;
+            info[3] = 0.0;
         }
         return;
     }
@@ -128,20 +130,26 @@ __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int
         for (int i = tid; i < k; i += kCholThreads) col[i] -= A[(long long)i * n + k] * xk;
         __syncthreads();
     }
-    double dec = 0.0, dmax = 0.0, tmax = 0.0;
+    double dec = 0.0, dmax = 0.0, tmax = 0.0, qmax = 0.0;
     for (int i = tid; i < n; i += kCholThreads) {
         d[i] = col[i];
         dec -= g[i] * col[i];
         dmax = fmax(dmax, fabs(col[i]));
         tmax = fmax(tmax, fabs(th[i]));
+        // the step in units of the FP32 spacing at th_i (the parameters are stored in FP32)
+        const float tf = (float)th[i];
+        const double ulp = tf != 0.0f ? ldexp(1.0, ilogbf(tf) - 23) : 1.4e-45;
+        qmax = fmax(qmax, fabs(col[i]) / ulp);
     }
     dec = chol_block_sum(dec, sh);
     dmax = chol_block_max(dmax, sh);
     tmax = chol_block_max(tmax, sh);
+    qmax = chol_block_max(qmax, sh);
     if (tid == 0) {
         info[0] = 0.0;
         info[1] = dec;
         info[2] = tmax > 0.0 ? dmax / tmax : dmax;
+        info[3] = qmax;
     }
 }
 

@@ -122,3 +122,23 @@ def test_fit_batched_rejects_bad_epochs(dia, small_batch):
     with pytest.raises(dia.DIAError) as ex:
         dia.fit_batched(gpu(b.R), bad, b.m, o)
     assert ex.value.status == dia.E_SIZE
+
+
+def test_loss_grad_batched_uneven_full_size_sampled(dia):
+    # the 64-epoch uneven batch (sides 512..2048 against a shared 2048^2 reference, m = 17) in one
+    # persistent launch; the smallest and the largest epochs are checked against the oracle
+    b = sf.config4()
+    m = b.m
+    o, oo = objs(dia, b)
+    th = np.stack([np.r_[e.K_true.ravel() * 0.97, e.B0_true + 1.0] for e in b.epochs]).astype(np.float32)
+    loss, grad = dia.loss_grad_batched(gpu(b.R), epochs_gpu(dia, b), gpu(th), m, o)
+    torch.cuda.synchronize()
+    sides = [e.I.shape[0] for e in b.epochs]
+    for k in (int(np.argmin(sides)), int(np.argmax(sides))):
+        L_ref, g_ref = oracle.loss_grad(crop_R(b, k), b.epochs[k].I, th[k], m, oo)
+        g = grad[k].cpu().double().numpy()
+        eK = np.linalg.norm(g[:-1] - g_ref[:-1]) / np.linalg.norm(g_ref[:-1])
+        eB = abs(g[-1] - g_ref[-1]) / abs(g_ref[-1])
+        print(f"epoch {k} side {sides[k]}: grad rel err dK {eK:.2e} dB0 {eB:.2e}")
+        assert eK <= 1e-5 and eB <= 1e-5
+        assert abs(loss[k].item() - L_ref) <= 2e-6 * abs(L_ref)

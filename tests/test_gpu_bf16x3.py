@@ -134,3 +134,26 @@ def test_bf16x3_rejects_unshared_windows_and_sizes(dia):
         dia.loss_grad_batched(gpu(b2.R), ep2, torch.zeros((2, 122), dtype=torch.float32, device=DEV), 11, o,
                               precision="bf16x3")
     assert ex.value.status == dia.E_ARG
+
+
+def test_loss_grad_bf16x3_full_size_batch_sampled(dia):
+    # the benchmarked launch: 32 epochs of 2048^2 against the shared 2048^2 reference, m = 25;
+    # the first and last epochs are checked against the oracle (direct loops over 4.1 M pixels)
+    b = sf.config5(n_epochs=32)
+    m = b.m
+    o, oo = objs(dia, b)
+    th = np.stack([np.r_[e.K_true.ravel() * 1.02, e.B0_true] for e in b.epochs]).astype(np.float32)
+    ep = [dia.Epoch(I=gpu(e.I)) for e in b.epochs]
+    loss, grad = dia.loss_grad_batched(gpu(b.R), ep, gpu(th), m, o, precision="bf16x3")
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy()
+    grad = grad.cpu().double().numpy()
+    for k in (0, 31):
+        e = b.epochs[k]
+        L_ref, g_ref = oracle.loss_grad(b.R, e.I, th[k], m, oo)
+        gb, lb = bounds(b.R, e.I, th[k], m, oo)
+        err = np.abs(grad[k] - g_ref)
+        print(f"epoch {k}: grad rel err {np.linalg.norm(err) / np.linalg.norm(g_ref):.2e}, "
+              f"worst err / bound {np.max(err / gb):.3f}, loss err {abs(loss[k] - L_ref):.3e} (bound {lb:.3e})")
+        assert np.all(err <= gb)
+        assert abs(loss[k] - L_ref) <= lb
