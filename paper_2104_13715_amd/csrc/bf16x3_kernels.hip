@@ -59,13 +59,14 @@ __device__ __forceinline__ unsigned split_pack(float x) {
     return ((unsigned)__builtin_bit_cast(unsigned short, h) << 16) | __builtin_bit_cast(unsigned short, l);
 }
 
-// 8 packed (hi << 16 | lo) words -> the hi and lo bf16 fragments
+// 8 packed (hi << 16 | lo) words -> the hi and lo bf16 fragments, one byte permute per dword:
+// hi dword k = upper halves of words 2k, 2k+1; lo dword k = their lower halves
 __device__ __forceinline__ void unpack8(const unsigned (&w)[8], bf16x8& hi, bf16x8& lo) {
     u32x4 h, l;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        h[k] = (w[2 * k] >> 16) | (w[2 * k + 1] & 0xFFFF0000u);
-        l[k] = (w[2 * k] & 0xFFFFu) | (w[2 * k + 1] << 16);
+        h[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x07060302u);
+        l[k] = __builtin_amdgcn_perm(w[2 * k + 1], w[2 * k], 0x05040100u);
     }
     hi = __builtin_bit_cast(bf16x8, h);
     lo = __builtin_bit_cast(bf16x8, l);
@@ -85,9 +86,9 @@ struct BfSmem {
     alignas(16) unsigned short Khi[G::NCH * 2 * kEB * 8];
     alignas(16) unsigned short Klo[G::NCH * 2 * kEB * 8];
     alignas(16) unsigned Rw[G::RH * G::RS];
-    // forward results M[epoch][pixel] (float), then g as hi / lo bf16 planes in the same bytes
+    // forward results M[epoch][pixel] (float), then g as hi / lo bf16 planes in each epoch's slot
     alignas(16) unsigned short Gt[2 * kEB * G::PT];
-    alignas(16) short toff[G::TP];  // word offset of tap t in the staged window (0 for padding taps)
+    alignas(16) int toff[G::TP];  // word offset of tap t in the staged window (0 for padding taps)
     const float* Ip[kEB];
     const float* Wp[kEB];
     const float* Fp[kEB];
@@ -96,9 +97,12 @@ struct BfSmem {
     double lsum[kWaves][kEB];  // per-wave FP64 loss of each epoch
 };
 
-// g planes: element (epoch e, pixel p); 8-pixel groups are rotated by e so that the 32 lanes of
-// a backward A-fragment read (one epoch each, same pixels) hit different banks
-__device__ __forceinline__ int gidx(int e, int p, int pt) { return e * pt + (p ^ ((e & 7) << 3)); }
+// g planes: epoch e owns the 4 * pt bytes that held its forward results: hi plane, then lo plane
+// (so that finishing half of the epochs overwrites only their own slots).  8-pixel groups are
+// rotated by e so that the 32 lanes of a backward A-fragment read (one epoch each, same pixels)
+// hit different banks.
+__device__ __forceinline__ int ghi(int e, int p, int pt) { return 2 * e * pt + (p ^ ((e & 7) << 3)); }
+__device__ __forceinline__ int glo(int e, int p, int pt) { return 2 * e * pt + pt + (p ^ ((e & 7) << 3)); }
 
 template <int M>
 __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         sm.Fp[tid] = ok && g.F ? g.F[eg] : nullptr;
         sm.Mp[tid] = ok && g.Mk ? g.Mk[eg] : nullptr;
     }
-    for (int t = tid; t < G::TP; t += kThreads) sm.toff[t] = (short)(t < G::T ? (t / M) * G::RS + t % M : 0);
+    for (int t = tid; t < G::TP; t += kThreads) sm.toff[t] = t < G::T ? (t / M) * G::RS + t % M : 0;
 
     // backward B-fragment base of each owned tap block: tap n = 32 tb + l32 (clamped inside the tap range)
     int nb_off[G::TBW];
@@ -154,8 +158,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     for (int idx = tid; idx < kWaves * kEB; idx += kThreads) (&sm.lsum[0][0])[idx] = 0.0;
 
     float* Ms = reinterpret_cast<float*>(sm.Gt);
-    unsigned short* Ghi = sm.Gt;
-    unsigned short* Glo = sm.Gt + kEB * G::PT;
+    unsigned short* Ghi = sm.Gt;  // both planes, indexed by ghi() / glo()
     const int py = tid / kTC, px = tid % kTC;  // the objective phase: one pixel per thread
 
     for (int t = t_begin; t < t_end; ++t) {
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
             for (int c = 0; c < G::NCH; ++c) {
                 const bf16x8 ah = *reinterpret_cast<const bf16x8*>(sm.Khi + ((c * 2 + q) * kEB + l32) * 8);
                 const bf16x8 al = *reinterpret_cast<const bf16x8*>(sm.Klo + ((c * 2 + q) * kEB + l32) * 8);
-                const short* tp = sm.toff + 16 * c + 8 * q;
+                const int* tp = sm.toff + 16 * c + 8 * q;
                 unsigned wv0[8], wv1[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
@@ -204,47 +207,54 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         }
         __syncthreads();
 
-        // per-pixel objective (FP32); g as hi / lo bf16 planes
+        // per-pixel objective (FP32); g as hi / lo bf16 planes, half of the epochs at a time
         {
-            float mv[kEB], lv[kEB];
-#pragma unroll
-            for (int e = 0; e < kEB; ++e) mv[e] = Ms[e * G::PT + tid];
-            __syncthreads();  // every M value is in registers before the planes overwrite them
             const int y = ty0 + py, x = tx0 + px;
             const bool valid = (y < Hv) && (x < Wv);
             const long long pix = (long long)(y + G::HALF) * g.ldI + (x + G::HALF);
+            constexpr int EH = kEB / 2;
 #pragma unroll
-            for (int e = 0; e < kEB; ++e) {
-                float gv = 0.0f;
-                lv[e] = 0.0f;
-                const float* Ie = sm.Ip[e];
-                if (valid && Ie != nullptr) {
-                    const uint8_t* Me = sm.Mp[e];
-                    if (Me == nullptr || Me[pix] != 0) {
-                        const float* We = sm.Wp[e];
-                        const float* Fe = sm.Fp[e];
-                        pixel_objective(g.obj, Ie[pix], mv[e] + sm.B0[e], We ? We[pix] : 1.0f, Fe ? Fe[pix] : 1.0f,
-                                        lv[e], gv);
+            for (int h = 0; h < 2; ++h) {
+                float mv[EH], lv[EH];
+#pragma unroll
+                for (int k = 0; k < EH; ++k) mv[k] = Ms[(h * EH + k) * G::PT + tid];
+                __syncthreads();  // this half's M values are in registers before its planes overwrite them
+#pragma unroll
+                for (int k = 0; k < EH; ++k) {
+                    const int e = h * EH + k;
+                    float gv = 0.0f;
+                    lv[k] = 0.0f;
+                    const float* Ie = sm.Ip[e];
+                    if (valid && Ie != nullptr) {
+                        const uint8_t* Me = sm.Mp[e];
+                        if (Me == nullptr || Me[pix] != 0) {
+                            const float* We = sm.Wp[e];
+                            const float* Fe = sm.Fp[e];
+                            pixel_objective(g.obj, Ie[pix], mv[k] + sm.B0[e], We ? We[pix] : 1.0f,
+                                            Fe ? Fe[pix] : 1.0f, lv[k], gv);
+                        }
+                    }
+                    const unsigned p = split_pack(gv);
+                    Ghi[ghi(e, tid, G::PT)] = (unsigned short)(p >> 16);
+                    Ghi[glo(e, tid, G::PT)] = (unsigned short)(p & 0xFFFFu);
+                }
+                // the wave's 64 pixel losses of these 16 epochs: halving exchange (lane bit d decides
+                // which half of the remaining epochs a lane keeps), then the last two pairs; lane L ends
+                // with epoch (L >> 2) & 15 of the half
+#pragma unroll
+                for (int d = 32, n = EH / 2; d >= 4; d >>= 1, n >>= 1) {
+                    const bool up = (lane & d) != 0;
+#pragma unroll
+                    for (int i = 0; i < n; ++i) {
+                        const float mine = up ? lv[n + i] : lv[i];
+                        const float other = up ? lv[i] : lv[n + i];
+                        lv[i] = mine + __shfl_xor(other, d);
                     }
                 }
-                const unsigned p = split_pack(gv);
-                Ghi[gidx(e, tid, G::PT)] = (unsigned short)(p >> 16);
-                Glo[gidx(e, tid, G::PT)] = (unsigned short)(p & 0xFFFFu);
+                float tot = lv[0] + __shfl_xor(lv[0], 2);
+                tot += __shfl_xor(tot, 1);
+                if ((lane & 3) == 0) sm.lsum[w][h * EH + ((lane >> 2) & 15)] += (double)tot;
             }
-            // the wave's 64 pixel losses of every epoch: halving exchange (lane bit k decides which half
-            // of the remaining epochs a lane keeps), then the last pair; lane L ends with epoch (L >> 1) & 31
-#pragma unroll
-            for (int d = 32, n = kEB / 2; d >= 2; d >>= 1, n >>= 1) {
-                const bool up = (lane & d) != 0;
-#pragma unroll
-                for (int i = 0; i < n; ++i) {
-                    const float mine = up ? lv[n + i] : lv[i];
-                    const float other = up ? lv[i] : lv[n + i];
-                    lv[i] = mine + __shfl_xor(other, d);
-                }
-            }
-            const float tot = lv[0] + __shfl_xor(lv[0], 1);
-            if ((lane & 1) == 0) sm.lsum[w][(lane >> 1) & 31] += (double)tot;
         }
         __syncthreads();
 
@@ -258,8 +268,8 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
 #pragma unroll 2
             for (int s = 0; s < G::PT / 16; ++s) {
                 const int pofs = s * 16 + 8 * q;  // first pixel of this lane's 8 (tile row s / 2)
-                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(Ghi + gidx(l32, pofs, G::PT));
-                const bf16x8 al = *reinterpret_cast<const bf16x8*>(Glo + gidx(l32, pofs, G::PT));
+                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(Ghi + ghi(l32, pofs, G::PT));
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(Ghi + glo(l32, pofs, G::PT));
                 const int rofs = (s >> 1) * G::RS + (s & 1) * 16;
 #pragma unroll
                 for (int i = 0; i < G::TBW; ++i) {
