@@ -11,7 +11,7 @@
 //   * K of the block (hi / lo) is laid out in LDS in MFMA A-fragment order once per launch.
 //   * Per tile the reference window (with its m-1 halo) is staged as packed (hi << 16 | lo)
 //     words.  Forward: wave w forms rows 2w, 2w+1 of the tile for all 32 epochs; the B fragment
-//     of a lane is 8 taps of one pixel, read through a table of tap offsets.  The per-pixel objective
+//     of a lane is 8 taps of one pixel, read with compile-time offsets.  The per-pixel objective
 //     (FP32, the same formulas as the fused pass) gives g, split into hi / lo bf16 in LDS.
 //   * Backward: the flattened taps (plus a constant-one column that yields dL/dB0) are cut into
 //     blocks of 32; wave w owns blocks w, w+8, ...; a K step is 16 pixels of one tile row.
@@ -51,6 +51,18 @@ struct BfGeo {
     static constexpr int RS = RW | 1;                  // row stride (words)
     static constexpr int PT = kTR * kTC;               // pixels per tile (= threads per workgroup)
     static constexpr int HALF = (M - 1) / 2;
+    // forward gather with compile-time offsets: lanes of half 0 read tap t0 = 16 c + j, lanes of
+    // half 1 tap t0 + 8; their addresses differ by 8 + delta * (RS - M) words (delta = 1 when the
+    // two taps sit in different kernel rows), so each half keeps two base pointers and every
+    // offset is an immediate.  Padding taps (t >= T) read an arbitrary staged word (their K is 0).
+    static constexpr int off(int c, int j) {
+        const int t0 = 16 * c + j;
+        return t0 < T ? (t0 / M) * RS + t0 % M : 0;
+    }
+    static constexpr int delta(int c, int j) {
+        const int t0 = 16 * c + j, t1 = t0 + 8;
+        return (t0 < T && t1 < T) ? (t1 / M - t0 / M) : 0;
+    }
 };
 
 __device__ __forceinline__ unsigned split_pack(float x) {
@@ -88,7 +100,6 @@ struct BfSmem {
     alignas(16) unsigned Rw[G::RH * G::RS];
     // forward results M[epoch][pixel] (float), then g as hi / lo bf16 planes in each epoch's slot
     alignas(16) unsigned short Gt[2 * kEB * G::PT];
-    alignas(16) int toff[G::TP];  // word offset of tap t in the staged window (0 for padding taps)
     const float* Ip[kEB];
     const float* Wp[kEB];
     const float* Fp[kEB];
@@ -139,7 +150,6 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         sm.Fp[tid] = ok && g.F ? g.F[eg] : nullptr;
         sm.Mp[tid] = ok && g.Mk ? g.Mk[eg] : nullptr;
     }
-    for (int t = tid; t < G::TP; t += kThreads) sm.toff[t] = t < G::T ? (t / M) * G::RS + t % M : 0;
 
     // backward B-fragment base of each owned tap block: tap n = 32 tb + l32 (clamped inside the tap range)
     int nb_off[G::TBW];
@@ -179,16 +189,16 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
             f32x16 acc0, acc1;
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.0f;
-            const unsigned* pw = sm.Rw + (2 * w) * G::RS + l32;
-#pragma unroll 2
+            const unsigned* p0 = sm.Rw + (2 * w) * G::RS + l32 + (q ? 8 : 0);
+            const unsigned* p1 = p0 + (q ? G::RS - M : 0);
+#pragma unroll
             for (int c = 0; c < G::NCH; ++c) {
                 const bf16x8 ah = *reinterpret_cast<const bf16x8*>(sm.Khi + ((c * 2 + q) * kEB + l32) * 8);
                 const bf16x8 al = *reinterpret_cast<const bf16x8*>(sm.Klo + ((c * 2 + q) * kEB + l32) * 8);
-                const int* tp = sm.toff + 16 * c + 8 * q;
                 unsigned wv0[8], wv1[8];
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
-                    const unsigned* pj = pw + tp[j];
+                    const unsigned* pj = (G::delta(c, j) ? p1 : p0) + G::off(c, j);
                     wv0[j] = pj[0];
                     wv1[j] = pj[G::RS];
                 }
