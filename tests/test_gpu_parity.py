@@ -118,6 +118,19 @@ def test_model_sampled_at_full_ccd_size(dia):
         assert abs(M[i, j] - ref) <= 2e-6 * scale
 
 
+def test_loss_grad_full_ccd_pair(dia):
+    # the benchmarked launch: the 4096^2 CCD-sized pair, m = 19, the tile shape the fits use;
+    # the whole loss and gradient against the oracle's direct loops (1.2e10 products)
+    p = sf.config3()
+    theta = np.concatenate([p.K_true.ravel() * 1.03, [p.B0_true + 2.0]]).astype(np.float32)
+    o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", p.sigma0_adu, p.gain)
+    L, g = run_loss_grad(dia, p.R, p.I, theta, p.m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(p.R, p.I, theta, p.m, o_or)
+    eK, eB = check_grad(g, g_ref, p.m)
+    check_loss(L, L_ref, p.R, p.I, theta, p.m, o_or)
+    print(f"4096^2: grad rel err dK {eK:.2e} dB0 {eB:.2e}, loss rel err {abs(L - L_ref) / abs(L_ref):.2e}")
+
+
 # ------------------------------------------------------------------------------ loss and gradient
 @pytest.mark.parametrize("rho", RHOS)
 @pytest.mark.parametrize("var", VARS)
