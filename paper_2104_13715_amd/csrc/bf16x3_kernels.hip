@@ -12,13 +12,15 @@
 //   * Per tile the reference window (with its m-1 halo) is staged as packed (hi << 16 | lo)
 //     words.  Forward: wave w forms rows 2w, 2w+1 of the tile for all 32 epochs; the B fragment
 //     of a lane is 8 taps of one pixel, read with compile-time offsets.  The per-pixel objective
-//     (FP32, the same formulas as the fused pass) gives g, split into hi / lo bf16 in LDS.
+//     (FP32 with hardware reciprocal / log; the same formulas as the fused pass) gives g, split
+//     into hi / lo bf16 in LDS.
 //   * Backward: the flattened taps (plus a constant-one column that yields dL/dB0) are cut into
 //     blocks of 32; wave w owns blocks w, w+8, ...; a K step is 16 pixels of one tile row.
 // The lane layouts used (gfx950, 32x32x16): A lane l holds A[l % 32][8 (l / 32) + j],
 // B lane l holds B[8 (l / 32) + j][l % 32], D lane l register r holds
 // D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "api_util.h"
@@ -55,11 +57,11 @@ struct BfGeo {
     // half 1 tap t0 + 8; their addresses differ by 8 + delta * (RS - M) words (delta = 1 when the
     // two taps sit in different kernel rows), so each half keeps two base pointers and every
     // offset is an immediate.  Padding taps (t >= T) read an arbitrary staged word (their K is 0).
-    static constexpr int off(int c, int j) {
+    __host__ __device__ __attribute__((always_inline)) static constexpr int off(int c, int j) {
         const int t0 = 16 * c + j;
         return t0 < T ? (t0 / M) * RS + t0 % M : 0;
     }
-    static constexpr int delta(int c, int j) {
+    __host__ __device__ __attribute__((always_inline)) static constexpr int delta(int c, int j) {
         const int t0 = 16 * c + j, t1 = t0 + 8;
         return (t0 < T && t1 < T) ? (t1 / M - t0 / M) : 0;
     }
@@ -92,6 +94,123 @@ __device__ __forceinline__ f32x16 mfma3(const bf16x8& ah, const bf16x8& al, cons
     return c;
 }
 
+// The per-pixel objective of the split-precision path in FP32 with the hardware reciprocal,
+// reciprocal square root and logarithm (about 1 ulp each: far below the 2^-17 split of g).
+// Same formulas as the fused pass; Gaussian with fixed variance needs no square root at all.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_ln(float x) { return __builtin_amdgcn_logf(x) * 0.69314718056f; }
+__device__ __forceinline__ float fast_ln1p(float q) {
+    // series where 1 + q would round away the information, hardware log2 elsewhere
+    return q < 1e-3f ? q * (1.0f - q * (0.5f - q * (1.0f / 3.0f))) : fast_ln(1.0f + q);
+}
+
+template <int RHO>
+__device__ __forceinline__ void rho_psi_fast(const ObjParams& o, float z, float& rho, float& psi) {
+    if constexpr (RHO == DIA_RHO_GAUSS) {
+        rho = 0.5f * z * z;
+        psi = z;
+    } else if constexpr (RHO == DIA_RHO_HUBER) {
+        const float c = (float)o.c, az = fabsf(z);
+        const bool in = az <= c;
+        rho = in ? 0.5f * z * z : c * (az - 0.5f * c);
+        psi = in ? z : copysignf(c, z);
+    } else {
+        const float c = (float)o.c;
+        const float q = z * z * (float)o.inv_c2;
+        rho = 0.5f * c * c * fast_ln1p(q);
+        psi = z * fast_rcp(1.0f + q);
+    }
+}
+
+// l and g = dl/dM of one pixel (r = I - M), the mode fixed at compile time
+template <int RHO, int VAR>
+__device__ __forceinline__ void pixel_objective_fast(const ObjParams& o, float Iv, float M, float w, float F, float& l,
+                                                     float& g) {
+    const float r = Iv - M;
+    float rho, psi;
+    if constexpr (VAR == DIA_VAR_WEIGHTS) {
+        if constexpr (RHO == DIA_RHO_GAUSS) {
+            l = 0.5f * r * r * w;
+            g = -r * w;
+        } else {
+            const float sw = __builtin_amdgcn_sqrtf(w);
+            rho_psi_fast<RHO>(o, r * sw, rho, psi);
+            l = rho;
+            g = -psi * sw;
+        }
+    } else {
+        constexpr bool model = (VAR == DIA_VAR_CCD_MODEL || VAR == DIA_VAR_EMCCD_MODEL);
+        const float X = model ? M : Iv;
+        const float iF = fast_rcp(F);
+        const float floor_v = (float)o.var_floor;
+        float raw, slope;
+        if constexpr (VAR == DIA_VAR_CCD_DATA || VAR == DIA_VAR_CCD_MODEL) {
+            slope = (float)o.inv_gain * iF;
+            raw = (float)o.s0sq * iF * iF + fmaxf(X, 0.0f) * slope;
+        } else {
+            slope = (float)(o.excess * o.inv_gain) * iF;
+            raw = fmaxf(X, 0.0f) * slope;
+        }
+        const float v = fmaxf(raw, floor_v);
+        if constexpr (!model && RHO == DIA_RHO_GAUSS) {
+            const float iv = fast_rcp(v);
+            l = 0.5f * r * r * iv;
+            g = -r * iv;
+        } else {
+            const float inv_s = fast_rsq(v);
+            rho_psi_fast<RHO>(o, r * inv_s, rho, psi);
+            if constexpr (!model) {
+                l = rho;
+                g = -psi * inv_s;
+            } else {
+                const float dv = (X > 0.0f && raw > floor_v) ? slope : 0.0f;
+                const float inv_v = inv_s * inv_s;
+                l = rho + 0.5f * fast_ln(v);
+                g = -psi * inv_s * (1.0f + 0.5f * r * dv * inv_v) + 0.5f * dv * inv_v;
+            }
+        }
+    }
+}
+
+// calls f(integral_constant<RHO>, integral_constant<VAR>) for the objective's run-time mode
+template <int RHO, class Fn>
+__device__ __forceinline__ void with_var(int var, Fn&& f) {
+    switch (var) {
+        case DIA_VAR_WEIGHTS: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_WEIGHTS>{}); break;
+        case DIA_VAR_CCD_DATA: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_CCD_DATA>{}); break;
+        case DIA_VAR_CCD_MODEL: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_CCD_MODEL>{}); break;
+        case DIA_VAR_EMCCD_DATA: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_EMCCD_DATA>{}); break;
+        default: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_EMCCD_MODEL>{}); break;
+    }
+}
+template <class Fn>
+__device__ __forceinline__ void with_mode(const ObjParams& o, Fn&& f) {
+    switch (o.rho) {
+        case DIA_RHO_GAUSS: with_var<DIA_RHO_GAUSS>(o.var, f); break;
+        case DIA_RHO_HUBER: with_var<DIA_RHO_HUBER>(o.var, f); break;
+        default: with_var<DIA_RHO_CAUCHY>(o.var, f); break;
+    }
+}
+
+// A value that is the same in every lane, read from LDS, moved into scalar registers: the
+// compiler then branches on it with the scalar unit and addresses memory as scalar base +
+// per-lane offset instead of 64-bit vector arithmetic per epoch.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+__device__ __forceinline__ float uniform_f(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(unsigned, x)));
+}
+
 template <int M>
 struct BfSmem {
     using G = BfGeo<M>;
@@ -105,7 +224,7 @@ struct BfSmem {
     const float* Fp[kEB];
     const uint8_t* Mp[kEB];
     float B0[kEB];
-    double lsum[kWaves][kEB];  // per-wave FP64 loss of each epoch
+    double lsum[kEB];          // FP64 loss of each epoch (added to by the wave that owns it)
 };
 
 // g planes: epoch e owns the 4 * pt bytes that held its forward results: hi plane, then lo plane
@@ -165,11 +284,10 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     for (int i = 0; i < G::TBW; ++i)
 #pragma unroll
         for (int r = 0; r < 16; ++r) dk64[i][r] = 0.0;
-    for (int idx = tid; idx < kWaves * kEB; idx += kThreads) (&sm.lsum[0][0])[idx] = 0.0;
+    if (tid < kEB) sm.lsum[tid] = 0.0;
 
     float* Ms = reinterpret_cast<float*>(sm.Gt);
     unsigned short* Ghi = sm.Gt;  // both planes, indexed by ghi() / glo()
-    const int py = tid / kTC, px = tid % kTC;  // the objective phase: one pixel per thread
 
     for (int t = t_begin; t < t_end; ++t) {
         const int ty0 = (t / ntx) * kTR, tx0 = (t % ntx) * kTC;
@@ -217,55 +335,53 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         }
         __syncthreads();
 
-        // per-pixel objective (FP32); g as hi / lo bf16 planes, half of the epochs at a time
-        {
-            const int y = ty0 + py, x = tx0 + px;
-            const bool valid = (y < Hv) && (x < Wv);
-            const long long pix = (long long)(y + G::HALF) * g.ldI + (x + G::HALF);
-            constexpr int EH = kEB / 2;
+        // per-pixel objective (FP32).  Wave w owns epochs w, w + 8, w + 16, w + 24: it takes an
+        // epoch's 512 forward results into registers, requests the epoch's target (and weight /
+        // flat / mask) values of the tile before it uses any, and writes g as hi / lo bf16 planes
+        // into the slot the forward results held (only this wave touches that slot, and its LDS
+        // reads precede its writes).  Lanes outside the valid region read pixel (0, 0) of the
+        // window (always inside) and contribute zero.
+        with_mode(g.obj, [&](auto rho_c, auto var_c) {
+            constexpr int RHO = decltype(rho_c)::value, VAR = decltype(var_c)::value;
+            constexpr int NG = G::PT / 64;  // pixel groups of one lane
+#pragma unroll 1
+            for (int k = 0; k < kEB / kWaves; ++k) {
+                const int e = w + kWaves * k;
+                const float* Ie = uniform_ptr(sm.Ip[e]);
+                const float* We = g.W ? uniform_ptr(sm.Wp[e]) : nullptr;
+                const float* Fe = g.F ? uniform_ptr(sm.Fp[e]) : nullptr;
+                const uint8_t* Me = g.Mk ? uniform_ptr(sm.Mp[e]) : nullptr;
+                const float B0 = uniform_f(sm.B0[e]);
+                float iv[NG], wv[NG], fv[NG], mv[NG];
+                bool ok[NG];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                float mv[EH], lv[EH];
-#pragma unroll
-                for (int k = 0; k < EH; ++k) mv[k] = Ms[(h * EH + k) * G::PT + tid];
-                __syncthreads();  // this half's M values are in registers before its planes overwrite them
-#pragma unroll
-                for (int k = 0; k < EH; ++k) {
-                    const int e = h * EH + k;
-                    float gv = 0.0f;
-                    lv[k] = 0.0f;
-                    const float* Ie = sm.Ip[e];
-                    if (valid && Ie != nullptr) {
-                        const uint8_t* Me = sm.Mp[e];
-                        if (Me == nullptr || Me[pix] != 0) {
-                            const float* We = sm.Wp[e];
-                            const float* Fe = sm.Fp[e];
-                            pixel_objective(g.obj, Ie[pix], mv[k] + sm.B0[e], We ? We[pix] : 1.0f,
-                                            Fe ? Fe[pix] : 1.0f, lv[k], gv);
-                        }
-                    }
-                    const unsigned p = split_pack(gv);
-                    Ghi[ghi(e, tid, G::PT)] = (unsigned short)(p >> 16);
-                    Ghi[glo(e, tid, G::PT)] = (unsigned short)(p & 0xFFFFu);
+                for (int i = 0; i < NG; ++i) {
+                    const int y = ty0 + 2 * i + q, x = tx0 + l32;
+                    const bool valid = (y < Hv) && (x < Wv) && Ie != nullptr;
+                    const long long pix = valid ? (long long)(y + G::HALF) * g.ldI + (x + G::HALF) : 0;
+                    iv[i] = Ie ? global_ptr(Ie)[pix] : 0.0f;
+                    wv[i] = We ? global_ptr(We)[pix] : 1.0f;
+                    fv[i] = Fe ? global_ptr(Fe)[pix] : 1.0f;
+                    ok[i] = valid && (Me == nullptr || global_ptr(Me)[pix] != 0);
                 }
-                // the wave's 64 pixel losses of these 16 epochs: halving exchange (lane bit d decides
-                // which half of the remaining epochs a lane keeps), then the last two pairs; lane L ends
-                // with epoch (L >> 2) & 15 of the half
 #pragma unroll
-                for (int d = 32, n = EH / 2; d >= 4; d >>= 1, n >>= 1) {
-                    const bool up = (lane & d) != 0;
+                for (int i = 0; i < NG; ++i) mv[i] = Ms[e * G::PT + 64 * i + lane];
+                float lsum = 0.0f;
 #pragma unroll
-                    for (int i = 0; i < n; ++i) {
-                        const float mine = up ? lv[n + i] : lv[i];
-                        const float other = up ? lv[i] : lv[n + i];
-                        lv[i] = mine + __shfl_xor(other, d);
-                    }
+                for (int i = 0; i < NG; ++i) {
+                    float l, gv;
+                    pixel_objective_fast<RHO, VAR>(g.obj, iv[i], mv[i] + B0, wv[i], fv[i], l, gv);
+                    lsum += ok[i] ? l : 0.0f;
+                    const unsigned pk = split_pack(ok[i] ? gv : 0.0f);
+                    Ghi[ghi(e, 64 * i + lane, G::PT)] = (unsigned short)(pk >> 16);
+                    Ghi[glo(e, 64 * i + lane, G::PT)] = (unsigned short)(pk & 0xFFFFu);
                 }
-                float tot = lv[0] + __shfl_xor(lv[0], 2);
-                tot += __shfl_xor(tot, 1);
-                if ((lane & 3) == 0) sm.lsum[w][h * EH + ((lane >> 2) & 15)] += (double)tot;
+                double d = (double)lsum;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o);
+                if (lane == 0) sm.lsum[e] += d;
             }
-        }
+        });
         __syncthreads();
 
         // backward: dK[32 epochs x 32 taps] per owned tap block, K steps of 16 pixels
@@ -324,9 +440,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     __syncthreads();
     if (tid < kEB) {
         const int eg = eb * kEB + tid;
-        double sl = 0.0;
-        for (int k = 0; k < kWaves; ++k) sl += sm.lsum[k][tid];
-        if (eg < g.n_ep) g.partial[((long long)eg * g.wpb + wi) * npp + G::T + 1] = sl;
+        if (eg < g.n_ep) g.partial[((long long)eg * g.wpb + wi) * npp + G::T + 1] = sm.lsum[tid];
     }
 }
 
