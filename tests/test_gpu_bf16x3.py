@@ -87,6 +87,44 @@ def test_loss_grad_bf16x3_matches_oracle(dia, m, side, n, rho):
     print(f"m={m} n={n}: worst error / bound {worst:.3f}")
 
 
+MODES = [(r, v) for r in ("gauss", "huber", "cauchy")
+         for v in ("weights", "ccd_data", "ccd_model", "emccd_data", "emccd_model")]
+
+
+@pytest.mark.parametrize("rho,var", MODES)
+def test_loss_grad_bf16x3_every_objective_mode(dia, rho, var):
+    # every (rho, sigma source) pair; epoch 0 carries a flat field, epoch 1 a bad-pixel mask,
+    # epoch 2 both, epoch 3 neither (null entries beside non-null ones in the same launch)
+    m, side, n = 9, 76, 4
+    b = shared_batch(n, m, side, 300 + 7 * MODES.index((rho, var)))
+    rng = np.random.default_rng(11)
+    c = {"gauss": 1.345, "huber": 1.345, "cauchy": 2.3849}[rho]
+    th = np.stack([oracle.init_theta(e.I, m) * np.r_[np.full(m * m, 0.97), 1.0] for e in b.epochs]).astype(np.float32)
+    L_ref, g_ref, gbs, lbs, ep = [], [], [], [], []
+    for k, e in enumerate(b.epochs):
+        flat = rng.uniform(0.9, 1.1, e.I.shape).astype(np.float32) if k in (0, 2) else None
+        mask = (rng.random(e.I.shape) > 0.1).astype(np.uint8) if k in (1, 2) else None
+        w = None
+        if var == "weights":
+            w = (1.0 / np.maximum(b.sigma0_adu ** 2 + np.maximum(e.I, 0) / b.gain, 1.0)).astype(np.float32)
+        oo = oracle.Objective(rho=rho, var=var, sigma0=b.sigma0_adu, gain=b.gain, c=c, weights=w, flat=flat,
+                              mask=mask)
+        Lr, gr = oracle.loss_grad(b.R, e.I, th[k], m, oo)
+        gb, lb = bounds(b.R, e.I, th[k], m, oo)
+        L_ref.append(Lr), g_ref.append(gr), gbs.append(gb), lbs.append(lb)
+        ep.append(dia.Epoch(I=gpu(e.I), weights=None if w is None else gpu(w),
+                            flat=None if flat is None else gpu(flat),
+                            mask=None if mask is None else gpu(mask, torch.uint8)))
+    o = dia.Objective(rho=rho, var=var, sigma0=b.sigma0_adu, gain=b.gain, c=c)
+    loss, grad = dia.loss_grad_batched(gpu(b.R), ep, gpu(th), m, o, precision="bf16x3")
+    torch.cuda.synchronize()
+    loss, grad = loss.cpu().numpy(), grad.cpu().double().numpy()
+    for k in range(n):
+        err = np.abs(grad[k] - g_ref[k])
+        assert np.all(err <= gbs[k]), (k, float(np.max(err / gbs[k])))
+        assert abs(loss[k] - L_ref[k]) <= lbs[k], (k, loss[k], L_ref[k], lbs[k])
+
+
 def test_bf16x3_agrees_with_fp32_path(dia):
     m, side, n = 17, 140, 9
     b = shared_batch(n, m, side, 91)
