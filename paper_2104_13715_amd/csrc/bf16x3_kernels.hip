@@ -7,11 +7,12 @@
 // parts (products hi*hi + hi*lo + lo*hi: about 16 significant bits per operand, 2^-17 relative
 // representation error).  MFMA accumulates one tile in FP32; tile results are added in FP64.
 //
-// Workgroup = 8 waves, one block of 32 epochs, a contiguous range of 16 x 32 pixel tiles.
+// Workgroup = 8 waves, one block of 32 epochs, a contiguous range of 8 x 64 pixel tiles.
 //   * K of the block (hi / lo) is laid out in LDS in MFMA A-fragment order once per launch.
 //   * Per tile the reference window (with its m-1 halo) is staged as packed (hi << 16 | lo)
-//     words.  Forward: wave w forms rows 2w, 2w+1 of the tile for all 32 epochs; the B fragment
-//     of a lane is 8 taps of one pixel, read with compile-time offsets.  The per-pixel objective
+//     words.  Forward: wave w forms row w of the tile (two blocks of 32 pixels, 32 words apart,
+//     so a lane's paired read touches disjoint banks) for all 32 epochs; the B fragment of a
+//     lane is 8 taps of one pixel, read with compile-time offsets.  The per-pixel objective
 //     (FP32 with hardware reciprocal / log; the same formulas as the fused pass) gives g, split
 //     into hi / lo bf16 in LDS.
 //   * Backward: the flattened taps (plus a constant-one column that yields dL/dB0) are cut into
@@ -35,10 +36,10 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kEB = 32;             // epochs per block
 constexpr int kWaves = 8;
-constexpr int kTR = 2 * kWaves;     // tile rows (2 per wave)
-constexpr int kTC = 32;             // tile columns (one pixel per lane)
+constexpr int kTR = kWaves;         // tile rows (one per wave in the forward pass)
+constexpr int kTC = 64;             // tile columns (two MFMA blocks of 32)
 constexpr int kThreads = 64 * kWaves;
-static_assert(kThreads == 2 * kWaves * 32, "one thread per tile pixel in the objective phase");
+static_assert(kTR * kTC == 8 * 64, "a wave covers the tile with eight 64-pixel groups (in pairs) in the objective phase");
 constexpr int kTargetGroups = 256;  // one workgroup per CU on MI355X
 
 template <int M>
@@ -51,6 +52,7 @@ struct BfGeo {
     static constexpr int RH = kTR + M - 1;             // staged reference rows
     static constexpr int RW = kTC + M - 1 + 8;         // staged columns (+8: padded-tap reads stay inside)
     static constexpr int RS = RW | 1;                  // row stride (words)
+    static_assert(kTC == 64, "the two forward column blocks are 32 words apart: disjoint LDS banks");
     static constexpr int PT = kTR * kTC;               // pixels per tile (= threads per workgroup)
     static constexpr int HALF = (M - 1) / 2;
     // forward gather with compile-time offsets: lanes of half 0 read tap t0 = 16 c + j, lanes of
@@ -71,6 +73,16 @@ __device__ __forceinline__ unsigned split_pack(float x) {
     const __bf16 h = (__bf16)x;
     const __bf16 l = (__bf16)(x - (float)h);
     return ((unsigned)__builtin_bit_cast(unsigned short, h) << 16) | __builtin_bit_cast(unsigned short, l);
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// two values split at once: hi = (hi(a) | hi(b) << 16), lo likewise (round to nearest even)
+__device__ __forceinline__ void split2(float a, float b, unsigned& hi, unsigned& lo) {
+    const f32x2 v = {a, b};
+    hi = __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+    const f32x2 h = {__builtin_bit_cast(float, hi << 16), __builtin_bit_cast(float, hi & 0xFFFF0000u)};
+    lo = __builtin_bit_cast(unsigned, __builtin_convertvector(v - h, bf16x2));
 }
 
 // 8 packed (hi << 16 | lo) words -> the hi and lo bf16 fragments, one byte permute per dword:
@@ -123,16 +135,18 @@ __device__ __forceinline__ void rho_psi_fast(const ObjParams& o, float z, float&
     }
 }
 
-// l and g = dl/dM of one pixel (r = I - M), the mode fixed at compile time
-template <int RHO, int VAR>
+// l and g = dl/dM of one pixel (r = I - M), the mode fixed at compile time; HAS_F = false
+// means no flat field (F = 1), which drops a reciprocal and three products from the variance.
+template <int RHO, int VAR, bool HAS_F>
 __device__ __forceinline__ void pixel_objective_fast(const ObjParams& o, float Iv, float M, float w, float F, float& l,
                                                      float& g) {
     const float r = Iv - M;
     float rho, psi;
     if constexpr (VAR == DIA_VAR_WEIGHTS) {
         if constexpr (RHO == DIA_RHO_GAUSS) {
-            l = 0.5f * r * r * w;
-            g = -r * w;
+            const float t = r * w;
+            l = 0.5f * r * t;
+            g = -t;
         } else {
             const float sw = __builtin_amdgcn_sqrtf(w);
             rho_psi_fast<RHO>(o, r * sw, rho, psi);
@@ -141,22 +155,23 @@ __device__ __forceinline__ void pixel_objective_fast(const ObjParams& o, float I
         }
     } else {
         constexpr bool model = (VAR == DIA_VAR_CCD_MODEL || VAR == DIA_VAR_EMCCD_MODEL);
+        constexpr bool ccd = (VAR == DIA_VAR_CCD_DATA || VAR == DIA_VAR_CCD_MODEL);
         const float X = model ? M : Iv;
-        const float iF = fast_rcp(F);
         const float floor_v = (float)o.var_floor;
         float raw, slope;
-        if constexpr (VAR == DIA_VAR_CCD_DATA || VAR == DIA_VAR_CCD_MODEL) {
-            slope = (float)o.inv_gain * iF;
-            raw = (float)o.s0sq * iF * iF + fmaxf(X, 0.0f) * slope;
+        if constexpr (HAS_F) {
+            const float iF = fast_rcp(F);
+            slope = (float)(ccd ? o.inv_gain : o.excess * o.inv_gain) * iF;
+            raw = ccd ? (float)o.s0sq * iF * iF + fmaxf(X, 0.0f) * slope : fmaxf(X, 0.0f) * slope;
         } else {
-            slope = (float)(o.excess * o.inv_gain) * iF;
-            raw = fmaxf(X, 0.0f) * slope;
+            slope = (float)(ccd ? o.inv_gain : o.excess * o.inv_gain);
+            raw = ccd ? fmaf(fmaxf(X, 0.0f), slope, (float)o.s0sq) : fmaxf(X, 0.0f) * slope;
         }
         const float v = fmaxf(raw, floor_v);
         if constexpr (!model && RHO == DIA_RHO_GAUSS) {
-            const float iv = fast_rcp(v);
-            l = 0.5f * r * r * iv;
-            g = -r * iv;
+            const float t = r * fast_rcp(v);
+            l = 0.5f * r * t;
+            g = -t;
         } else {
             const float inv_s = fast_rsq(v);
             rho_psi_fast<RHO>(o, r * inv_s, rho, psi);
@@ -173,23 +188,33 @@ __device__ __forceinline__ void pixel_objective_fast(const ObjParams& o, float I
     }
 }
 
-// calls f(integral_constant<RHO>, integral_constant<VAR>) for the objective's run-time mode
+// calls f(integral_constant<RHO>, integral_constant<VAR>, integral_constant<HAS_F>) for the
+// objective's run-time mode (the weights mode never reads a flat field)
+template <int RHO, int VAR, class Fn>
+__device__ __forceinline__ void with_flat(bool has_f, Fn&& f) {
+    using R = std::integral_constant<int, RHO>;
+    using V = std::integral_constant<int, VAR>;
+    if (VAR != DIA_VAR_WEIGHTS && has_f)
+        f(R{}, V{}, std::integral_constant<bool, VAR != DIA_VAR_WEIGHTS>{});
+    else
+        f(R{}, V{}, std::false_type{});
+}
 template <int RHO, class Fn>
-__device__ __forceinline__ void with_var(int var, Fn&& f) {
+__device__ __forceinline__ void with_var(int var, bool has_f, Fn&& f) {
     switch (var) {
-        case DIA_VAR_WEIGHTS: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_WEIGHTS>{}); break;
-        case DIA_VAR_CCD_DATA: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_CCD_DATA>{}); break;
-        case DIA_VAR_CCD_MODEL: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_CCD_MODEL>{}); break;
-        case DIA_VAR_EMCCD_DATA: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_EMCCD_DATA>{}); break;
-        default: f(std::integral_constant<int, RHO>{}, std::integral_constant<int, DIA_VAR_EMCCD_MODEL>{}); break;
+        case DIA_VAR_WEIGHTS: with_flat<RHO, DIA_VAR_WEIGHTS>(has_f, f); break;
+        case DIA_VAR_CCD_DATA: with_flat<RHO, DIA_VAR_CCD_DATA>(has_f, f); break;
+        case DIA_VAR_CCD_MODEL: with_flat<RHO, DIA_VAR_CCD_MODEL>(has_f, f); break;
+        case DIA_VAR_EMCCD_DATA: with_flat<RHO, DIA_VAR_EMCCD_DATA>(has_f, f); break;
+        default: with_flat<RHO, DIA_VAR_EMCCD_MODEL>(has_f, f); break;
     }
 }
 template <class Fn>
-__device__ __forceinline__ void with_mode(const ObjParams& o, Fn&& f) {
+__device__ __forceinline__ void with_mode(const ObjParams& o, bool has_f, Fn&& f) {
     switch (o.rho) {
-        case DIA_RHO_GAUSS: with_var<DIA_RHO_GAUSS>(o.var, f); break;
-        case DIA_RHO_HUBER: with_var<DIA_RHO_HUBER>(o.var, f); break;
-        default: with_var<DIA_RHO_CAUCHY>(o.var, f); break;
+        case DIA_RHO_GAUSS: with_var<DIA_RHO_GAUSS>(o.var, has_f, f); break;
+        case DIA_RHO_HUBER: with_var<DIA_RHO_HUBER>(o.var, has_f, f); break;
+        default: with_var<DIA_RHO_CAUCHY>(o.var, has_f, f); break;
     }
 }
 
@@ -207,8 +232,44 @@ template <class T>
 __device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
     return (const __attribute__((address_space(1))) T*)p;
 }
+// Raw buffer view of the bytes from a (wave-uniform) base on: a load is then the scalar
+// descriptor + one 32-bit per-lane byte offset, with no 64-bit address arithmetic per lane.
+// Callers keep their offsets inside the array they address.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_view(const char* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(base), (short)0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ float view_f32(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ unsigned view_u8(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, 0);
+}
 __device__ __forceinline__ float uniform_f(float x) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(unsigned, x)));
+}
+
+// Sum of a double over the 64 lanes of a wave (the same value in every lane): DPP exchanges
+// inside each row of 16 lanes (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_ror 4, row_ror 8)
+// leave every lane with its row's sum; the four row sums are read out and added.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x124>(v);
+    v += dpp_f64<0x128>(v);
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
 template <int M>
@@ -227,12 +288,11 @@ struct BfSmem {
     double lsum[kEB];          // FP64 loss of each epoch (added to by the wave that owns it)
 };
 
-// g planes: epoch e owns the 4 * pt bytes that held its forward results: hi plane, then lo plane
-// (so that finishing half of the epochs overwrites only their own slots).  8-pixel groups are
-// rotated by e so that the 32 lanes of a backward A-fragment read (one epoch each, same pixels)
-// hit different banks.
-__device__ __forceinline__ int ghi(int e, int p, int pt) { return 2 * e * pt + (p ^ ((e & 7) << 3)); }
-__device__ __forceinline__ int glo(int e, int p, int pt) { return 2 * e * pt + pt + (p ^ ((e & 7) << 3)); }
+// g planes: epoch e owns the 4 * pt bytes that held its forward results: hi plane, then lo plane.
+// 8-pixel groups are permuted by (e mod 16) so that the 16 lanes served together by a backward
+// A-fragment read (one epoch each, the same 8 pixels, 16 bytes per lane) cover all 64 banks.
+__device__ __forceinline__ int ghi(int e, int p, int pt) { return 2 * e * pt + (p ^ ((e & 15) << 3)); }
+__device__ __forceinline__ int glo(int e, int p, int pt) { return 2 * e * pt + pt + (p ^ ((e & 15) << 3)); }
 
 template <int M>
 __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
@@ -289,25 +349,45 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     float* Ms = reinterpret_cast<float*>(sm.Gt);
     unsigned short* Ghi = sm.Gt;  // both planes, indexed by ghi() / glo()
 
+    // The reference window of a tile (RH x RW words; this thread's are words tid + k * kThreads)
+    // is fetched into registers one tile ahead, while the previous tile's backward pass runs, and
+    // written to LDS at the top of the tile.  Words outside the reference read its last row /
+    // column (always inside) and are replaced by zero.
+    constexpr int SPT = (G::RH * G::RW + kThreads - 1) / kThreads;
+    float rpre[SPT];
+    auto fetch_R = [&](int t) {
+        const int ty0 = (t / ntx) * kTR, tx0 = (t % ntx) * kTC;
+        const char* Rb = uniform_ptr(reinterpret_cast<const char*>(g.R + (long long)ty0 * g.ldR + tx0));
+        const int rmax = min(g.rows - 1 - ty0, G::RH - 1), cmax = min(g.cols - 1 - tx0, G::RW - 1);
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int idx = tid + k * kThreads;
+            const int r = idx / G::RW, c = idx - r * G::RW;
+            const float v = view_f32(raw_view(Rb), (unsigned)(min(r, rmax) * g.ldR + min(c, cmax)) * 4u);
+            rpre[k] = (r <= rmax && c <= cmax) ? v : 0.0f;
+        }
+    };
+    if (t_begin < t_end) fetch_R(t_begin);
+
     for (int t = t_begin; t < t_end; ++t) {
         const int ty0 = (t / ntx) * kTR, tx0 = (t % ntx) * kTC;
         // keep the per-epoch tables in LDS (not hoisted into registers across tiles)
         asm volatile("" ::: "memory");
         __syncthreads();  // previous tile's readers are done (and, first time, the tables are visible)
-        for (int idx = tid; idx < G::RH * G::RW; idx += kThreads) {
+#pragma unroll
+        for (int k = 0; k < SPT; ++k) {
+            const int idx = tid + k * kThreads;
             const int r = idx / G::RW, c = idx - r * G::RW;
-            const int gr = ty0 + r, gc = tx0 + c;
-            const float v = (gr < g.rows && gc < g.cols) ? g.R[(long long)gr * g.ldR + gc] : 0.0f;
-            sm.Rw[r * G::RS + c] = split_pack(v);
+            if (idx < G::RH * G::RW) sm.Rw[r * G::RS + c] = split_pack(rpre[k]);
         }
         __syncthreads();
 
-        // forward: rows 2w, 2w+1 of the tile, pixel l32, all 32 epochs
+        // forward: row w of the tile, pixels l32 and 32 + l32, all 32 epochs
         {
             f32x16 acc0, acc1;
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.0f;
-            const unsigned* p0 = sm.Rw + (2 * w) * G::RS + l32 + (q ? 8 : 0);
+            const unsigned* p0 = sm.Rw + w * G::RS + l32 + (q ? 8 : 0);
             const unsigned* p1 = p0 + (q ? G::RS - M : 0);
 #pragma unroll
             for (int c = 0; c < G::NCH; ++c) {
@@ -318,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
                 for (int j = 0; j < 8; ++j) {
                     const unsigned* pj = (G::delta(c, j) ? p1 : p0) + G::off(c, j);
                     wv0[j] = pj[0];
-                    wv1[j] = pj[G::RS];
+                    wv1[j] = pj[32];
                 }
                 bf16x8 bh, bl;
                 unpack8(wv0, bh, bl);
@@ -329,8 +409,8 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int el = 8 * (r >> 2) + 4 * q + (r & 3);
-                Ms[el * G::PT + (2 * w) * kTC + l32] = acc0[r];
-                Ms[el * G::PT + (2 * w + 1) * kTC + l32] = acc1[r];
+                Ms[el * G::PT + w * kTC + l32] = acc0[r];
+                Ms[el * G::PT + w * kTC + 32 + l32] = acc1[r];
             }
         }
         __syncthreads();
@@ -339,50 +419,111 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         // epoch's 512 forward results into registers, requests the epoch's target (and weight /
         // flat / mask) values of the tile before it uses any, and writes g as hi / lo bf16 planes
         // into the slot the forward results held (only this wave touches that slot, and its LDS
-        // reads precede its writes).  Lanes outside the valid region read pixel (0, 0) of the
-        // window (always inside) and contribute zero.
-        with_mode(g.obj, [&](auto rho_c, auto var_c) {
-            constexpr int RHO = decltype(rho_c)::value, VAR = decltype(var_c)::value;
-            constexpr int NG = G::PT / 64;  // pixel groups of one lane
-#pragma unroll 1
-            for (int k = 0; k < kEB / kWaves; ++k) {
-                const int e = w + kWaves * k;
-                const float* Ie = uniform_ptr(sm.Ip[e]);
-                const float* We = g.W ? uniform_ptr(sm.Wp[e]) : nullptr;
-                const float* Fe = g.F ? uniform_ptr(sm.Fp[e]) : nullptr;
-                const uint8_t* Me = g.Mk ? uniform_ptr(sm.Mp[e]) : nullptr;
-                const float B0 = uniform_f(sm.B0[e]);
-                float iv[NG], wv[NG], fv[NG], mv[NG];
-                bool ok[NG];
+        // reads precede its writes).  Lane l, group i is pixel (row i, column l) of the tile; its
+        // byte offset from the tile's first pixel is the same in every epoch (lanes past a ragged
+        // edge read the nearest pixel inside and contribute zero).
+        {
+            constexpr int NG = G::PT / 64;
+            unsigned ob[NG];
+            unsigned vmask = 0u;
+            {
+                const int x = tx0 + lane, xc = min(x, Wv - 1) - tx0;
 #pragma unroll
                 for (int i = 0; i < NG; ++i) {
-                    const int y = ty0 + 2 * i + q, x = tx0 + l32;
-                    const bool valid = (y < Hv) && (x < Wv) && Ie != nullptr;
-                    const long long pix = valid ? (long long)(y + G::HALF) * g.ldI + (x + G::HALF) : 0;
-                    iv[i] = Ie ? global_ptr(Ie)[pix] : 0.0f;
-                    wv[i] = We ? global_ptr(We)[pix] : 1.0f;
-                    fv[i] = Fe ? global_ptr(Fe)[pix] : 1.0f;
-                    ok[i] = valid && (Me == nullptr || global_ptr(Me)[pix] != 0);
+                    const int y = ty0 + i, yc = min(y, Hv - 1) - ty0;
+                    vmask |= (y < Hv && x < Wv) ? (1u << i) : 0u;
+                    ob[i] = (unsigned)(yc * g.ldI + xc) * 4u;
                 }
-#pragma unroll
-                for (int i = 0; i < NG; ++i) mv[i] = Ms[e * G::PT + 64 * i + lane];
-                float lsum = 0.0f;
-#pragma unroll
-                for (int i = 0; i < NG; ++i) {
-                    float l, gv;
-                    pixel_objective_fast<RHO, VAR>(g.obj, iv[i], mv[i] + B0, wv[i], fv[i], l, gv);
-                    lsum += ok[i] ? l : 0.0f;
-                    const unsigned pk = split_pack(ok[i] ? gv : 0.0f);
-                    Ghi[ghi(e, 64 * i + lane, G::PT)] = (unsigned short)(pk >> 16);
-                    Ghi[glo(e, 64 * i + lane, G::PT)] = (unsigned short)(pk & 0xFFFFu);
-                }
-                double d = (double)lsum;
-#pragma unroll
-                for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o);
-                if (lane == 0) sm.lsum[e] += d;
             }
-        });
+            const long long tile0 = (long long)(ty0 + G::HALF) * g.ldI + (tx0 + G::HALF);
+            with_mode(g.obj, g.F != nullptr, [&](auto rho_c, auto var_c, auto flat_c) {
+                constexpr int RHO = decltype(rho_c)::value, VAR = decltype(var_c)::value;
+                constexpr bool HAS_F = decltype(flat_c)::value;
+                // target values (and B0) one epoch ahead: epoch k + 1's loads are in flight while
+                // epoch k is computed (epochs past the batch read epoch 0 and count nothing)
+                float inext[NG], b0_next;
+                bool live_next;
+                auto fetch_I = [&](int k) {
+                    const int e = w + kWaves * k;
+                    const float* Ie = uniform_ptr(sm.Ip[e]);
+                    live_next = Ie != nullptr;
+                    b0_next = uniform_f(sm.B0[e]);
+                    const char* Ib = uniform_ptr(reinterpret_cast<const char*>((Ie ? Ie : uniform_ptr(sm.Ip[0])) + tile0));
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) inext[i] = view_f32(raw_view(Ib), ob[i]);
+                };
+                fetch_I(0);
+#pragma unroll 1
+                for (int k = 0; k < kEB / kWaves; ++k) {
+                    const int e = w + kWaves * k;
+                    const bool live = live_next;
+                    const float B0 = b0_next;
+                    float iv[NG], wv[NG], fv[NG], mv[NG];
+                    bool ok[NG];
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) ok[i] = live && ((vmask >> i) & 1u);
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) iv[i] = inext[i];
+                    if (k + 1 < kEB / kWaves) fetch_I(k + 1);
+                    const float* We = (live && g.W) ? uniform_ptr(sm.Wp[e]) : nullptr;
+                    if (We) {
+                        const char* Wb = uniform_ptr(reinterpret_cast<const char*>(We + tile0));
+#pragma unroll
+                        for (int i = 0; i < NG; ++i) wv[i] = view_f32(raw_view(Wb), ob[i]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < NG; ++i) wv[i] = 1.0f;
+                    }
+                    const float* Fe = (HAS_F && live) ? uniform_ptr(sm.Fp[e]) : nullptr;
+                    if (Fe) {
+                        const char* Fb = uniform_ptr(reinterpret_cast<const char*>(Fe + tile0));
+#pragma unroll
+                        for (int i = 0; i < NG; ++i) fv[i] = view_f32(raw_view(Fb), ob[i]);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < NG; ++i) fv[i] = 1.0f;
+                    }
+                    const uint8_t* Me = (live && g.Mk) ? uniform_ptr(sm.Mp[e]) : nullptr;
+                    if (Me) {
+                        const char* Mb = uniform_ptr(reinterpret_cast<const char*>(Me + tile0));
+#pragma unroll
+                        for (int i = 0; i < NG; ++i)
+                            ok[i] = ok[i] & (view_u8(raw_view(Mb), ob[i] >> 2) != 0);  // offsets always inside
+                    }
+#pragma unroll
+                    for (int i = 0; i < NG; ++i) mv[i] = Ms[e * G::PT + 64 * i + lane];
+                    // ghi(e, 64 i + lane): the permutation flips bit 6 of the pixel index (the
+                    // group's parity) when (e mod 16) >= 8, so even and odd groups get their own base
+                    const int rot = (e & 15) << 3, flip = rot >> 6;
+                    unsigned short* hb = Ghi + 2 * e * G::PT + (lane ^ (rot & 63));
+                    unsigned short* hb_even = hb + 64 * flip;
+                    unsigned short* hb_odd = hb - 64 * flip;
+                    float lsum = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < NG; i += 2) {
+                        float l0, g0, l1, g1;
+                        pixel_objective_fast<RHO, VAR, HAS_F>(g.obj, iv[i], mv[i] + B0, wv[i], fv[i], l0, g0);
+                        pixel_objective_fast<RHO, VAR, HAS_F>(g.obj, iv[i + 1], mv[i + 1] + B0, wv[i + 1], fv[i + 1],
+                                                              l1, g1);
+                        lsum += ok[i] ? l0 : 0.0f;
+                        lsum += ok[i + 1] ? l1 : 0.0f;
+                        unsigned hi, lo;
+                        split2(ok[i] ? g0 : 0.0f, ok[i + 1] ? g1 : 0.0f, hi, lo);
+                        unsigned short* h0 = hb_even + 64 * i;
+                        unsigned short* h1 = hb_odd + 64 * (i + 1);
+                        h0[0] = (unsigned short)hi;
+                        h0[G::PT] = (unsigned short)lo;
+                        h1[0] = (unsigned short)(hi >> 16);
+                        h1[G::PT] = (unsigned short)(lo >> 16);
+                    }
+                    const double d = wave_sum_f64((double)lsum);
+                    if (lane == 0) sm.lsum[e] += d;
+                }
+            });
+        }
         __syncthreads();
+
+        if (t + 1 < t_end) fetch_R(t + 1);
 
         // backward: dK[32 epochs x 32 taps] per owned tap block, K steps of 16 pixels
         {
@@ -393,10 +534,10 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
                 for (int r = 0; r < 16; ++r) accb[i][r] = 0.0f;
 #pragma unroll 2
             for (int s = 0; s < G::PT / 16; ++s) {
-                const int pofs = s * 16 + 8 * q;  // first pixel of this lane's 8 (tile row s / 2)
+                const int pofs = s * 16 + 8 * q;  // first pixel of this lane's 8 (tile row s / 4)
                 const bf16x8 ah = *reinterpret_cast<const bf16x8*>(Ghi + ghi(l32, pofs, G::PT));
                 const bf16x8 al = *reinterpret_cast<const bf16x8*>(Ghi + glo(l32, pofs, G::PT));
-                const int rofs = (s >> 1) * G::RS + (s & 1) * 16;
+                const int rofs = (s >> 2) * G::RS + (s & 3) * 16;
 #pragma unroll
                 for (int i = 0; i < G::TBW; ++i) {
                     const int tb = w + kWaves * i;
@@ -472,6 +613,8 @@ size_t bf16x3_scratch_bytes(int, int n_ep) { return align_up(4 * sizeof(void*) *
 
 int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m) {
     if (!bf16x3_supported(m)) return DIA_E_ARG;
+    // per-pixel byte offsets inside a tile (8 rows) are 32-bit
+    if ((long long)x.ld * 4 * (kTR + 1) >= (1LL << 32)) return DIA_E_SIZE;
     if (x.rows != first.rows || x.cols != first.cols || x.ld != first.ld) return DIA_E_SIZE;
     if (x.ref_row0 != first.ref_row0 || x.ref_col0 != first.ref_col0) return DIA_E_SIZE;
     return DIA_OK;
@@ -479,6 +622,8 @@ int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m) {
 
 int bf16x3_prepare(char* scratch, const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
                    const float* theta0, long long theta_stride, double* partial, hipStream_t s, Bf16x3Args* out) {
+    // byte offsets of a staged reference window (kTR + m - 1 rows) are 32-bit
+    if ((long long)R.ld * 4 * (kTR + m) >= (1LL << 32)) return DIA_E_SIZE;
     std::vector<const void*> ptrs(4 * (size_t)n);
     bool any_w = false, any_f = false, any_m = false;
     for (int e = 0; e < n; ++e) {
