@@ -15,8 +15,8 @@
 //     lane is 8 taps of one pixel, read with compile-time offsets.  The per-pixel objective
 //     (FP32 with hardware reciprocal / log; the same formulas as the fused pass) gives g, split
 //     into hi / lo bf16 in LDS.
-//   * Backward: the flattened taps (plus a constant-one column that yields dL/dB0) are cut into
-//     blocks of 32; wave w owns blocks w, w+8, ...; a K step is 16 pixels of one tile row.
+//   * Backward: the flattened taps are cut into blocks of 32; wave w owns blocks w, w+8, ...; a
+//     K step is 16 pixels of one tile row.  dL/dB0 = sum of g is added up in the objective phase.
 // The lane layouts used (gfx950, 32x32x16): A lane l holds A[l % 32][8 (l / 32) + j],
 // B lane l holds B[8 (l / 32) + j][l % 32], D lane l register r holds
 // D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
@@ -45,7 +45,7 @@ constexpr int kTargetGroups = 256;  // one workgroup per CU on MI355X
 template <int M>
 struct BfGeo {
     static constexpr int T = M * M;
-    static constexpr int TP = (T + 1 + 31) / 32 * 32;  // taps + the B0 column, in blocks of 32
+    static constexpr int TP = (T + 31) / 32 * 32;      // taps in blocks of 32 (padding taps: K = 0)
     static constexpr int NCH = TP / 16;                // forward K steps (16 taps)
     static constexpr int NTB = TP / 32;                // backward tap blocks
     static constexpr int TBW = (NTB + kWaves - 1) / kWaves;
@@ -286,6 +286,7 @@ struct BfSmem {
     const uint8_t* Mp[kEB];
     float B0[kEB];
     double lsum[kEB];          // FP64 loss of each epoch (added to by the wave that owns it)
+    double gsum[kEB];          // FP64 dL/dB0 = sum of g of each epoch (likewise)
 };
 
 // g planes: epoch e owns the 4 * pt bytes that held its forward results: hi plane, then lo plane.
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     }
 
     // backward B-fragment base of each owned tap block: tap n = 32 tb + l32 (clamped inside the tap range)
+    const int nblk = (G::NTB - __builtin_amdgcn_readfirstlane(w) + kWaves - 1) / kWaves;  // TBW or TBW - 1
     int nb_off[G::TBW];
 #pragma unroll
     for (int i = 0; i < G::TBW; ++i) {
@@ -344,7 +346,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     for (int i = 0; i < G::TBW; ++i)
 #pragma unroll
         for (int r = 0; r < 16; ++r) dk64[i][r] = 0.0;
-    if (tid < kEB) sm.lsum[tid] = 0.0;
+    if (tid < kEB) sm.lsum[tid] = sm.gsum[tid] = 0.0;
 
     float* Ms = reinterpret_cast<float*>(sm.Gt);
     unsigned short* Ghi = sm.Gt;  // both planes, indexed by ghi() / glo()
@@ -382,6 +384,37 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         }
         __syncthreads();
 
+        // objective set-up, ahead of the forward pass so that the wave's first target loads are in
+        // flight during it.  Lane l, group i is pixel (row i, column l) of the tile; its byte
+        // offset from the tile's first pixel is the same in every epoch (lanes past a ragged edge
+        // read the nearest pixel inside and contribute zero).  Target values (and B0) are fetched
+        // one epoch ahead (epochs past the batch read epoch 0 and count nothing).
+        constexpr int NG = G::PT / 64;
+        unsigned ob[NG];
+        unsigned vmask = 0u;
+        {
+            const int x = tx0 + lane, xc = min(x, Wv - 1) - tx0;
+#pragma unroll
+            for (int i = 0; i < NG; ++i) {
+                const int y = ty0 + i, yc = min(y, Hv - 1) - ty0;
+                vmask |= (y < Hv && x < Wv) ? (1u << i) : 0u;
+                ob[i] = (unsigned)(yc * g.ldI + xc) * 4u;
+            }
+        }
+        const long long tile0 = (long long)(ty0 + G::HALF) * g.ldI + (tx0 + G::HALF);
+        float inext[NG], b0_next;
+        bool live_next;
+        auto fetch_I = [&](int k) {
+            const int e = w + kWaves * k;
+            const float* Ie = uniform_ptr(sm.Ip[e]);
+            live_next = Ie != nullptr;
+            b0_next = uniform_f(sm.B0[e]);
+            const char* Ib = uniform_ptr(reinterpret_cast<const char*>((Ie ? Ie : uniform_ptr(sm.Ip[0])) + tile0));
+#pragma unroll
+            for (int i = 0; i < NG; ++i) inext[i] = view_f32(raw_view(Ib), ob[i]);
+        };
+        fetch_I(0);
+
         // forward: row w of the tile, pixels l32 and 32 + l32, all 32 epochs
         {
             f32x16 acc0, acc1;
@@ -416,43 +449,14 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         __syncthreads();
 
         // per-pixel objective (FP32).  Wave w owns epochs w, w + 8, w + 16, w + 24: it takes an
-        // epoch's 512 forward results into registers, requests the epoch's target (and weight /
-        // flat / mask) values of the tile before it uses any, and writes g as hi / lo bf16 planes
-        // into the slot the forward results held (only this wave touches that slot, and its LDS
-        // reads precede its writes).  Lane l, group i is pixel (row i, column l) of the tile; its
-        // byte offset from the tile's first pixel is the same in every epoch (lanes past a ragged
-        // edge read the nearest pixel inside and contribute zero).
+        // epoch's 512 forward results into registers, requests the epoch's weight / flat / mask
+        // values (if any) before it uses any, and writes g as hi / lo bf16 planes into the slot the
+        // forward results held (only this wave touches that slot, and its LDS reads precede its
+        // writes).
         {
-            constexpr int NG = G::PT / 64;
-            unsigned ob[NG];
-            unsigned vmask = 0u;
-            {
-                const int x = tx0 + lane, xc = min(x, Wv - 1) - tx0;
-#pragma unroll
-                for (int i = 0; i < NG; ++i) {
-                    const int y = ty0 + i, yc = min(y, Hv - 1) - ty0;
-                    vmask |= (y < Hv && x < Wv) ? (1u << i) : 0u;
-                    ob[i] = (unsigned)(yc * g.ldI + xc) * 4u;
-                }
-            }
-            const long long tile0 = (long long)(ty0 + G::HALF) * g.ldI + (tx0 + G::HALF);
             with_mode(g.obj, g.F != nullptr, [&](auto rho_c, auto var_c, auto flat_c) {
                 constexpr int RHO = decltype(rho_c)::value, VAR = decltype(var_c)::value;
                 constexpr bool HAS_F = decltype(flat_c)::value;
-                // target values (and B0) one epoch ahead: epoch k + 1's loads are in flight while
-                // epoch k is computed (epochs past the batch read epoch 0 and count nothing)
-                float inext[NG], b0_next;
-                bool live_next;
-                auto fetch_I = [&](int k) {
-                    const int e = w + kWaves * k;
-                    const float* Ie = uniform_ptr(sm.Ip[e]);
-                    live_next = Ie != nullptr;
-                    b0_next = uniform_f(sm.B0[e]);
-                    const char* Ib = uniform_ptr(reinterpret_cast<const char*>((Ie ? Ie : uniform_ptr(sm.Ip[0])) + tile0));
-#pragma unroll
-                    for (int i = 0; i < NG; ++i) inext[i] = view_f32(raw_view(Ib), ob[i]);
-                };
-                fetch_I(0);
 #pragma unroll 1
                 for (int k = 0; k < kEB / kWaves; ++k) {
                     const int e = w + kWaves * k;
@@ -498,7 +502,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
                     unsigned short* hb = Ghi + 2 * e * G::PT + (lane ^ (rot & 63));
                     unsigned short* hb_even = hb + 64 * flip;
                     unsigned short* hb_odd = hb - 64 * flip;
-                    float lsum = 0.0f;
+                    float lsum = 0.0f, gsum = 0.0f;
 #pragma unroll
                     for (int i = 0; i < NG; i += 2) {
                         float l0, g0, l1, g1;
@@ -507,8 +511,11 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
                                                               l1, g1);
                         lsum += ok[i] ? l0 : 0.0f;
                         lsum += ok[i + 1] ? l1 : 0.0f;
+                        g0 = ok[i] ? g0 : 0.0f;
+                        g1 = ok[i + 1] ? g1 : 0.0f;
+                        gsum += g0 + g1;
                         unsigned hi, lo;
-                        split2(ok[i] ? g0 : 0.0f, ok[i + 1] ? g1 : 0.0f, hi, lo);
+                        split2(g0, g1, hi, lo);
                         unsigned short* h0 = hb_even + 64 * i;
                         unsigned short* h1 = hb_odd + 64 * (i + 1);
                         h0[0] = (unsigned short)hi;
@@ -516,8 +523,11 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
                         h1[0] = (unsigned short)(hi >> 16);
                         h1[G::PT] = (unsigned short)(lo >> 16);
                     }
-                    const double d = wave_sum_f64((double)lsum);
-                    if (lane == 0) sm.lsum[e] += d;
+                    const double dl = wave_sum_f64((double)lsum), dg = wave_sum_f64((double)gsum);
+                    if (lane == 0) {
+                        sm.lsum[e] += dl;
+                        sm.gsum[e] += dg;
+                    }
                 }
             });
         }
@@ -525,42 +535,46 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
 
         if (t + 1 < t_end) fetch_R(t + 1);
 
-        // backward: dK[32 epochs x 32 taps] per owned tap block, K steps of 16 pixels
+        // backward: dK[32 epochs x 32 taps] per owned tap block, K steps of 16 pixels.  The number
+        // of blocks a wave owns (TBW or TBW - 1) is wave-uniform and fixed at compile time in each
+        // instance, so the step loop has no branches.  Padding taps (n >= T) read a valid word;
+        // their columns are discarded.
         {
-            f32x16 accb[G::TBW];
+            auto backward = [&](auto nb_c) {
+                constexpr int NB = decltype(nb_c)::value;
+                f32x16 accb[NB];
 #pragma unroll
-            for (int i = 0; i < G::TBW; ++i)
+                for (int i = 0; i < NB; ++i)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) accb[i][r] = 0.0f;
+                    for (int r = 0; r < 16; ++r) accb[i][r] = 0.0f;
 #pragma unroll 2
-            for (int s = 0; s < G::PT / 16; ++s) {
-                const int pofs = s * 16 + 8 * q;  // first pixel of this lane's 8 (tile row s / 4)
-                const bf16x8 ah = *reinterpret_cast<const bf16x8*>(Ghi + ghi(l32, pofs, G::PT));
-                const bf16x8 al = *reinterpret_cast<const bf16x8*>(Ghi + glo(l32, pofs, G::PT));
-                const int rofs = (s >> 2) * G::RS + (s & 3) * 16;
+                for (int s = 0; s < G::PT / 16; ++s) {
+                    const int pofs = s * 16 + 8 * q;  // first pixel of this lane's 8 (tile row s / 4)
+                    const bf16x8 ah = *reinterpret_cast<const bf16x8*>(Ghi + ghi(l32, pofs, G::PT));
+                    const bf16x8 al = *reinterpret_cast<const bf16x8*>(Ghi + glo(l32, pofs, G::PT));
+                    const int rofs = (s >> 2) * G::RS + (s & 3) * 16;
+                    unsigned wv[NB][8];
 #pragma unroll
-                for (int i = 0; i < G::TBW; ++i) {
-                    const int tb = w + kWaves * i;
-                    if (tb < G::NTB) {
-                        unsigned wv[8];
-                        const unsigned* pr = sm.Rw + nb_off[i] + rofs;
+                    for (int i = 0; i < NB; ++i)
 #pragma unroll
-                        for (int j = 0; j < 8; ++j) wv[j] = pr[j];
-                        if ((tb + 1) * 32 > G::T) {
-                            const int n = tb * 32 + l32;
+                        for (int j = 0; j < 8; ++j) wv[i][j] = sm.Rw[nb_off[i] + rofs + j];
 #pragma unroll
-                            for (int j = 0; j < 8; ++j) wv[j] = n < G::T ? wv[j] : (n == G::T ? 0x3F800000u : 0u);
-                        }
+                    for (int i = 0; i < NB; ++i) {
                         bf16x8 bh, bl;
-                        unpack8(wv, bh, bl);
+                        unpack8(wv[i], bh, bl);
                         accb[i] = mfma3(ah, al, bh, bl, accb[i]);
                     }
                 }
+#pragma unroll
+                for (int i = 0; i < NB; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) dk64[i][r] += (double)accb[i][r];
+            };
+            if (nblk == G::TBW) {
+                backward(std::integral_constant<int, G::TBW>{});
+            } else if constexpr (G::TBW > 1) {
+                backward(std::integral_constant<int, G::TBW - 1>{});
             }
-#pragma unroll
-            for (int i = 0; i < G::TBW; ++i)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) dk64[i][r] += (double)accb[i][r];
         }
     }
 
@@ -568,9 +582,8 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     const int npp = G::T + 2;
 #pragma unroll
     for (int i = 0; i < G::TBW; ++i) {
-        const int tb = w + kWaves * i;
-        const int n = tb * 32 + l32;
-        if (tb < G::NTB && n <= G::T) {
+        const int n = (w + kWaves * i) * 32 + l32;
+        if (i < nblk && n < G::T) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int eg = eb * kEB + 8 * (r >> 2) + 4 * q + (r & 3);
@@ -581,7 +594,10 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     __syncthreads();
     if (tid < kEB) {
         const int eg = eb * kEB + tid;
-        if (eg < g.n_ep) g.partial[((long long)eg * g.wpb + wi) * npp + G::T + 1] = sm.lsum[tid];
+        if (eg < g.n_ep) {
+            g.partial[((long long)eg * g.wpb + wi) * npp + G::T] = sm.gsum[tid];
+            g.partial[((long long)eg * g.wpb + wi) * npp + G::T + 1] = sm.lsum[tid];
+        }
     }
 }
 
