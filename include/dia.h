@@ -239,7 +239,10 @@ int dia_batched_workspace_size(dia_image R, const dia_epoch* epochs /*host[n]*/,
 
 /* Per-epoch loss and gradient at theta[e] (device float[n][m*m+1]):
  * loss[e] (device double[n]), grad[e*(m*m+1) + k] (device float[n][m*m+1]).
- * Asynchronous on stream. */
+ * Asynchronous on stream.  BF16X3 only launches kernels (one per block of 32
+ * epochs, the epochs' array pointers passed as kernel arguments) and never
+ * waits on the host; FP32 uploads its tile plan and synchronizes stream first.
+ * Calls that share ws must be ordered on one stream. */
 int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs /*host[n]*/, int32_t n, int32_t m,
                           const dia_objective* obj, int32_t precision, const float* theta, double* loss,
                           float* grad, void* ws, size_t ws_bytes, void* stream);

@@ -52,7 +52,6 @@ struct BLayout {
     int n = 0, npp = 0, nld = 0, nchunks = 0;
     size_t partial = 0, gt = 0, th64 = 0, epochs = 0, chunks = 0, cbeg = 0, cend = 0, ints = 0;
     size_t blocks = 0, stride = 0, b_state = 0, b_sel = 0, b_vecs = 0;
-    size_t gemm = 0;
     size_t newton = 0;
     size_t total = 0;
 };
@@ -80,10 +79,6 @@ BLayout make_blayout(const dia_epoch* ep, int n_ep, int m, int precision, bool f
     off = align_up(off + sizeof(int) * (size_t)n_ep);
     L.ints = off;
     off = align_up(off + sizeof(int) * 16);
-    if (precision == DIA_PREC_BF16X3) {
-        L.gemm = off;
-        off = align_up(off + bf16x3_scratch_bytes(m, n_ep));
-    }
     if (fit) {
         L.b_state = 0;
         L.b_sel = align_up(sizeof(FitState));
@@ -230,20 +225,19 @@ int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32
     hipStream_t s = static_cast<hipStream_t>(stream);
     char* base = static_cast<char*>(ws);
     try {
-        if (hipStreamSynchronize(s) != hipSuccess) return DIA_E_HIP;  // the workspace is free to overwrite
         int* ints = reinterpret_cast<int*>(base + L.ints);
+        int rows_per = 0;
         if (precision == DIA_PREC_BF16X3) {
-            Bf16x3Args g;
-            const int pc = bf16x3_prepare(base + L.gemm, R, epochs, n, m, *obj, theta, (long long)L.n * sizeof(float),
-                                          reinterpret_cast<double*>(base + L.partial), s, &g);
+            // nothing is uploaded: the per-epoch pointers travel in the kernel arguments, and the
+            // reduction derives each epoch's partial rows from rows_per
+            std::vector<Bf16x3Args> g;
+            const int pc = bf16x3_prepare(R, epochs, n, m, *obj, theta, (long long)L.n * sizeof(float),
+                                          reinterpret_cast<double*>(base + L.partial), &g);
             if (pc != DIA_OK) return pc;
             if (bf16x3_launch_eval(g, s) != hipSuccess) return DIA_E_HIP;
-            std::vector<int> cb(n), ce(n);
-            const int rows_per = bf16x3_partial_rows(m, epochs[0].rows, epochs[0].cols, n) / n;
-            for (int e = 0; e < n; ++e) cb[e] = e * rows_per, ce[e] = (e + 1) * rows_per;
-            if (!upload(base + L.cbeg, cb.data(), sizeof(int) * n, s) || !upload(base + L.cend, ce.data(), sizeof(int) * n, s))
-                return DIA_E_HIP;
+            rows_per = bf16x3_partial_rows(m, epochs[0].rows, epochs[0].cols, n) / n;
         } else {
+            if (hipStreamSynchronize(s) != hipSuccess) return DIA_E_HIP;  // the workspace is free to overwrite
             double* th64 = reinterpret_cast<double*>(base + L.th64);
             if (launch_widen(theta, th64, (long long)n * L.n, s) != hipSuccess) return DIA_E_HIP;
             const std::vector<EpochDev> d = epoch_descs(R, epochs, n, m, theta, (long long)L.n * sizeof(float), th64,
@@ -261,8 +255,9 @@ int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32
         BatchReduceArgs br;
         std::memset(&br, 0, sizeof(br));
         br.partial = reinterpret_cast<const double*>(base + L.partial);
-        br.cbeg = reinterpret_cast<const int*>(base + L.cbeg);
-        br.cend = reinterpret_cast<const int*>(base + L.cend);
+        br.cbeg = rows_per > 0 ? nullptr : reinterpret_cast<const int*>(base + L.cbeg);
+        br.cend = rows_per > 0 ? nullptr : reinterpret_cast<const int*>(base + L.cend);
+        br.rows_per = rows_per;
         br.npp = L.npp;
         br.gt = reinterpret_cast<double*>(base + L.gt);
         br.out_loss = loss;
@@ -324,7 +319,8 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
             int variant = 0;
             int n_chunks = 0, grid = 0;
             BatchedArgs b;
-            Bf16x3Args g;
+            std::vector<Bf16x3Args> g;
+            int rows_per = 0;
             if (precision == DIA_PREC_FP32) {
                 const std::vector<EpochDev> d = epoch_descs(R, epochs, n, m, v0.theta_eval, (long long)L.stride,
                                                             v0.theta_eval64, (long long)L.stride, done0,
@@ -337,21 +333,18 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
                 grid = batched_grid(m, variant, n_chunks);
                 b = batched_args(base, L, R, *obj, n_chunks);
             } else {
-                TRY(bf16x3_prepare(base + L.gemm, R, epochs, n, m, *obj, v0.theta_eval, (long long)L.stride,
-                                   reinterpret_cast<double*>(base + L.partial), cs, &g) == DIA_OK);
-                std::vector<int> cb(n), ce(n);
-                const int rows_per = bf16x3_partial_rows(m, epochs[0].rows, epochs[0].cols, n) / n;
-                for (int e = 0; e < n; ++e) cb[e] = e * rows_per, ce[e] = (e + 1) * rows_per;
-                TRY(upload(base + L.cbeg, cb.data(), sizeof(int) * n, cs));
-                TRY(upload(base + L.cend, ce.data(), sizeof(int) * n, cs));
+                TRY(bf16x3_prepare(R, epochs, n, m, *obj, v0.theta_eval, (long long)L.stride,
+                                   reinterpret_cast<double*>(base + L.partial), &g) == DIA_OK);
+                rows_per = bf16x3_partial_rows(m, epochs[0].rows, epochs[0].cols, n) / n;
             }
             TRY(launch_zero_ints(ints, 16, cs) == hipSuccess);
 
             BatchReduceArgs br;
             std::memset(&br, 0, sizeof(br));
             br.partial = reinterpret_cast<const double*>(base + L.partial);
-            br.cbeg = reinterpret_cast<const int*>(base + L.cbeg);
-            br.cend = reinterpret_cast<const int*>(base + L.cend);
+            br.cbeg = rows_per > 0 ? nullptr : reinterpret_cast<const int*>(base + L.cbeg);
+            br.cend = rows_per > 0 ? nullptr : reinterpret_cast<const int*>(base + L.cend);
+            br.rows_per = rows_per;
             br.npp = L.npp;
             br.gt = reinterpret_cast<double*>(base + L.gt);
             br.st = st0;

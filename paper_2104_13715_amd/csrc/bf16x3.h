@@ -6,18 +6,26 @@
 // is hi*hi + hi*lo + lo*hi, accumulated in FP32 per tile and in FP64 across tiles.
 #pragma once
 
+#include <vector>
+
 #include "dia_common.h"
 
 namespace dia {
 
+constexpr int kBf16x3Block = 32;  // epochs per launch (one MFMA row block)
+
+// Arguments of one launch: one block of up to 32 epochs.  The per-epoch pointers travel in the
+// kernel arguments (nothing is uploaded per call).
 struct Bf16x3Args {
     const float* R;                // shared reference at the epochs' common window
     long long ldR;
-    int rows, cols, m, n_ep;
-    const float* const* I;         // device array of n_ep target pointers
-    const float* const* W;         // device arrays of per-epoch weights / flat / mask (entries may be null)
-    const float* const* F;
-    const uint8_t* const* Mk;
+    int rows, cols, m, n_ep;       // n_ep: epochs in the whole batch
+    int eb;                        // this launch's block: epochs 32 eb ...
+    const float* I[kBf16x3Block];  // per-epoch arrays of the block (null past the batch; W / F / Mk
+    const float* W[kBf16x3Block];  // entries may be null, and has_w / has_f / has_m say whether any
+    const float* F[kBf16x3Block];  // epoch of the batch has one)
+    const uint8_t* Mk[kBf16x3Block];
+    int has_w, has_f, has_m;
     long long ldI;
     const float* theta0;           // epoch e's parameters at byte offset e * theta_stride
     long long theta_stride;
@@ -28,11 +36,10 @@ struct Bf16x3Args {
 
 bool bf16x3_supported(int m);
 int bf16x3_partial_rows(int m, int rows, int cols, int n_ep);
-size_t bf16x3_scratch_bytes(int m, int n_ep);
 int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m);
-// Uploads the per-epoch pointer arrays into scratch (synchronises s) and fills *out.
-int bf16x3_prepare(char* scratch, const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
-                   const float* theta0, long long theta_stride, double* partial, hipStream_t s, Bf16x3Args* out);
-hipError_t bf16x3_launch_eval(const Bf16x3Args& g, hipStream_t s);
+// Fills one argument block per 32 epochs (host only; no device work).
+int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
+                   const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out);
+hipError_t bf16x3_launch_eval(const std::vector<Bf16x3Args>& blocks, hipStream_t s);
 
 }  // namespace dia

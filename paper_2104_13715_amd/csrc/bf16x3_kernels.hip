@@ -34,13 +34,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kEB = 32;             // epochs per block
+constexpr int kEB = kBf16x3Block;  // epochs per block
 constexpr int kWaves = 8;
 constexpr int kTR = kWaves;         // tile rows (one per wave in the forward pass)
 constexpr int kTC = 64;             // tile columns (two MFMA blocks of 32)
 constexpr int kThreads = 64 * kWaves;
 static_assert(kTR * kTC == 8 * 64, "a wave covers the tile with eight 64-pixel groups (in pairs) in the objective phase");
-constexpr int kTargetGroups = 256;  // one workgroup per CU on MI355X
+constexpr int kTargetGroups = 256;  // workgroups per launch: one per CU on MI355X
 
 template <int M>
 struct BfGeo {
@@ -301,8 +301,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     __shared__ BfSmem<M> sm;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int l32 = lane & 31, q = lane >> 5;
-    const int neb = (g.n_ep + kEB - 1) / kEB;
-    const int eb = blockIdx.x % neb, wi = blockIdx.x / neb;
+    const int eb = g.eb, wi = blockIdx.x;
     const int Hv = g.rows - M + 1, Wv = g.cols - M + 1;
     const int ntx = (Wv + kTC - 1) / kTC, nty = (Hv + kTR - 1) / kTR, ntiles = ntx * nty;
     const int t_begin = (int)((long long)ntiles * wi / g.wpb), t_end = (int)((long long)ntiles * (wi + 1) / g.wpb);
@@ -325,10 +324,10 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         const bool ok = eg < g.n_ep;
         sm.B0[tid] = ok ? reinterpret_cast<const float*>(reinterpret_cast<const char*>(g.theta0) + eg * g.theta_stride)[G::T]
                         : 0.0f;
-        sm.Ip[tid] = ok ? g.I[eg] : nullptr;
-        sm.Wp[tid] = ok && g.W ? g.W[eg] : nullptr;
-        sm.Fp[tid] = ok && g.F ? g.F[eg] : nullptr;
-        sm.Mp[tid] = ok && g.Mk ? g.Mk[eg] : nullptr;
+        sm.Ip[tid] = ok ? g.I[tid] : nullptr;
+        sm.Wp[tid] = ok ? g.W[tid] : nullptr;
+        sm.Fp[tid] = ok ? g.F[tid] : nullptr;
+        sm.Mp[tid] = ok ? g.Mk[tid] : nullptr;
     }
 
     // backward B-fragment base of each owned tap block: tap n = 32 tb + l32 (clamped inside the tap range)
@@ -454,7 +453,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         // forward results held (only this wave touches that slot, and its LDS reads precede its
         // writes).
         {
-            with_mode(g.obj, g.F != nullptr, [&](auto rho_c, auto var_c, auto flat_c) {
+            with_mode(g.obj, g.has_f != 0, [&](auto rho_c, auto var_c, auto flat_c) {
                 constexpr int RHO = decltype(rho_c)::value, VAR = decltype(var_c)::value;
                 constexpr bool HAS_F = decltype(flat_c)::value;
 #pragma unroll 1
@@ -469,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
 #pragma unroll
                     for (int i = 0; i < NG; ++i) iv[i] = inext[i];
                     if (k + 1 < kEB / kWaves) fetch_I(k + 1);
-                    const float* We = (live && g.W) ? uniform_ptr(sm.Wp[e]) : nullptr;
+                    const float* We = (live && g.has_w) ? uniform_ptr(sm.Wp[e]) : nullptr;
                     if (We) {
                         const char* Wb = uniform_ptr(reinterpret_cast<const char*>(We + tile0));
 #pragma unroll
@@ -487,7 +486,7 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
 #pragma unroll
                         for (int i = 0; i < NG; ++i) fv[i] = 1.0f;
                     }
-                    const uint8_t* Me = (live && g.Mk) ? uniform_ptr(sm.Mp[e]) : nullptr;
+                    const uint8_t* Me = (live && g.has_m) ? uniform_ptr(sm.Mp[e]) : nullptr;
                     if (Me) {
                         const char* Mb = uniform_ptr(reinterpret_cast<const char*>(Me + tile0));
 #pragma unroll
@@ -601,19 +600,21 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     }
 }
 
-int wpb_for(int m, int rows, int cols, int n_ep) {
+// workgroups per launch (one launch per block of 32 epochs): one per CU, or one per tile when
+// there are fewer tiles
+int wpb_for(int m, int rows, int cols) {
     const long long ntiles = (long long)((rows - m + 1 + kTR - 1) / kTR) * ((cols - m + 1 + kTC - 1) / kTC);
-    const int neb = (n_ep + kEB - 1) / kEB;
-    long long w = (kTargetGroups + neb - 1) / neb;
-    if (w > ntiles) w = ntiles;
-    return (int)std::max<long long>(w, 1);
+    return (int)std::max<long long>(std::min<long long>(kTargetGroups, ntiles), 1);
 }
 
 template <int M>
-hipError_t launch_m(const Bf16x3Args& g, hipStream_t s) {
-    const int neb = (g.n_ep + kEB - 1) / kEB;
-    hipLaunchKernelGGL(bf16x3_eval_kernel<M>, dim3(neb * g.wpb), dim3(kThreads), 0, s, g);
-    return hipGetLastError();
+hipError_t launch_m(const std::vector<Bf16x3Args>& blocks, hipStream_t s) {
+    for (const Bf16x3Args& g : blocks) {
+        hipLaunchKernelGGL(bf16x3_eval_kernel<M>, dim3(g.wpb), dim3(kThreads), 0, s, g);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
@@ -622,10 +623,8 @@ bool bf16x3_supported(int m) { return m == 9 || m == 17 || m == 19 || m == 25; }
 
 int bf16x3_partial_rows(int m, int rows, int cols, int n_ep) {
     if (!bf16x3_supported(m) || rows < m || cols < m || n_ep < 1) return n_ep > 0 ? n_ep : 1;
-    return n_ep * wpb_for(m, rows, cols, n_ep);
+    return n_ep * wpb_for(m, rows, cols);
 }
-
-size_t bf16x3_scratch_bytes(int, int n_ep) { return align_up(4 * sizeof(void*) * (size_t)std::max(n_ep, 1)); }
 
 int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m) {
     if (!bf16x3_supported(m)) return DIA_E_ARG;
@@ -636,37 +635,23 @@ int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m) {
     return DIA_OK;
 }
 
-int bf16x3_prepare(char* scratch, const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
-                   const float* theta0, long long theta_stride, double* partial, hipStream_t s, Bf16x3Args* out) {
+int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
+                   const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out) {
     // byte offsets of a staged reference window (kTR + m - 1 rows) are 32-bit
     if ((long long)R.ld * 4 * (kTR + m) >= (1LL << 32)) return DIA_E_SIZE;
-    std::vector<const void*> ptrs(4 * (size_t)n);
-    bool any_w = false, any_f = false, any_m = false;
-    for (int e = 0; e < n; ++e) {
-        ptrs[e] = ep[e].I;
-        ptrs[n + e] = ep[e].weights;
-        ptrs[2 * n + e] = ep[e].flat;
-        ptrs[3 * n + e] = ep[e].mask;
-        any_w |= ep[e].weights != nullptr;
-        any_f |= ep[e].flat != nullptr;
-        any_m |= ep[e].mask != nullptr;
-    }
-    if (hipMemcpyAsync(scratch, ptrs.data(), sizeof(void*) * ptrs.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return DIA_E_HIP;
     Bf16x3Args g;
     std::memset(&g, 0, sizeof(g));
-    const void* const* dp = reinterpret_cast<const void* const*>(scratch);
     g.R = R.data + (long long)ep[0].ref_row0 * R.ld + ep[0].ref_col0;
     g.ldR = R.ld;
     g.rows = ep[0].rows;
     g.cols = ep[0].cols;
     g.m = m;
     g.n_ep = n;
-    g.I = reinterpret_cast<const float* const*>(dp);
-    g.W = any_w ? reinterpret_cast<const float* const*>(dp + n) : nullptr;
-    g.F = any_f ? reinterpret_cast<const float* const*>(dp + 2 * n) : nullptr;
-    g.Mk = any_m ? reinterpret_cast<const uint8_t* const*>(dp + 3 * n) : nullptr;
+    for (int e = 0; e < n; ++e) {
+        g.has_w |= ep[e].weights != nullptr;
+        g.has_f |= ep[e].flat != nullptr;
+        g.has_m |= ep[e].mask != nullptr;
+    }
     g.ldI = ep[0].ld;
     g.theta0 = theta0;
     g.theta_stride = theta_stride;
@@ -675,17 +660,30 @@ int bf16x3_prepare(char* scratch, const dia_image& R, const dia_epoch* ep, int n
     g.obj.flat = nullptr;
     g.obj.mask = nullptr;
     g.partial = partial;
-    g.wpb = wpb_for(m, g.rows, g.cols, n);
-    *out = g;
+    g.wpb = wpb_for(m, g.rows, g.cols);
+    out->clear();
+    for (int eb = 0; eb * kEB < n; ++eb) {
+        g.eb = eb;
+        for (int k = 0; k < kEB; ++k) {
+            const int e = eb * kEB + k;
+            const bool in = e < n;
+            g.I[k] = in ? ep[e].I : nullptr;
+            g.W[k] = in ? ep[e].weights : nullptr;
+            g.F[k] = in ? ep[e].flat : nullptr;
+            g.Mk[k] = in ? ep[e].mask : nullptr;
+        }
+        out->push_back(g);
+    }
     return DIA_OK;
 }
 
-hipError_t bf16x3_launch_eval(const Bf16x3Args& g, hipStream_t s) {
-    switch (g.m) {
-        case 9: return launch_m<9>(g, s);
-        case 17: return launch_m<17>(g, s);
-        case 19: return launch_m<19>(g, s);
-        case 25: return launch_m<25>(g, s);
+hipError_t bf16x3_launch_eval(const std::vector<Bf16x3Args>& blocks, hipStream_t s) {
+    if (blocks.empty()) return hipErrorInvalidValue;
+    switch (blocks[0].m) {
+        case 9: return launch_m<9>(blocks, s);
+        case 17: return launch_m<17>(blocks, s);
+        case 19: return launch_m<19>(blocks, s);
+        case 25: return launch_m<25>(blocks, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -425,7 +425,8 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchRed
     FitState* st = br.st ? reinterpret_cast<FitState*>(reinterpret_cast<char*>(br.st) + off) : nullptr;
     if (st != nullptr && st->done != 0) return;
     const int col = blockIdx.x * kReduceCols + (tid % kReduceCols);
-    const double tot = reduce_columns(br.partial, br.npp, br.cbeg[e], br.cend[e], col, red);
+    const int r0 = br.cbeg ? br.cbeg[e] : e * br.rows_per, r1 = br.cend ? br.cend[e] : (e + 1) * br.rows_per;
+    const double tot = reduce_columns(br.partial, br.npp, r0, r1, col, red);
     double* gt = br.gt + (long long)e * br.npp;
     if (tid < kReduceCols && col < br.npp) {
         gt[col] = tot;

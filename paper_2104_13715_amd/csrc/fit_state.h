@@ -77,8 +77,9 @@ struct ReduceArgs {
 // e * stride from the epoch-0 pointers.
 struct BatchReduceArgs {
     const double* partial;  // [n_chunks][npp]
-    const int* cbeg;        // chunk rows of epoch e: [cbeg[e], cend[e])
-    const int* cend;
+    const int* cbeg;        // chunk rows of epoch e: [cbeg[e], cend[e]), or, when cbeg is null,
+    const int* cend;        // [e * rows_per, (e + 1) * rows_per)
+    int rows_per;
     int npp;
     double* gt;             // [n_epochs][npp]
     double* out_loss;       // loss-grad mode: [n_epochs]
