@@ -111,7 +111,9 @@ int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM,
  * written to memory).  The tile shape is the one the fits use for this kernel
  * size and image-size class: the first call for a new (m, size class) in a
  * process times the compiled shapes on this data, synchronising the stream
- * once (DIA_TILE_VARIANT=k pins shape k, DIA_AUTOTUNE=0 keeps the default):
+ * once (DIA_TILE_VARIANT=k pins shape k, DIA_AUTOTUNE=0 keeps the default;
+ * shapes: 0 the default rows per thread, 1 / 2 / 3 one / two / four rows per
+ * thread where the LDS budget allows, compiled for m = 9, 17, 19, 25):
  *   *loss   = L(theta)  summed over valid, unmasked pixels, FP64      (device double[1])
  *   grad[k] = dL/dK_k = sum_p g_p R_(p + k),  grad[m*m] = dL/dB0 = sum_p g_p,
  *             g_p = d l_p / d M_p                                      (device float[m*m+1])

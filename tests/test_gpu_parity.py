@@ -159,6 +159,19 @@ def test_loss_grad_kernel_sizes_and_ragged_tiles(dia, m, H, W):
     check_grad(g, g_ref, m)
 
 
+@pytest.mark.parametrize("variant", ["1", "2", "3"])
+@pytest.mark.parametrize("m,H,W", [(9, 130, 301), (17, 200, 170), (19, 300, 250), (25, 170, 151)])
+def test_loss_grad_pinned_tile_shapes(dia, monkeypatch, m, H, W, variant):
+    # every compiled tile shape
+    monkeypatch.setenv("DIA_TILE_VARIANT", variant)
+    R, I, theta, _ = random_problem(200 + m, H, W, m)
+    o_or, o_gpu = to_objs(dia, "cauchy", "ccd_model", sigma0=8.0, gain=1.5)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    check_loss(L, L_ref, R, I, theta, m, o_or)
+    check_grad(g, g_ref, m)
+
+
 def test_loss_grad_valid_region_of_one_pixel(dia):
     m = 9
     R, I, theta, _ = random_problem(3, 9, 9, m)
