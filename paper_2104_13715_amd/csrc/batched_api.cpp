@@ -334,7 +334,8 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
                 b = batched_args(base, L, R, *obj, n_chunks);
             } else {
                 TRY(bf16x3_prepare(R, epochs, n, m, *obj, v0.theta_eval, (long long)L.stride,
-                                   reinterpret_cast<double*>(base + L.partial), &g) == DIA_OK);
+                                   reinterpret_cast<double*>(base + L.partial), &g, done0,
+                                   (long long)L.stride) == DIA_OK);
                 rows_per = bf16x3_partial_rows(m, epochs[0].rows, epochs[0].cols, n) / n;
             }
             TRY(launch_zero_ints(ints, 16, cs) == hipSuccess);

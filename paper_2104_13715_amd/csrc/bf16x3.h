@@ -32,6 +32,8 @@ struct Bf16x3Args {
     ObjParams obj;                 // scalars (the per-epoch arrays above replace its pointers)
     double* partial;               // row (e * wpb + w) holds workgroup w's [dK (m*m), dB0, loss] for epoch e
     int wpb;                       // workgroups per block of 32 epochs
+    const int* done;               // fits: epoch e's done flag at byte offset e * done_stride (else null);
+    long long done_stride;         // a launch whose epochs are all done returns at once
 };
 
 bool bf16x3_supported(int m);
@@ -39,7 +41,8 @@ int bf16x3_partial_rows(int m, int rows, int cols, int n_ep);
 int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m);
 // Fills one argument block per 32 epochs (host only; no device work).
 int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
-                   const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out);
+                   const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out,
+                   const int* done = nullptr, long long done_stride = 0);
 hipError_t bf16x3_launch_eval(const std::vector<Bf16x3Args>& blocks, hipStream_t s);
 
 }  // namespace dia

@@ -302,6 +302,17 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int l32 = lane & 31, q = lane >> 5;
     const int eb = g.eb, wi = blockIdx.x;
+    if (g.done != nullptr) {  // a fit: nothing to do once every epoch of the block has converged
+        __shared__ int live;
+        if (threadIdx.x == 0) live = 0;
+        __syncthreads();
+        const int eg = eb * kEB + (int)threadIdx.x;
+        if (threadIdx.x < kEB && eg < g.n_ep &&
+            *reinterpret_cast<const int*>(reinterpret_cast<const char*>(g.done) + eg * g.done_stride) == 0)
+            live = 1;
+        __syncthreads();
+        if (live == 0) return;
+    }
     const int Hv = g.rows - M + 1, Wv = g.cols - M + 1;
     const int ntx = (Wv + kTC - 1) / kTC, nty = (Hv + kTR - 1) / kTR, ntiles = ntx * nty;
     const int t_begin = (int)((long long)ntiles * wi / g.wpb), t_end = (int)((long long)ntiles * (wi + 1) / g.wpb);
@@ -636,7 +647,8 @@ int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m) {
 }
 
 int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
-                   const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out) {
+                   const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out,
+                   const int* done, long long done_stride) {
     // byte offsets of a staged reference window (kTR + m - 1 rows) are 32-bit
     if ((long long)R.ld * 4 * (kTR + m) >= (1LL << 32)) return DIA_E_SIZE;
     Bf16x3Args g;
@@ -661,6 +673,8 @@ int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const 
     g.obj.mask = nullptr;
     g.partial = partial;
     g.wpb = wpb_for(m, g.rows, g.cols);
+    g.done = done;
+    g.done_stride = done_stride;
     out->clear();
     for (int eb = 0; eb * kEB < n; ++eb) {
         g.eb = eb;
