@@ -357,24 +357,48 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
             br.queue = ints;
             br.n_done = ints + 1;
 
-            TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess);
-            bool ok = true;
-            for (int k = 0; k < o.poll_every; ++k) {
-                if (precision == DIA_PREC_FP32)
-                    ok = ok && launch_batched_eval(m, grid, b, cs, variant) == hipSuccess;
-                else
-                    ok = ok && bf16x3_launch_eval(g, cs) == hipSuccess;
-                ok = ok && launch_reduce_batched(br, n, cs) == hipSuccess;
-            }
-            TRY(hipStreamEndCapture(cs, &graph) == hipSuccess);
-            TRY(ok);
-            TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess);
+            // poll_every optimiser iterations as one graph
+            auto capture = [&]() -> bool {
+                if (exec) (void)hipGraphExecDestroy(exec);
+                if (graph) (void)hipGraphDestroy(graph);
+                exec = nullptr;
+                graph = nullptr;
+                if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+                bool ok = true;
+                for (int k = 0; k < o.poll_every; ++k) {
+                    if (precision == DIA_PREC_FP32)
+                        ok = ok && launch_batched_eval(m, grid, b, cs, variant) == hipSuccess;
+                    else
+                        ok = ok && bf16x3_launch_eval(g, cs) == hipSuccess;
+                    ok = ok && launch_reduce_batched(br, n, cs) == hipSuccess;
+                }
+                if (hipStreamEndCapture(cs, &graph) != hipSuccess || !ok) return false;
+                return hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            };
+            TRY(capture());
             const int max_reps = o.max_eval / o.poll_every + 2;
             int n_done = 0;
+            std::vector<int> done_h(n), live;
             for (int rep = 0; rep < max_reps && n_done < n && rc == DIA_OK; ++rep) {
                 TRY(hipGraphLaunch(exec, cs) == hipSuccess);
                 TRY(hipMemcpyAsync(&n_done, ints + 1, sizeof(int), hipMemcpyDeviceToHost, cs) == hipSuccess);
                 TRY(hipStreamSynchronize(cs) == hipSuccess);
+                // split precision: once the unconverged epochs fit in fewer blocks of 32, gather
+                // them into full blocks (a block costs the same however many of its epochs still run)
+                if (precision == DIA_PREC_BF16X3 && n_done < n &&
+                    (n - n_done + kBf16x3Block - 1) / kBf16x3Block < (int)g.size()) {
+                    TRY(hipMemcpy2DAsync(done_h.data(), sizeof(int), &st0->done, (size_t)L.stride, sizeof(int), n,
+                                         hipMemcpyDeviceToHost, cs) == hipSuccess);
+                    TRY(hipStreamSynchronize(cs) == hipSuccess);
+                    live.clear();
+                    for (int e = 0; e < n; ++e)
+                        if (done_h[e] == 0) live.push_back(e);
+                    if (live.empty()) break;
+                    TRY(bf16x3_prepare(R, epochs, n, m, *obj, v0.theta_eval, (long long)L.stride,
+                                       reinterpret_cast<double*>(base + L.partial), &g, done0, (long long)L.stride,
+                                       &live) == DIA_OK);
+                    TRY(capture());
+                }
             }
             if (rc != DIA_OK) break;
             std::vector<NewtonOutcome> nw(n);

@@ -20,8 +20,8 @@ struct Bf16x3Args {
     const float* R;                // shared reference at the epochs' common window
     long long ldR;
     int rows, cols, m, n_ep;       // n_ep: epochs in the whole batch
-    int eb;                        // this launch's block: epochs 32 eb ...
-    const float* I[kBf16x3Block];  // per-epoch arrays of the block (null past the batch; W / F / Mk
+    int ep[kBf16x3Block];          // epoch index of each of the launch's 32 slots (-1: empty)
+    const float* I[kBf16x3Block];  // per-slot arrays (null in empty slots; W / F / Mk
     const float* W[kBf16x3Block];  // entries may be null, and has_w / has_f / has_m say whether any
     const float* F[kBf16x3Block];  // epoch of the batch has one)
     const uint8_t* Mk[kBf16x3Block];
@@ -39,10 +39,11 @@ struct Bf16x3Args {
 bool bf16x3_supported(int m);
 int bf16x3_partial_rows(int m, int rows, int cols, int n_ep);
 int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m);
-// Fills one argument block per 32 epochs (host only; no device work).
+// Fills one argument block per 32 epochs of `live` (every epoch when null), in order (host only;
+// no device work).
 int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
                    const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out,
-                   const int* done = nullptr, long long done_stride = 0);
+                   const int* done = nullptr, long long done_stride = 0, const std::vector<int>* live = nullptr);
 hipError_t bf16x3_launch_eval(const std::vector<Bf16x3Args>& blocks, hipStream_t s);
 
 }  // namespace dia

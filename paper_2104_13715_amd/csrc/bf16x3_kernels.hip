@@ -301,13 +301,13 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     __shared__ BfSmem<M> sm;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int l32 = lane & 31, q = lane >> 5;
-    const int eb = g.eb, wi = blockIdx.x;
+    const int wi = blockIdx.x;
     if (g.done != nullptr) {  // a fit: nothing to do once every epoch of the block has converged
         __shared__ int live;
         if (threadIdx.x == 0) live = 0;
         __syncthreads();
-        const int eg = eb * kEB + (int)threadIdx.x;
-        if (threadIdx.x < kEB && eg < g.n_ep &&
+        const int eg = threadIdx.x < kEB ? g.ep[threadIdx.x] : -1;
+        if (eg >= 0 &&
             *reinterpret_cast<const int*>(reinterpret_cast<const char*>(g.done) + eg * g.done_stride) == 0)
             live = 1;
         __syncthreads();
@@ -320,9 +320,9 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
     // K of this block in A-fragment order: (step c, half q, epoch e, j) <- tap 16 c + 8 q + j
     for (int idx = tid; idx < kEB * G::TP; idx += kThreads) {
         const int e = idx / G::TP, t = idx - e * G::TP;
-        const int eg = eb * kEB + e;
+        const int eg = g.ep[e];
         float v = 0.0f;
-        if (eg < g.n_ep && t < G::T)
+        if (eg >= 0 && t < G::T)
             v = reinterpret_cast<const float*>(reinterpret_cast<const char*>(g.theta0) + eg * g.theta_stride)[t];
         const unsigned p = split_pack(v);
         const int c = t >> 4, qq = (t >> 3) & 1, j = t & 7;
@@ -331,8 +331,8 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         sm.Klo[at] = (unsigned short)(p & 0xFFFFu);
     }
     if (tid < kEB) {
-        const int eg = eb * kEB + tid;
-        const bool ok = eg < g.n_ep;
+        const int eg = g.ep[tid];
+        const bool ok = eg >= 0;
         sm.B0[tid] = ok ? reinterpret_cast<const float*>(reinterpret_cast<const char*>(g.theta0) + eg * g.theta_stride)[G::T]
                         : 0.0f;
         sm.Ip[tid] = ok ? g.I[tid] : nullptr;
@@ -596,15 +596,15 @@ __global__ __launch_bounds__(kThreads) void bf16x3_eval_kernel(Bf16x3Args g) {
         if (i < nblk && n < G::T) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int eg = eb * kEB + 8 * (r >> 2) + 4 * q + (r & 3);
-                if (eg < g.n_ep) g.partial[((long long)eg * g.wpb + wi) * npp + n] = dk64[i][r];
+                const int eg = g.ep[8 * (r >> 2) + 4 * q + (r & 3)];
+                if (eg >= 0) g.partial[((long long)eg * g.wpb + wi) * npp + n] = dk64[i][r];
             }
         }
     }
     __syncthreads();
     if (tid < kEB) {
-        const int eg = eb * kEB + tid;
-        if (eg < g.n_ep) {
+        const int eg = g.ep[tid];
+        if (eg >= 0) {
             g.partial[((long long)eg * g.wpb + wi) * npp + G::T] = sm.gsum[tid];
             g.partial[((long long)eg * g.wpb + wi) * npp + G::T + 1] = sm.lsum[tid];
         }
@@ -648,7 +648,7 @@ int bf16x3_check_epoch(const dia_epoch& first, const dia_epoch& x, int m) {
 
 int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const dia_objective& obj,
                    const float* theta0, long long theta_stride, double* partial, std::vector<Bf16x3Args>* out,
-                   const int* done, long long done_stride) {
+                   const int* done, long long done_stride, const std::vector<int>* live) {
     // byte offsets of a staged reference window (kTR + m - 1 rows) are 32-bit
     if ((long long)R.ld * 4 * (kTR + m) >= (1LL << 32)) return DIA_E_SIZE;
     Bf16x3Args g;
@@ -676,11 +676,13 @@ int bf16x3_prepare(const dia_image& R, const dia_epoch* ep, int n, int m, const 
     g.done = done;
     g.done_stride = done_stride;
     out->clear();
-    for (int eb = 0; eb * kEB < n; ++eb) {
-        g.eb = eb;
+    const int nl = live ? (int)live->size() : n;
+    for (int b0 = 0; b0 < nl; b0 += kEB) {
         for (int k = 0; k < kEB; ++k) {
-            const int e = eb * kEB + k;
-            const bool in = e < n;
+            const int e = b0 + k < nl ? (live ? (*live)[b0 + k] : b0 + k) : -1;
+            if (e >= n) return DIA_E_ARG;
+            const bool in = e >= 0;
+            g.ep[k] = e;
             g.I[k] = in ? ep[e].I : nullptr;
             g.W[k] = in ? ep[e].weights : nullptr;
             g.F[k] = in ? ep[e].flat : nullptr;

@@ -159,6 +159,28 @@ def test_fit_bf16x3_matches_oracle(dia):
         assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4
 
 
+def test_fit_bf16x3_more_epochs_than_a_block(dia):
+    # 40 epochs: two launches of 32 slots at first; as epochs converge the unconverged ones are
+    # gathered into one block (slots then hold arbitrary epoch indices)
+    m, side, n = 9, 72, 40
+    b = shared_batch(n, m, side, 98)
+    o, oo = objs(dia, b)
+    ep = [dia.Epoch(I=gpu(e.I)) for e in b.epochs]
+    theta, res, st = dia.fit_batched(gpu(b.R), ep, m, o, precision="bf16x3")
+    assert st >= 0
+    th = theta.cpu().double().numpy()
+    evals = [r.n_eval for r in res]
+    print(f"evals per epoch: min {min(evals)} max {max(evals)}")
+    for k, e in enumerate(b.epochs):
+        ref = oracle.solve(b.R, e.I, m, oo)
+        K, Kr = th[k, :-1], ref[:-1]
+        eK = np.linalg.norm(K - Kr) / np.linalg.norm(Kr)
+        eP = abs(K.sum() - Kr.sum()) / abs(Kr.sum())
+        eB = abs(th[k, -1] - ref[-1]) / max(abs(ref[-1]), 1.0)
+        assert res[k].status >= 0
+        assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4, (k, eK, eP, eB)
+
+
 def test_bf16x3_rejects_unshared_windows_and_sizes(dia):
     b = sf.batched(92, 3, 9, 200, 300, (120, 160))  # different sides and offsets
     o, _ = objs(dia, b)
