@@ -216,44 +216,68 @@ def crop(pair: Pair, size: int) -> Pair:
                 meta=dict(pair.meta, crop=size))
 
 
+def _batched_epoch(config: int, e: int, R64: np.ndarray, m: int, ref_size: int, side_range, noise: bool,
+                   gain: float, sigma0_e: float) -> Epoch:
+    """Epoch e of a batch: everything it draws comes from its own stream rng_for(config, e + 1)."""
+    er = rng_for(config, e + 1)
+    lo, hi = side_range
+    side = int(er.integers(lo, hi + 1))
+    r0 = int(er.integers(0, ref_size - side + 1))
+    c0 = int(er.integers(0, ref_size - side + 1))
+    K = kernel_gaussian(m, er.uniform(1.2, 3.0), dx=er.uniform(-0.5, 0.5), dy=er.uniform(-0.5, 0.5),
+                        total=er.uniform(0.7, 1.3))
+    B0 = float(er.uniform(-50.0, 50.0))
+    I_nl = correlate_target(R64[r0:r0 + side, c0:c0 + side], K, B0)
+    I = add_ccd_noise(I_nl, gain, sigma0_e, er) if noise else I_nl
+    return Epoch(I=I.astype(np.float32), row0=r0, col0=c0, K_true=K, B0_true=B0)
+
+
+_POOL_R64 = None
+
+
+def _pool_init(R64):
+    global _POOL_R64
+    _POOL_R64 = R64
+
+
+def _pool_epoch(a):
+    return _batched_epoch(a[0], a[1], _POOL_R64, *a[2:])
+
+
 def batched(config: int, n_epochs: int, m: int, ref_size: int, n_stars: int, side_range, *,
-            fwhm=3.0, noise=True) -> Batch:
+            fwhm=3.0, noise=True, workers: int = 1) -> Batch:
     """Shared reference star field with per-epoch targets cut from it.
 
     Each epoch e draws a square side in ``side_range`` (inclusive), a crop offset uniform in
     [0, ref_size - side], a Gaussian kernel with FWHM ~ U(1.2, 3.0), sum ~ U(0.7, 1.3) and
-    subpixel offset ~ U(-0.5, 0.5)^2, and B0 ~ U(-50, 50)."""
+    subpixel offset ~ U(-0.5, 0.5)^2, and B0 ~ U(-50, 50).  With workers > 1 the epochs are made
+    in that many freshly started worker processes (identical result: each epoch has its own
+    random stream)."""
     rng = rng_for(config, 0)
     R = star_field(rng, ref_size, ref_size, n_stars, 1e2, 1e6, "moffat", fwhm, 500.0).astype(np.float32)
     R64 = R.astype(np.float64)
     gain, sigma0_e = 1.5, 8.0
-    epochs = []
-    for e in range(n_epochs):
-        er = rng_for(config, e + 1)
-        lo, hi = side_range
-        side = int(er.integers(lo, hi + 1))
-        r0 = int(er.integers(0, ref_size - side + 1))
-        c0 = int(er.integers(0, ref_size - side + 1))
-        K = kernel_gaussian(m, er.uniform(1.2, 3.0), dx=er.uniform(-0.5, 0.5), dy=er.uniform(-0.5, 0.5),
-                            total=er.uniform(0.7, 1.3))
-        B0 = float(er.uniform(-50.0, 50.0))
-        I_nl = correlate_target(R64[r0:r0 + side, c0:c0 + side], K, B0)
-        I = add_ccd_noise(I_nl, gain, sigma0_e, er) if noise else I_nl
-        epochs.append(Epoch(I=I.astype(np.float32), row0=r0, col0=c0, K_true=K, B0_true=B0))
+    tail = (m, ref_size, side_range, noise, gain, sigma0_e)
+    if workers > 1 and n_epochs > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(min(workers, n_epochs), initializer=_pool_init, initargs=(R64,)) as pool:
+            epochs = pool.map(_pool_epoch, [(config, e) + tail for e in range(n_epochs)], chunksize=1)
+    else:
+        epochs = [_batched_epoch(config, e, R64, *tail) for e in range(n_epochs)]
     return Batch(R=R, epochs=epochs, m=m, sigma0_adu=sigma0_e / gain, gain=gain,
                  meta=dict(config=config, ref_size=ref_size, n_stars=n_stars, side_range=side_range))
 
 
-def config4(noise=True, n_epochs=64, ref_size=2048, side_range=(512, 2048)) -> Batch:
+def config4(noise=True, n_epochs=64, ref_size=2048, side_range=(512, 2048), workers=1) -> Batch:
     """64 epochs of side U{512..2048} cut from a shared 2048^2 reference (30,000 stars), 17x17 kernels."""
     n = int(round(30000 * (ref_size / 2048) ** 2))
-    return batched(4, n_epochs, 17, ref_size, n, side_range, noise=noise)
+    return batched(4, n_epochs, 17, ref_size, n, side_range, noise=noise, workers=workers)
 
 
-def config5(noise=True, n_epochs=256, ref_size=2048) -> Batch:
+def config5(noise=True, n_epochs=256, ref_size=2048, workers=1) -> Batch:
     """256 epochs at 2048^2 against one shared 2048^2 reference (40,000 stars), 25x25 kernels."""
     n = int(round(40000 * (ref_size / 2048) ** 2))
-    return batched(5, n_epochs, 25, ref_size, n, (ref_size, ref_size), noise=noise)
+    return batched(5, n_epochs, 25, ref_size, n, (ref_size, ref_size), noise=noise, workers=workers)
 
 
 def paper_reference(size: int = 142, seed: int = 0, phi_R: float | None = None) -> np.ndarray:
