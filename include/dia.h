@@ -171,8 +171,10 @@ typedef struct {
  * per-pixel curvature: exact for a Gaussian objective with fixed variance,
  * the Gauss-Newton / IRLS weight otherwise) by Cholesky, with a backtracking
  * line search on the loss; it stops when the Newton decrement -g.d is below
- * the FP64 resolution of the loss or the step below the FP32 resolution of
- * theta. */
+ * the FP64 resolution of the loss, the step below the FP32 resolution of
+ * theta, or an accepted step lowers the loss by no more than 1e-13 |L| (the
+ * rounding level of the loss summed over millions of pixels: the gradient
+ * is then at its noise floor). */
 void dia_fit_opts_default(dia_fit_opts* opts /*host*/);
 
 typedef struct {

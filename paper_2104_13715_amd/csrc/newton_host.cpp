@@ -153,6 +153,9 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
             if (std::isfinite(Lt) && Lt <= L - 1e-4 * alpha * dec) {
                 if (hipMemcpyAsync(th, v.theta_eval64, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
                     return DIA_E_HIP;
+                // a decrease at the rounding level of the FP64 loss sum (millions of terms):
+                // the gradient is at its noise floor, and further steps only chase that noise
+                if (L - Lt <= 1e-13 * (std::fabs(L) + 1.0)) out->converged = 1;
                 L = Lt;
                 accepted = true;
                 break;
@@ -166,6 +169,7 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
             break;
         }
         ++out->steps;
+        if (out->converged) break;
     }
     if (launch_set_x(st, v, th, n, L, s) != hipSuccess) return DIA_E_HIP;
     return hipStreamSynchronize(s) == hipSuccess ? DIA_OK : DIA_E_HIP;

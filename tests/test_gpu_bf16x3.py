@@ -181,6 +181,41 @@ def test_fit_bf16x3_more_epochs_than_a_block(dia):
         assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4, (k, eK, eP, eB)
 
 
+def test_fit_full_size_epoch_at_gradient_noise_floor(dia):
+    # epoch 246 of the seeded 256 x 2048^2, m = 25 batch at full size: its FP64 gradient reaches the
+    # rounding floor of the 4.1 M-term sums while the Newton decrement is still above its bar; the
+    # polish must declare convergence, and the fit must match the oracle's exact minimiser
+    # (tests/golden/make_c5_epoch246.py) to the 1e-4 bar, in both precisions and the single-pair fit
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("c5_epoch246", os.path.join(here, "make_c5_epoch246.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    R, e = mod.epoch()
+    ref = np.loadtxt(os.path.join(here, "c5_epoch246_oracle_theta.txt"))
+    m = mod.M
+    o = dia.Objective(rho="gauss", var="ccd_data", sigma0=mod.SIGMA0_E / mod.GAIN, gain=mod.GAIN)
+
+    def errs(th):
+        th = np.asarray(th, np.float64).ravel()
+        K, Kr = th[:-1], ref[:-1]
+        return (np.linalg.norm(K - Kr) / np.linalg.norm(Kr), abs(K.sum() - Kr.sum()) / abs(Kr.sum()),
+                abs(th[-1] - ref[-1]) / max(abs(ref[-1]), 1.0))
+
+    Rg, Ig = gpu(R), gpu(e.I)
+    for prec in ("bf16x3", "fp32"):
+        theta, res, st = dia.fit_batched(Rg, [dia.Epoch(I=Ig)], m, o, precision=prec)
+        eK, eP, eB = errs(theta.cpu().numpy())
+        print(f"{prec}: stop {res[0].stop} newton {res[0].n_newton} K {eK:.2e} P {eP:.2e} B0 {eB:.2e}")
+        assert st == 0 and res[0].stop == "newton"
+        assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4
+    f = dia.fit(Rg, Ig, m, o)
+    eK, eP, eB = errs(f.theta.cpu().numpy())
+    assert f.status == 0 and f.stop == "newton"
+    assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4
+
+
 def test_bf16x3_rejects_unshared_windows_and_sizes(dia):
     b = sf.batched(92, 3, 9, 200, 300, (120, 160))  # different sides and offsets
     o, _ = objs(dia, b)
