@@ -165,8 +165,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (per-GPU throughput is the "
-              "whole-job value; see DESIGN.md for how the fit would shard)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path, so --gpus must be 1 "
+              "(the value is that GPU's throughput)", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -27,8 +27,11 @@ What it computes, with the passage each part follows:
 * ``adam_step``      one bias-corrected Adam update (Sec. 2.3, Kingma & Ba defaults)
 * ``init_theta``     B0 = median(I), flat or Gaussian K (Sec. 2.9)
 * ``photometric_scale``  P = sum K (eq. photometric_scale_factor)
+* ``covariance``     Sec. 2.5: Sigma = F^-1 of the observed Fisher information F (eq. covmatrix),
+                     standard errors sqrt(Sigma_pp) (eq. deltatheta), the error of P, and the
+                     paper's validity tests of Sigma (determinant and eigenvalues positive)
 
-Readings where the paper is silent are listed in DESIGN.md ("Readings of the paper").
+Where the paper is silent or ambiguous, the reading taken is stated where it is used.
 Parity pins for every function live in ``tests/test_oracle_pins.py``.
 """
 from __future__ import annotations
@@ -312,6 +315,28 @@ def hessian(R, I, theta, m, obj: Objective):
     _, _, h = pixel_terms(obj, Iv, M, m)
     A, _ = normal_matrix(R, m, h)
     return A
+
+
+def covariance(F) -> dict:
+    """Sec. 2.5 for a Fisher information F (n x n, the last parameter B0, the first n - 1 the kernel):
+      cov     = F^-1                                   (eq. covmatrix)
+      sigma   = sqrt(cov_pp)                           (eq. deltatheta, the Cramer-Rao bound)
+      sigma_P = sqrt(1^T cov_KK 1), the error of P = sum K (eq. photometric_scale_factor)
+      valid   = the paper's two tests of cov: its determinant is positive, and after
+                diagonalisation every eigenvalue is positive
+      logdet  = ln det cov (NaN when the determinant is not positive)"""
+    F = _f64(F)
+    n = F.shape[0]
+    cov = np.linalg.inv(F)
+    cov = 0.5 * (cov + cov.T)
+    ev = np.linalg.eigvalsh(cov)
+    sign, logdet = np.linalg.slogdet(cov)
+    d = np.diag(cov)
+    sP2 = float(cov[:n - 1, :n - 1].sum())
+    return dict(cov=cov, sigma=np.sqrt(np.where(d > 0, d, np.nan)),
+                sigma_P=float(np.sqrt(sP2)) if sP2 > 0 else float("nan"),
+                valid=bool(sign > 0 and np.all(ev > 0)), logdet=float(logdet) if sign > 0 else float("nan"),
+                eigvals=ev)
 
 
 def _irls_weights(obj: Objective, Iv, M, m):

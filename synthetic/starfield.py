@@ -6,8 +6,8 @@ the tests, the benchmark and the smoke check, and holds none of the fit's
 arithmetic: the noiseless target is formed with scipy's own correlation
 routine, never with the oracle or the GPU library.
 
-Recipe (Section 3.1 "Generating artificial images" for the scene, the
-workload table in the design doc for the sizes):
+Recipe (Section 3.1 "Generating artificial images" for the scene; the sizes
+of each workload are those of the config functions below):
 
 * stars at continuous positions uniform over the frame, fluxes log-uniform
   between ``flux_min`` and ``flux_max`` (the paper's own F^(-3/2) law is
