@@ -94,11 +94,13 @@ typedef struct {
 } dia_objective;
 
 /* Operations for dia_workspace_size. */
-enum { DIA_OP_MODEL = 0, DIA_OP_LOSS_GRAD = 1, DIA_OP_FIT = 2, DIA_OP_FIT_CLIPPED = 3, DIA_OP_HESSIAN = 4 };
+enum { DIA_OP_MODEL = 0, DIA_OP_LOSS_GRAD = 1, DIA_OP_FIT = 2, DIA_OP_FIT_CLIPPED = 3, DIA_OP_HESSIAN = 4,
+       DIA_OP_COVARIANCE = 5 };
 
 /* Workspace bytes that dia_loss_grad (DIA_OP_LOSS_GRAD) or dia_fit
  * (DIA_OP_FIT; DIA_OP_FIT_CLIPPED when opts->max_outer > 1) need for an image
- * of rows x cols with leading dimension ld and an m x m kernel.
+ * of rows x cols with leading dimension ld and an m x m kernel
+ * (DIA_OP_COVARIANCE: n = m*m + 1 parameters; rows, cols and ld are not used).
  * Returns DIA_E_ARG / DIA_E_SIZE on bad input. */
 int dia_workspace_size(int32_t op, int32_t rows, int32_t cols, int64_t ld, int32_t m, size_t* bytes /*host*/);
 
@@ -157,6 +159,24 @@ typedef struct {
     int32_t poll_every;    /* graph replays between host checks of the done flag          */
     int32_t max_newton;    /* exact-Hessian Newton steps after each fit (0 = none)         */
 } dia_fit_opts;
+
+/* Covariance of the fitted parameters from the observed Fisher information
+ * (Section 2.5, eq. covmatrix): for F = dia_hessian's H at the fit (device
+ * double[n*n], n = m*m + 1, symmetric; not modified),
+ *   cov     = F^-1                           (device double[n*n], row-major)
+ *   sigma   = sqrt(diag cov), the Cramer-Rao error of each parameter (eq. deltatheta)
+ *                                            (device double[n])
+ *   sigma_P = sqrt(sum over kernel taps i, j of cov[i][j]), the error of the
+ *             photometric scale factor P = sum K   (device double[1])
+ *   info    = [valid, ln det cov, smallest Cholesky pivot of F]   (device double[3])
+ * valid = 1 when F is positive definite (its Cholesky factorisation exists),
+ * which is the paper's validity test of cov: then every eigenvalue of cov and
+ * its determinant are positive.  valid = 0 means cov is not a covariance
+ * matrix; the other outputs are then NaN.  Computed in FP64: F = L L^T in one
+ * workgroup, W = L^-1, cov = W^T W.  Workspace: DIA_OP_COVARIANCE (two n x n
+ * FP64 matrices).  Asynchronous on stream. */
+int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, double* sigma_P, double* info, void* ws,
+                   size_t ws_bytes, void* stream);
 
 /* Fill opts with the paper's settings (Section 2.9): flat init, lr_K 1e-3,
  * lr_B0 10, tol_switch 1e-6, L-BFGS lr 1 with history 10, tol_change 1e-8,

@@ -7,6 +7,8 @@ memory and the current stream.  The names follow the C ABI in include/dia.h:
 * ``loss_grad(R, I, theta, m, objective)``     fused forward + objective + backward
 * ``fit(R, I, m, objective, **opts)``           Adam then L-BFGS on the device
 * ``DIALoss.apply(theta, R, I, m, objective)``  autograd wrapper around ``loss_grad``
+* ``hessian(R, I, theta, m, objective)``         observed Fisher information (Section 2.5)
+* ``covariance(F, m)``                          its inverse, standard errors, validity flag
 
 If libdia.so has not been built this module raises ImportError: there is no
 fallback path.
@@ -33,7 +35,7 @@ OK, W_NOT_CONVERGED = 0, 1
 E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_NONFINITE = -1, -2, -3, -4, -5
 RHO = {"gauss": 0, "huber": 1, "cauchy": 2}
 VAR = {"weights": 0, "ccd_data": 1, "ccd_model": 2, "emccd_data": 3, "emccd_model": 4}
-OP_MODEL, OP_LOSS_GRAD, OP_FIT, OP_FIT_CLIPPED, OP_HESSIAN = 0, 1, 2, 3, 4
+OP_MODEL, OP_LOSS_GRAD, OP_FIT, OP_FIT_CLIPPED, OP_HESSIAN, OP_COVARIANCE = 0, 1, 2, 3, 4, 5
 INIT = {"flat": 0, "gauss": 1, "user": 2}
 STOP = {0: "none", 1: "rel_change", 2: "gradient", 3: "line_search", 4: "cap", 5: "newton"}
 
@@ -80,6 +82,7 @@ _lib.dia_workspace_size.argtypes = [_i32, _i32, _i32, _i64, _i32, ctypes.POINTER
 _lib.dia_model.argtypes = [_Image, _vp, _i32, _vp, _i64, _vp]
 _lib.dia_loss_grad.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_hessian.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _sz, _vp]
+_lib.dia_covariance.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_opts_default.argtypes = [ctypes.POINTER(_FitOpts)]
 _lib.dia_fit_opts_default.restype = None
 _lib.dia_fit.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _i32, ctypes.POINTER(_FitOpts), _vp,
@@ -90,15 +93,15 @@ _lib.dia_loss_grad_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i3
                                        _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, ctypes.POINTER(_Objective),
                                  ctypes.POINTER(_FitOpts), _i32, _vp, ctypes.POINTER(_FitResult), _vp, _sz, _vp]
-for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_hessian", "dia_fit", "dia_batched_workspace_size",
-           "dia_loss_grad_batched", "dia_fit_batched"):
+for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_hessian", "dia_covariance", "dia_fit",
+           "dia_batched_workspace_size", "dia_loss_grad_batched", "dia_fit_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 PREC = {"fp32": 0, "bf16x3": 1}
 
 EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad", "dia_hessian",
-           "dia_fit_opts_default", "dia_fit", "dia_batched_workspace_size", "dia_loss_grad_batched",
-           "dia_fit_batched")
+           "dia_covariance", "dia_fit_opts_default", "dia_fit", "dia_batched_workspace_size",
+           "dia_loss_grad_batched", "dia_fit_batched")
 
 
 class DIAError(RuntimeError):
@@ -244,6 +247,43 @@ def hessian(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objec
     _check(_lib.dia_hessian(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, out.data_ptr(), p, nb,
                             _stream(R.device)), "dia_hessian")
     return out
+
+
+@dataclass
+class Covariance:
+    """Section 2.5 at a fit: cov = F^-1, sigma = sqrt(diag cov), sigma_P = the error of P = sum K;
+    valid is the positive-definiteness test of cov (logdet = ln det cov, min_pivot = the smallest
+    Cholesky pivot of F); the tensors are NaN when valid is False."""
+    cov: torch.Tensor
+    sigma: torch.Tensor
+    sigma_P: float
+    valid: bool
+    logdet: float
+    min_pivot: float
+
+
+def covariance(F: torch.Tensor, m: int, workspace: Optional[Workspace] = None) -> Covariance:
+    """Covariance estimate and validity test from an observed Fisher information F (float64, n x n)."""
+    n = m * m + 1
+    if F.dtype != torch.float64 or tuple(F.shape) != (n, n) or not F.is_contiguous() or F.device.type != "cuda":
+        raise ValueError("F must be a contiguous float64 device tensor of shape (m*m+1, m*m+1)")
+    cov = torch.empty((n, n), dtype=torch.float64, device=F.device)
+    sigma = torch.empty(n, dtype=torch.float64, device=F.device)
+    sP = torch.empty(1, dtype=torch.float64, device=F.device)
+    info = torch.empty(3, dtype=torch.float64, device=F.device)
+    ws = workspace or Workspace(F.device)
+    p, nb = ws.get(workspace_size(OP_COVARIANCE, 1, 1, 1, m))
+    _check(_lib.dia_covariance(F.data_ptr(), m, cov.data_ptr(), sigma.data_ptr(), sP.data_ptr(), info.data_ptr(),
+                               p, nb, _stream(F.device)), "dia_covariance")
+    h = info.cpu().tolist()
+    return Covariance(cov=cov, sigma=sigma, sigma_P=float(sP.item()), valid=h[0] == 1.0, logdet=h[1],
+                      min_pivot=h[2])
+
+
+def uncertainty(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
+                workspace: Optional[Workspace] = None) -> Covariance:
+    """Section 2.5 at theta: the covariance of the observed Fisher information (the exact Hessian)."""
+    return covariance(hessian(R, I, theta, m, objective, workspace), m, workspace)
 
 
 @dataclass

@@ -278,8 +278,19 @@ const char* dia_status_string(int status) {
     }
 }
 
+// the covariance region: F factored in place, then W = L^-1
+static size_t covariance_bytes(int m) {
+    const size_t n = (size_t)m * m + 1;
+    return 2 * align_up(sizeof(double) * n * n);
+}
+
 int dia_workspace_size(int32_t op, int32_t rows, int32_t cols, int64_t ld, int32_t m, size_t* bytes) {
     if (bytes == nullptr) return DIA_E_ARG;
+    if (op == DIA_OP_COVARIANCE) {
+        if (m < 1 || m > DIA_MAX_M || m % 2 == 0) return DIA_E_SIZE;
+        *bytes = covariance_bytes(m);
+        return DIA_OK;
+    }
     if (op < DIA_OP_MODEL || op > DIA_OP_HESSIAN) return DIA_E_ARG;
     if (rows < 1 || cols < 1 || ld < cols) return DIA_E_SIZE;
     const int c = check_m(m, rows, cols);
@@ -363,6 +374,21 @@ int dia_hessian(dia_image R, dia_image I, const dia_objective* obj, const float*
     } catch (...) {
         return DIA_E_HIP;
     }
+}
+
+int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, double* sigma_P, double* info, void* ws,
+                   size_t ws_bytes, void* stream) {
+    if (m < 1 || m > DIA_MAX_M || m % 2 == 0) return DIA_E_SIZE;
+    if (F == nullptr || cov == nullptr || sigma == nullptr || sigma_P == nullptr || info == nullptr) return DIA_E_ARG;
+    const int c = check_ws(ws, ws_bytes, covariance_bytes(m));
+    if (c != DIA_OK) return c;
+    const int n = m * m + 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* A = static_cast<double*>(ws);
+    double* W = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up(sizeof(double) * (size_t)n * n));
+    if (hipMemcpyAsync(A, F, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return DIA_E_HIP;
+    return launch_covariance(A, n, W, cov, sigma, sigma_P, info, s) == hipSuccess ? DIA_OK : DIA_E_HIP;
 }
 
 void dia_fit_opts_default(dia_fit_opts* o) {

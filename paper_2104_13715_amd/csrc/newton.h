@@ -11,6 +11,10 @@ hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int 
                                 hipStream_t s);
 hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, const double* th, double* d, double* info,
                              hipStream_t s);
+// Sigma = F^-1 with the validity flag (Section 2.5); A holds F on entry (factored in place),
+// W (n x n) is scratch; S (n x n), sigma (n), sigma_P (1), info (3) are the outputs.
+hipError_t launch_covariance(double* A, int n, double* W, double* S, double* sigma, double* sigma_P, double* info,
+                             hipStream_t s);
 hipError_t launch_newton_trial(const double* th, const double* d, double alpha, float* theta, double* theta64, int n,
                                hipStream_t s);
 hipError_t launch_set_x(FitState* st, FitVecs v, const double* th, int n, double L, hipStream_t s);

@@ -72,6 +72,37 @@ __device__ double chol_block_max(double v, double* sh) {
 // when factor != 0; then d = -(L L^T)^-1 g.  info[0] = 1 if A was not positive definite,
 // info[1] = -g.d (the Newton decrement squared), info[2] = max|d_i| / max|th_i|,
 // info[3] = max_i |d_i| / (FP32 spacing at th_i).
+// In place: column k of L (A = L L^T) into row k of A (A[k*n + i] = L[i][k], i >= k), one
+// workgroup, left-looking.  Returns false (in every thread) when A is not positive definite.
+// col: shared scratch of n doubles.
+__device__ bool chol_factor_block(double* A, int n, double* col, int* bad) {
+    const int tid = threadIdx.x;
+    if (tid == 0) *bad = 0;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        for (int k = tid; k < j; k += kCholThreads) col[k] = A[(long long)k * n + j];
+        __syncthreads();
+        for (int i = j + tid; i < n; i += kCholThreads) {
+            double s = A[(long long)j * n + i];
+            for (int k = 0; k < j; ++k) s -= A[(long long)k * n + i] * col[k];
+            A[(long long)j * n + i] = s;
+        }
+        __syncthreads();
+        const double dj = A[(long long)j * n + j];
+        if (!(dj > 0.0)) {
+            if (tid == 0) *bad = 1;
+            break;
+        }
+        const double sq = sqrt(dj);
+        __syncthreads();
+        for (int i = j + tid; i < n; i += kCholThreads)
+            A[(long long)j * n + i] = (i == j) ? sq : A[(long long)j * n + i] / sq;
+        __syncthreads();
+    }
+    __syncthreads();
+    return *bad == 0;
+}
+
 __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int n, int factor, const double* g,
                                                                   const double* th, double* d, double* info) {
     __shared__ double col[kMaxTheta];
@@ -80,28 +111,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int
     const int tid = threadIdx.x;
     if (tid == 0) bad = 0;
     __syncthreads();
-    if (factor) {
-        for (int j = 0; j < n; ++j) {
-            for (int k = tid; k < j; k += kCholThreads) col[k] = A[(long long)k * n + j];
-            __syncthreads();
-            for (int i = j + tid; i < n; i += kCholThreads) {
-                double s = A[(long long)j * n + i];
-                for (int k = 0; k < j; ++k) s -= A[(long long)k * n + i] * col[k];
-                A[(long long)j * n + i] = s;
-            }
-            __syncthreads();
-            const double dj = A[(long long)j * n + j];
-            if (!(dj > 0.0)) {
-                if (tid == 0) bad = 1;
-                break;
-            }
-            const double sq = sqrt(dj);
-            __syncthreads();
-            for (int i = j + tid; i < n; i += kCholThreads)
-                A[(long long)j * n + i] = (i == j) ? sq : A[(long long)j * n + i] / sq;
-            __syncthreads();
-        }
-    }
+    if (factor) chol_factor_block(A, n, col, &bad);
     __syncthreads();
     if (bad) {
         if (tid == 0) {
@@ -151,6 +161,108 @@ __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int
         info[2] = tmax > 0.0 ? dmax / tmax : dmax;
         info[3] = qmax;
     }
+}
+
+// ---------------------------------------------------------------- covariance (Section 2.5)
+// Sigma = F^-1 for the observed Fisher information F = L L^T: W = L^-1 (lower triangular), then
+// Sigma = W^T W.  info[0] = 1 when F (hence Sigma) is positive definite, the paper's validity
+// test of Sigma (a positive definite matrix has every eigenvalue and its determinant positive);
+// info[1] = ln det Sigma = -2 sum_k ln L_kk; info[2] = the smallest pivot L_kk^2.  When F is not
+// positive definite the outputs are NaN.
+__global__ __launch_bounds__(kCholThreads) void chol_factor_kernel(double* A, int n, double* info) {
+    __shared__ double col[kMaxTheta];
+    __shared__ double sh[32];
+    __shared__ int bad;
+    const bool ok = chol_factor_block(A, n, col, &bad);
+    double ld = 0.0, inv_pmin = 0.0;  // the smallest pivot through the largest reciprocal (all positive)
+    if (ok)
+        for (int k = threadIdx.x; k < n; k += kCholThreads) {
+            const double l = A[(long long)k * n + k];
+            ld += log(l);
+            inv_pmin = fmax(inv_pmin, 1.0 / (l * l));
+        }
+    ld = chol_block_sum(ld, sh);
+    inv_pmin = chol_block_max(inv_pmin, sh);
+    if (threadIdx.x == 0) {
+        info[0] = ok ? 1.0 : 0.0;
+        info[1] = ok ? -2.0 * ld : __builtin_nan("");
+        info[2] = ok ? 1.0 / inv_pmin : __builtin_nan("");
+    }
+}
+
+// Column j of W = L^-1 (one workgroup per column), row-major W[i*n + j], zero above the diagonal:
+// w_k = (delta_jk - sum_{j <= l < k} L[k][l] w_l) / L[k][k] for k = j, j+1, ... (the running sums
+// are updated as each w_k is found).
+__global__ __launch_bounds__(256) void tri_inverse_kernel(const double* A, int n, double* W, const double* info) {
+    __shared__ double acc[kMaxTheta];
+    const int j = blockIdx.x, tid = threadIdx.x;
+    if (info[0] != 1.0) {
+        for (int i = tid; i < n; i += 256) W[(long long)i * n + j] = __builtin_nan("");
+        return;
+    }
+    for (int i = tid; i < n; i += 256) {
+        acc[i] = 0.0;
+        if (i < j) W[(long long)i * n + j] = 0.0;
+    }
+    __syncthreads();
+    for (int k = j; k < n; ++k) {
+        const double wk = ((k == j ? 1.0 : 0.0) - acc[k]) / A[(long long)k * n + k];
+        if (tid == 0) W[(long long)k * n + j] = wk;
+        for (int i = k + 1 + tid; i < n; i += 256) acc[i] += A[(long long)k * n + i] * wk;
+        __syncthreads();
+    }
+}
+
+// Sigma[i][j] = sum_k W[k][i] W[k][j] (W lower triangular, so k >= max(i, j)); 32 x 32 output
+// tiles, k in chunks of 32 staged in LDS.
+constexpr int kCovTile = 32;
+__global__ __launch_bounds__(256) void cov_syrk_kernel(const double* W, int n, double* S) {
+    __shared__ double wa[kCovTile][kCovTile + 1];
+    __shared__ double wb[kCovTile][kCovTile + 1];
+    const int i0 = blockIdx.y * kCovTile, j0 = blockIdx.x * kCovTile;
+    const int tx = threadIdx.x % kCovTile, ty = threadIdx.x / kCovTile;  // ty in 0..7: 4 rows each
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = (i0 > j0 ? i0 : j0); k0 < n; k0 += kCovTile) {
+        for (int r = ty; r < kCovTile; r += 8) {
+            const int k = k0 + r;
+            wa[r][tx] = (k < n && i0 + tx < n) ? W[(long long)k * n + i0 + tx] : 0.0;
+            wb[r][tx] = (k < n && j0 + tx < n) ? W[(long long)k * n + j0 + tx] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int r = 0; r < kCovTile; ++r) {
+            const double b = wb[r][tx];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += wa[r][ty + 8 * q] * b;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + ty + 8 * q, j = j0 + tx;
+        if (i < n && j < n) S[(long long)i * n + j] = acc[q];
+    }
+}
+
+// sigma_p = sqrt(Sigma_pp); sigma_P^2 = 1^T Sigma_KK 1 = sum_k (sum_{i < n-1} W[k][i])^2 (the kernel
+// block of Sigma = W^T W), summed in a fixed order.
+__global__ __launch_bounds__(256) void cov_finish_kernel(const double* S, const double* W, int n, double* sigma,
+                                                         double* sigma_P, const double* info) {
+    __shared__ double sh[4];
+    const int tid = threadIdx.x;
+    const bool ok = info[0] == 1.0;
+    for (int i = tid; i < n; i += 256) sigma[i] = ok ? sqrt(S[(long long)i * n + i]) : __builtin_nan("");
+    double part = 0.0;
+    if (ok)
+        for (int k = tid; k < n; k += 256) {
+            double v = 0.0;
+            for (int i = 0; i < n - 1 && i <= k; ++i) v += W[(long long)k * n + i];
+            part += v * v;
+        }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((tid & 63) == 0) sh[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) *sigma_P = ok ? sqrt((sh[0] + sh[1]) + (sh[2] + sh[3])) : __builtin_nan("");
 }
 
 // theta_t = th + alpha d, stored as the FP32 parameters (and their FP64 widening) to evaluate.
@@ -216,6 +328,17 @@ hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int 
 hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, const double* th, double* d, double* info,
                              hipStream_t s) {
     hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(kCholThreads), 0, s, A, n, factor, g, th, d, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_covariance(double* A, int n, double* W, double* S, double* sigma, double* sigma_P, double* info,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(kCholThreads), 0, s, A, n, info);
+    hipLaunchKernelGGL(tri_inverse_kernel, dim3(n), dim3(256), 0, s, (const double*)A, n, W, (const double*)info);
+    const int nt = (n + kCovTile - 1) / kCovTile;
+    hipLaunchKernelGGL(cov_syrk_kernel, dim3(nt, nt), dim3(256), 0, s, (const double*)W, n, S);
+    hipLaunchKernelGGL(cov_finish_kernel, dim3(1), dim3(256), 0, s, (const double*)S, (const double*)W, n, sigma,
+                       sigma_P, (const double*)info);
     return hipGetLastError();
 }
 

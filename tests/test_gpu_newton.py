@@ -144,3 +144,86 @@ def test_fit_config2_full_size(dia):
     o_or, o_gpu = objs(dia, "gauss", "ccd_data", p.sigma0_adu, p.gain)
     res = dia.fit(gpu(p.R), gpu(p.I), p.m, o_gpu)
     check_fit(res, oracle.solve(p.R, p.I, p.m, o_or), p.m)
+
+
+# ------------------------------------------------------------------ covariance (Section 2.5)
+def check_covariance(dia, F, m, tag):
+    """GPU covariance of F against the oracle's (numpy inverse, eigenvalue and determinant tests).
+    Bar: the inverse of an FP64 matrix is accurate to about cond(F) * 1e-16 relative, so
+    |d cov| / |cov| <= 1e-13 cond(F) (Frobenius), and the same for sigma and sigma_P."""
+    ref = oracle.covariance(F)
+    out = dia.covariance(gpu(F, torch.float64), m)
+    torch.cuda.synchronize()
+    cond = np.linalg.cond(F)
+    tol = max(1e-13 * cond, 1e-12)
+    cov = out.cov.cpu().numpy()
+    e_cov = np.linalg.norm(cov - ref["cov"]) / np.linalg.norm(ref["cov"])
+    e_sig = np.max(np.abs(out.sigma.cpu().numpy() - ref["sigma"]) / ref["sigma"])
+    e_P = abs(out.sigma_P - ref["sigma_P"]) / ref["sigma_P"]
+    print(f"covariance {tag} n={F.shape[0]} cond {cond:.1e}: cov {e_cov:.1e} sigma {e_sig:.1e} sigma_P {e_P:.1e} "
+          f"logdet {out.logdet:.6f} vs {ref['logdet']:.6f}")
+    assert out.valid and ref["valid"]
+    assert e_cov <= tol and e_sig <= tol and e_P <= tol
+    assert abs(out.logdet - ref["logdet"]) <= 1e-9 * max(1.0, abs(ref["logdet"]))
+    assert out.min_pivot > 0.0
+    return out
+
+
+def test_covariance_of_oracle_fisher_information_c1(dia, c1):
+    m = c1.m
+    o_or, _ = objs(dia, "gauss", "ccd_data", c1.sigma0_adu, c1.gain)
+    theta = oracle.solve(c1.R, c1.I, m, o_or)
+    check_covariance(dia, oracle.hessian(c1.R, c1.I, theta, m, o_or), m, "C1")
+
+
+def test_covariance_one_tap_closed_form(dia):
+    rng = np.random.default_rng(41)
+    R = rng.uniform(10.0, 500.0, (40, 37))
+    w = rng.uniform(0.5, 2.0, R.shape)
+    o_or = oracle.Objective(rho="gauss", var="weights", weights=w)
+    F = oracle.hessian(R, np.zeros(R.shape), np.array([0.9, 2.0]), 1, o_or)
+    out = check_covariance(dia, F, 1, "m=1")
+    a, b, c = np.sum(w * R * R), np.sum(w * R), np.sum(w)
+    assert abs(out.sigma_P - np.sqrt(c / (a * c - b * b))) <= 1e-10 * out.sigma_P
+
+
+def test_uncertainty_end_to_end_at_the_fit(dia, c1):
+    # GPU Hessian + GPU covariance at the oracle's fit against the oracle's Hessian and covariance
+    m = c1.m
+    o_or, o_gpu = objs(dia, "cauchy", "ccd_model", c1.sigma0_adu, c1.gain)
+    theta = oracle.solve(c1.R, c1.I, m, o_or).astype(np.float32)
+    out = dia.uncertainty(gpu(c1.R), gpu(c1.I), gpu(theta), m, o_gpu)
+    ref = oracle.covariance(oracle.hessian(c1.R, c1.I, theta.astype(np.float64), m, o_or))
+    e_sig = np.max(np.abs(out.sigma.cpu().numpy() - ref["sigma"]) / ref["sigma"])
+    e_P = abs(out.sigma_P - ref["sigma_P"]) / ref["sigma_P"]
+    print(f"uncertainty C1 cauchy: sigma {e_sig:.1e} sigma_P {e_P:.1e} (sigma_P {out.sigma_P:.3e})")
+    assert out.valid and e_sig <= 1e-6 and e_P <= 1e-6
+
+
+@pytest.mark.parametrize("m,side", [(19, 120), (25, 110)])
+def test_covariance_at_full_parameter_count(dia, m, side):
+    # n = 362 and 626: the GPU Hessian of a random problem, then the covariance of that matrix
+    rng = np.random.default_rng(42 + m)
+    R = rng.uniform(50.0, 3000.0, (side, side)).astype(np.float32)
+    K = rng.uniform(0.0, 1.0, (m, m))
+    K /= K.sum()
+    theta = np.r_[K.ravel(), 5.0].astype(np.float32)
+    I = (oracle.model(R, theta, m) + rng.normal(0.0, 10.0, (side - m + 1, side - m + 1)))
+    Ifull = np.zeros((side, side), np.float32)
+    h = (m - 1) // 2
+    Ifull[h:side - h, h:side - h] = I
+    _, o_gpu = objs(dia, "gauss", "ccd_data", 8.0, 1.5)
+    F = dia.hessian(gpu(R), gpu(Ifull), gpu(theta), m, o_gpu).cpu().numpy()
+    check_covariance(dia, F, m, f"m={m}")
+
+
+def test_covariance_flags_a_matrix_that_is_not_positive_definite(dia):
+    m = 3
+    rng = np.random.default_rng(43)
+    A = rng.normal(size=(10, 10))
+    F = A @ A.T + 10.0 * np.eye(10)
+    F[4, 4] = -F[4, 4]
+    assert not oracle.covariance(F)["valid"]
+    out = dia.covariance(gpu(F, torch.float64), m)
+    assert not out.valid
+    assert torch.isnan(out.cov).all() and torch.isnan(out.sigma).all() and np.isnan(out.sigma_P)
