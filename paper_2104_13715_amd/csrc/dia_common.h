@@ -300,6 +300,7 @@ struct HessArgs {
     int rows, cols;
     double* partial;   // [splits][n_pairblocks][32]
 };
+constexpr int kHessBlockElems = 64 * 64;  // doubles per (split, tap-region pair) block of the Hessian partials
 int hess_pair_blocks(int m);
 int hess_splits(int m, int rows, int cols);
 hipError_t launch_hess(int m, const HessArgs& a, hipStream_t s);

@@ -16,7 +16,7 @@ NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own
     L.h = off;
     off = align_up(off + sizeof(double) * (size_t)hv_px);
     L.hpart = off;
-    off = align_up(off + sizeof(double) * (size_t)L.splits * L.npb * 32);
+    off = align_up(off + sizeof(double) * (size_t)L.splits * L.npb * kHessBlockElems);
     if (own_H) {
         L.H = off;
         off = align_up(off + sizeof(double) * (size_t)n * n);

@@ -12,32 +12,24 @@ namespace dia {
 
 constexpr int kCholThreads = 1024;
 
-// H[t1][t2] for the kernel taps from the split partials (fixed order), the background row from
+// H[t1][t2] for the kernel taps from the split partials (fixed order; element (min, max) of the
+// region-pair blocks of 64 x 64, so H is exactly symmetric), the background row from
 // hv = [sum h R_(p+t) (t < m*m), sum h].
 __global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partial, int splits, int npb, int m,
                                                             const double* hv, double* H) {
-    const int n = m * m + 1;
-    const int nb1 = (m + 3) / 4, nb2 = (m + 7) / 8;
+    constexpr int RG = 64;
+    const int n = m * m + 1, T = m * m;
+    const int nr = (T + RG - 1) / RG;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid < (long long)npb * 32) {
-        const int pb = (int)(gid / 32), k = (int)(gid % 32);
-        const int per_pa = nb1 * nb2;
-        int pa = pb / per_pa;
-        const int bb = pb % per_pa;
-        const int b1 = (bb / nb2) * 4 + k / 8, b2 = (bb % nb2) * 8 + k % 8;
-        int a1 = 0;
-        while (pa >= m - a1) {
-            pa -= m - a1;
-            ++a1;
-        }
-        const int a2 = a1 + pa;
-        if (b1 < m && b2 < m && !(a1 == a2 && b1 > b2)) {
-            double s = 0.0;
-            for (int sp = 0; sp < splits; ++sp) s += partial[((long long)sp * npb + pb) * 32 + k];
-            const int t1 = a1 * m + b1, t2 = a2 * m + b2;
-            H[(long long)t1 * n + t2] = s;
-            H[(long long)t2 * n + t1] = s;
-        }
+    if (gid < (long long)T * T) {
+        const int t1 = (int)(gid / T), t2 = (int)(gid % T);
+        const int lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
+        const int ra = lo / RG, rb = hi / RG;
+        const int pb = ra * nr - ra * (ra - 1) / 2 + (rb - ra);
+        const int k = (lo - ra * RG) * RG + (hi - rb * RG);
+        double s = 0.0;
+        for (int sp = 0; sp < splits; ++sp) s += partial[((long long)sp * npb + pb) * (RG * RG) + k];
+        H[(long long)t1 * n + t2] = s;
     }
     if (gid < n) {
         const int t = (int)gid;
@@ -319,7 +311,7 @@ __global__ __launch_bounds__(256) void theta_from_x_kernel(const FitState* st, F
 
 hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
                                 hipStream_t s) {
-    const long long work = std::max<long long>((long long)npb * 32, m * m + 1);
+    const long long work = std::max<long long>((long long)m * m * m * m, m * m + 1);
     const int blocks = (int)((work + 255) / 256);
     hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, hv, H);
     return hipGetLastError();
