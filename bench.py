@@ -44,11 +44,14 @@ def make_batch(args, sf):
     built in parallel worker processes; each has its own random stream, so the batch is the same)."""
     t0 = time.time()
     workers = min(16, os.cpu_count() or 1)
-    if args.batch_workload == "uneven":
+    if args.batch_workload == "emccd":
+        b = sf.config_emccd(n_epochs=args.emccd_epochs, size=max(int(x) for x in args.emccd_sizes.split(",")),
+                            m=max(int(x) for x in args.emccd_m.split(",")), workers=workers)
+    elif args.batch_workload == "uneven":
         b = sf.config4(n_epochs=args.batch_epochs, workers=workers)
     else:
         b = sf.config5(n_epochs=args.batch_epochs, workers=workers)
-    print(f"# generated {args.batch_epochs}-epoch batch in {time.time() - t0:.1f}s ({workers} processes)",
+    print(f"# generated {len(b.epochs)}-epoch batch in {time.time() - t0:.1f}s ({workers} processes)",
           file=sys.stderr, flush=True)
     return b
 
@@ -118,6 +121,80 @@ def batched_section(args, b, dia, torch, dev, np):
     return out
 
 
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else float("nan")
+
+
+def emccd_section(args, b, dia, torch, dev, np):
+    """Many small aligned pairs shaped like the EMCCD speed test of Section 5.1: n targets of one field
+    against the sharpest image as reference, Huber loss with the EMCCD model variance and the flat
+    field, central crops of each side in --emccd-sizes, each kernel size in --emccd-m.  Per image:
+    the single-pair fit's solution time (median and 16th / 84th percentiles over the targets, the
+    paper's statistic) from a flat box-car and from a Gaussian of width sqrt(phi_I^2 - phi_R^2); the
+    Spearman rank correlation of solution time with phi_I; then the whole set as one batched fit in
+    each precision (fits/s)."""
+    from scipy.stats import spearmanr
+    full = b.R.shape[0]
+    phi_I = np.asarray(b.meta["phi_I"])
+    phi_K = np.sqrt(np.maximum(phi_I ** 2 - b.meta["phi_R"] ** 2, 0.25))
+    ws = dia.Workspace(dev)
+    out = {"workload": (f"{len(b.epochs)} targets of one {full}x{full} field (2000 stars, Gaussian PSF of width "
+                        f"{b.meta['phi_R']}) and the shared flat, Huber loss with EMCCD model variance "
+                        f"(E = {b.meta['excess']}, G = {b.gain})"), "cases": []}
+    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    for size in [int(x) for x in args.emccd_sizes.split(",")]:
+        r0 = (full - size) // 2
+        sl = (slice(r0, r0 + size), slice(r0, r0 + size))
+        R = torch.from_numpy(np.ascontiguousarray(b.R[sl])).to(dev)
+        Fc = torch.from_numpy(np.ascontiguousarray(b.meta["flat"][sl])).to(dev)
+        Is = [torch.from_numpy(np.ascontiguousarray(e.I[sl])).to(dev) for e in b.epochs]
+        obj = dia.Objective(rho="huber", var="emccd_model", gain=b.gain, excess=b.meta["excess"], flat=Fc)
+        for m in [int(x) for x in args.emccd_m.split(",")]:
+            case = {"size": size, "m": m}
+            dia.fit(R, Is[0], m, obj, workspace=ws)  # warm the tile-shape choice and the workspace
+            torch.cuda.synchronize()
+            for init in ("flat", "gauss"):
+                t_ms, n_ev = [], []
+                for k, I in enumerate(Is):
+                    a, z = ev()
+                    a.record()
+                    r = dia.fit(R, I, m, obj, workspace=ws, init=init, init_phi=float(phi_K[k]))
+                    z.record()
+                    torch.cuda.synchronize()
+                    t_ms.append(a.elapsed_time(z))
+                    n_ev.append(r.n_eval)
+                rho_s = spearmanr(t_ms, phi_I).statistic
+                case[f"single_{init}"] = {"median_ms": round(_pct(t_ms, 50), 2), "p16_ms": round(_pct(t_ms, 16), 2),
+                                          "p84_ms": round(_pct(t_ms, 84), 2),
+                                          "evals_median": int(_pct(n_ev, 50)), "evals_p16": int(_pct(n_ev, 16)),
+                                          "evals_p84": int(_pct(n_ev, 84)), "spearman_time_phi_I": round(float(rho_s), 2)}
+            eps = [dia.Epoch(I=I, flat=Fc) for I in Is]
+            n = len(eps)
+            yy, xx = np.mgrid[:m, :m] - (m - 1) / 2.0
+            kg = np.exp(-0.5 * (xx[None] ** 2 + yy[None] ** 2) / phi_K[:, None, None] ** 2)
+            kg /= kg.sum(axis=(1, 2), keepdims=True)
+            th_g = torch.from_numpy(kg.reshape(n, -1).astype(np.float32)).to(dev)
+            th_g = torch.cat([th_g, torch.stack([I.median() for I in Is])[:, None]], 1).contiguous()
+            for prec in ("fp32", "bf16x3"):
+                for init in ("flat", "gauss"):
+                    th0 = th_g.clone() if init == "gauss" else None
+                    torch.cuda.synchronize()
+                    a, z = ev()
+                    a.record()
+                    th, res, st = dia.fit_batched(R, eps, m, obj, theta=th0, precision=prec, workspace=ws)
+                    z.record()
+                    torch.cuda.synchronize()
+                    t = a.elapsed_time(z) / 1e3
+                    e_ = [r.n_eval for r in res]
+                    case[f"batched_{prec}_{init}"] = {"fits_per_s": round(n / t, 1), "fit_s": round(t, 3),
+                                                      "evals_median": int(_pct(e_, 50)), "evals_max": int(max(e_)),
+                                                      "status": st}
+            out["cases"].append(case)
+            print(f"# emccd {case}", file=sys.stderr, flush=True)
+    return out
+
+
 def traffic_from_profile(kernel_sig: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it matches this kernel build."""
     path = os.path.join(ROOT, "profiles", "traffic_fused_eval_4096_m19.json")
@@ -153,9 +230,13 @@ def main() -> int:
     ap.add_argument("--batch-fp32-epochs", type=int, default=32,
                     help="the plain form of the batched workload runs on this many of its epochs")
     ap.add_argument("--batch-precisions", default="bf16x3,fp32")
-    ap.add_argument("--batch-workload", default="shared", choices=["shared", "uneven"],
+    ap.add_argument("--batch-workload", default="shared", choices=["shared", "uneven", "emccd"],
                     help="shared: epochs of 2048^2 on one shared window (m = 25); uneven: sides 512..2048 cut "
-                         "from a shared 2048^2 reference (m = 17, plain form only)")
+                         "from a shared 2048^2 reference (m = 17, plain form only); emccd: many small aligned "
+                         "pairs, Huber loss with the EMCCD noise model (printed alone)")
+    ap.add_argument("--emccd-epochs", type=int, default=158)
+    ap.add_argument("--emccd-sizes", default="482,242", help="central crop sides of the emccd workload")
+    ap.add_argument("--emccd-m", default="19,25", help="kernel sizes of the emccd workload")
     ap.add_argument("--only-batched", action="store_true", help="print the batched section alone")
     ap.add_argument("--profile-batched", default="",
                     help="only run --kernel-reps batched evaluations in this precision (for hardware-counter runs)")
@@ -180,6 +261,9 @@ def main() -> int:
     import paper_2104_13715_amd as dia
 
     dev = torch.device("cuda:0")
+    if args.batch_workload == "emccd":
+        print(json.dumps({"emccd": emccd_section(args, batch, dia, torch, dev, np)}))
+        return 0
     if args.only_batched:
         print(json.dumps({"batched": batched_section(args, batch, dia, torch, dev, np)}))
         return 0

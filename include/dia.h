@@ -190,7 +190,8 @@ int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, doubl
  * FP64 Hessian H = sum_p h_p x_p x_p^T (x_p the pixel's design row, h_p the
  * per-pixel curvature: exact for a Gaussian objective with fixed variance,
  * the Gauss-Newton / IRLS weight otherwise) by Cholesky, with a backtracking
- * line search on the loss; it stops when the Newton decrement -g.d is below
+ * line search on the loss (trial points evaluated at their unrounded FP64
+ * values); it stops when the Newton decrement -g.d is below
  * the FP64 resolution of the loss, the step below the FP32 resolution of
  * theta, or an accepted step lowers the loss by no more than 1e-13 |L| (the
  * rounding level of the loss summed over millions of pixels: the gradient
@@ -198,7 +199,10 @@ int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, doubl
 void dia_fit_opts_default(dia_fit_opts* opts /*host*/);
 
 typedef struct {
-    double loss;      /* final L(theta), FP64 reduction                 */
+    /* loss, P and B0 belong to the optimiser's final FP64 iterate; the returned
+     * theta is that iterate rounded to FP32 (sum K of the rounded kernel can
+     * differ from P by up to 2^-24 sum |K|) */
+    double loss;      /* final L, FP64 reduction                        */
     double P;         /* photometric scale factor sum K, FP64 (eq. photometric_scale_factor) */
     double B0;
     int32_t n_eval;   /* objective evaluations, all outer fits          */

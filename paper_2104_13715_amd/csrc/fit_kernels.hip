@@ -712,12 +712,15 @@ __global__ __launch_bounds__(kReduceThreads) void finalize_kernel(FitState* st0,
     const FitVecs v = offset_vecs(v0, off);
     float* theta_out = theta_out0 + (long long)blockIdx.x * n;
     write_theta(st, v.x, theta_out, n, sh, nullptr);
+    // P and B0 of the FP64 iterate (the point whose loss is reported), not of its FP32 rounding:
+    // when sum |K| is large against P (an unregularised kernel whose poorly constrained modes are
+    // big), rounding every pixel to FP32 moves sum K by up to 2^-24 sum |K|
     double s = 0.0;
-    for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) s += (double)theta_out[i];
-    const double P = block_sum(s, sh);
+    for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) s += v.x[i];
+    const double P = block_sum(s, sh) / st->ref_scale;
     if (threadIdx.x == 0) {
         st->out_P = P;
-        st->out_B0 = (double)theta_out[n - 1];
+        st->out_B0 = v.x[n - 1] - st->ref_shift * P;
         st->out_loss = st->L;
     }
 }

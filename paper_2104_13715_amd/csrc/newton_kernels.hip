@@ -258,12 +258,15 @@ __global__ __launch_bounds__(256) void cov_finish_kernel(const double* S, const 
 }
 
 // theta_t = th + alpha d, stored as the FP32 parameters (and their FP64 widening) to evaluate.
+// Trial point th + alpha d.  The fused pass reads the FP64 copy, so the line search sees the loss
+// at the unrounded iterate: in an ill-conditioned fit the loss change from rounding the stiff
+// parameters to FP32 can exceed the whole decrease still available along the soft directions.
 __global__ void newton_trial_kernel(const double* th, const double* d, double alpha, float* theta, double* theta64,
                                     int n) {
     for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) {
-        const float f = (float)(th[i] + alpha * d[i]);
-        theta[i] = f;
-        theta64[i] = (double)f;
+        const double t = th[i] + alpha * d[i];
+        theta[i] = (float)t;
+        theta64[i] = t;
     }
 }
 

@@ -280,6 +280,52 @@ def config5(noise=True, n_epochs=256, ref_size=2048, workers=1) -> Batch:
     return batched(5, n_epochs, 25, ref_size, n, (ref_size, ref_size), noise=noise, workers=workers)
 
 
+# ------------------------------------------------- many small aligned pairs (the EMCCD speed test)
+EMCCD_PHI_R = 1.82   # reference PSF width (Gaussian standard deviation, pixels; Section 5.1)
+EMCCD_GAIN = 1.0     # ADU per detected photon after the EM stage
+EMCCD_EXCESS = 2.0   # excess noise factor E of the EM register
+
+
+def _emccd_epoch(e: int, R64: np.ndarray, F: np.ndarray, m: int, noise: bool):
+    """Target e: the reference broadened to a target PSF width phi_I ~ U(2.2, 4.2) px (median ~3.2;
+    widths are Gaussian standard deviations, as in Section 3.1) by a Gaussian kernel of width
+    sqrt(phi_I^2 - phi_R^2), sum ~ U(0.8, 1.2), subpixel offset ~ U(-0.3, 0.3)^2, B0 ~ U(-20, 20);
+    noise with the EMCCD variance E max(I, 0) / (G F)."""
+    er = rng_for(6, e + 1)
+    phi_I = float(er.uniform(2.2, 4.2))
+    K = kernel_gaussian(m, FWHM_PER_SIGMA * math.sqrt(phi_I ** 2 - EMCCD_PHI_R ** 2), dx=er.uniform(-0.3, 0.3),
+                        dy=er.uniform(-0.3, 0.3), total=er.uniform(0.8, 1.2))
+    B0 = float(er.uniform(-20.0, 20.0))
+    I = correlate_target(R64, K, B0)
+    if noise:
+        I = I + np.sqrt(EMCCD_EXCESS * np.clip(I, 0.0, None) / (EMCCD_GAIN * F)) * er.standard_normal(I.shape)
+    return Epoch(I=I.astype(np.float32), row0=0, col0=0, K_true=K, B0_true=B0), phi_I
+
+
+def _pool_emccd(a):
+    return _emccd_epoch(a[0], _POOL_R64[0], _POOL_R64[1], a[1], a[2])
+
+
+def config_emccd(n_epochs: int = 158, size: int = 482, m: int = 19, noise: bool = True, workers: int = 1) -> Batch:
+    """Many small aligned pairs shaped like the EMCCD speed test (Section 5.1): a size^2 field of
+    2,000 stars (fluxes log-uniform 1e2..1e5, Gaussian PSF of width phi_R, sky 200) as the shared
+    reference, one flat field F ~ U(0.95, 1.05) per pixel used by every target, and n_epochs
+    targets of the whole field.  meta holds phi_R, each target's phi_I, the flat, gain and E."""
+    n_stars = int(round(2000 * (size / 482) ** 2))
+    R = star_field(rng_for(6, 0), size, size, n_stars, 1e2, 1e5, "gauss", FWHM_PER_SIGMA * EMCCD_PHI_R, 200.0).astype(np.float32)
+    F = rng_for(6, 100000).uniform(0.95, 1.05, (size, size))
+    R64 = R.astype(np.float64)
+    if workers > 1 and n_epochs > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(min(workers, n_epochs), initializer=_pool_init, initargs=((R64, F),)) as pool:
+            out = pool.map(_pool_emccd, [(e, m, noise) for e in range(n_epochs)], chunksize=1)
+    else:
+        out = [_emccd_epoch(e, R64, F, m, noise) for e in range(n_epochs)]
+    return Batch(R=R, epochs=[o[0] for o in out], m=m, sigma0_adu=0.0, gain=EMCCD_GAIN,
+                 meta=dict(config="emccd", size=size, n_stars=n_stars, phi_R=EMCCD_PHI_R,
+                           phi_I=[o[1] for o in out], flat=F.astype(np.float32), excess=EMCCD_EXCESS))
+
+
 def paper_reference(size: int = 142, seed: int = 0, phi_R: float | None = None) -> np.ndarray:
     """Noiseless reference following Section 3.1 steps (i)-(v): Gaussian PSF with standard deviation
     phi_R ~ U(0.5, 2.5), lg star density per 100x100 px ~ U(0, 3), F^(-3/2) ~ U(1e-9, 10^-4.5),

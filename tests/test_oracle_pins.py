@@ -159,6 +159,21 @@ def test_ccd_variance_matches_generator_noise():
     assert abs(np.var(z) - 1.0) < 4 * math.sqrt(2.0 / z.size)
 
 
+def test_emccd_variance_matches_generator_noise():
+    # the many-small-pairs workload: at the true parameters the EMCCD model variance
+    # E max(M, 0) / (G F) (eq. EMCCDNM) normalises the residuals to unit variance
+    b = sf.config_emccd(n_epochs=2, size=90, m=9)
+    F = oracle.valid(b.meta["flat"].astype(np.float64), 9)
+    obj = oracle.Objective(rho="gauss", var="emccd_model", gain=b.gain, excess=b.meta["excess"], var_floor=1e-6)
+    for e in b.epochs:
+        theta = np.concatenate([e.K_true.ravel(), [e.B0_true]])
+        M = oracle.model(b.R, theta, 9)
+        v, _ = oracle.oracle._variance(obj, M, F)
+        z = (oracle.valid(e.I.astype(np.float64), 9) - M) / np.sqrt(v)
+        assert abs(np.mean(z)) < 4 / math.sqrt(z.size)
+        assert abs(np.var(z) - 1.0) < 4 * math.sqrt(2.0 / z.size)
+
+
 # --------------------------------------------------------------------- gradient and curvature
 @pytest.mark.parametrize("rho", RHOS)
 @pytest.mark.parametrize("var", VARS)
