@@ -30,6 +30,10 @@ What it computes, with the passage each part follows:
 * ``covariance``     Sec. 2.5: Sigma = F^-1 of the observed Fisher information F (eq. covmatrix),
                      standard errors sqrt(Sigma_pp) (eq. deltatheta), the error of P, and the
                      paper's validity tests of Sigma (determinant and eigenvalues positive)
+* ``laplacian``, ``penalty``  Sec. 2.7: the kernel-pixel Laplacian L (eq. laplacian) and the MAP
+                     penalty lambda N_data theta^T L^T L theta added to the loss (eq. regularised_loss);
+                     ``loss_grad``, ``hessian``, ``solve`` and ``solve_chi2`` include it when
+                     Objective.lam > 0
 
 Where the paper is silent or ambiguous, the reading taken is stated where it is used.
 Parity pins for every function live in ``tests/test_oracle_pins.py``.
@@ -158,6 +162,7 @@ class Objective:
     weights: Optional[np.ndarray] = None
     flat: Optional[np.ndarray] = None
     mask: Optional[np.ndarray] = None
+    lam: float = 0.0  # lambda of eq. regularised_loss (0 = the maximum-likelihood fit)
 
     @property
     def model_sigma(self) -> bool:
@@ -234,7 +239,8 @@ def pixel_terms(obj: Objective, Iv: np.ndarray, M: np.ndarray, m: int):
 
 
 def loss_grad(R, I, theta, m, obj: Objective):
-    """L(theta) = sum over valid unmasked pixels of l, and its gradient [dL/dK (m*m), dL/dB0]."""
+    """L(theta) = sum over valid unmasked pixels of l, and its gradient [dL/dK (m*m), dL/dB0];
+    plus the penalty of eq. regularised_loss when obj.lam > 0."""
     R = _f64(R)
     Iv = _f64(valid(_f64(I), m))
     M = model(R, theta, m)
@@ -242,7 +248,46 @@ def loss_grad(R, I, theta, m, obj: Objective):
     grad = np.empty(m * m + 1)
     grad[:m * m] = grad_kernel(R, g, m)
     grad[m * m] = np.sum(g)
-    return float(np.sum(l)), grad
+    L = float(np.sum(l))
+    if obj.lam > 0.0:
+        p, pg, _ = penalty(theta, m, obj.lam, n_data(I, m))
+        L += p
+        grad += pg
+    return L, grad
+
+
+# ----------------------------------------------------------------------------- kernel regulariser
+def laplacian(m) -> np.ndarray:
+    """Sec. 2.7, eq. laplacian: the (m*m + 1)^2 Laplacian of the graph whose nodes are the kernel
+    pixels (a-major order, as in theta) and whose edges join pixels sharing a side (the reading
+    of "adjacent": 4-neighbours).  Diagonal = number of neighbours, -1 for each adjacent pair,
+    and a zero row and column for B0."""
+    n = m * m
+    L = np.zeros((n + 1, n + 1))
+    for a in range(m):
+        for b in range(m):
+            u = a * m + b
+            for da, db in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                if 0 <= a + da < m and 0 <= b + db < m:
+                    L[u, (a + da) * m + (b + db)] = -1.0
+                    L[u, u] += 1.0
+    return L
+
+
+def n_data(I, m) -> int:
+    """N_data of eq. regularised_loss: the number of pixels in the valid region the loss sums
+    over (the reading of "number of target image pixels" consistent with the data term)."""
+    H, W = np.shape(I)
+    return (H - m + 1) * (W - m + 1)
+
+
+def penalty(theta, m, lam, N):
+    """lambda N theta^T L^T L theta, its gradient 2 lambda N L^T L theta and Hessian 2 lambda N L^T L."""
+    L = laplacian(m)
+    theta = _f64(theta)
+    Lt = L @ theta
+    Hp = 2.0 * lam * N * (L.T @ L)
+    return float(lam * N * (Lt @ Lt)), Hp @ theta, Hp
 
 
 # ----------------------------------------------------------------------------- normal matrix
@@ -292,28 +337,37 @@ def fixed_weights(obj: Objective, I, m) -> np.ndarray:
     return w
 
 
-def solve_chi2(R, I, m, w, refine: int = 3) -> np.ndarray:
-    """Exact minimiser of 1/2 sum w (I - M)^2: (X^T W X) theta = X^T W I, by Cholesky.
+def solve_chi2(R, I, m, w, refine: int = 3, lam: float = 0.0) -> np.ndarray:
+    """Exact minimiser of 1/2 sum w (I - M)^2 [+ lambda N_data theta^T L^T L theta]:
+    (X^T W X + 2 lambda N_data L^T L) theta = X^T W I, by Cholesky (Sec. 2.7 for the penalty).
 
     The normal equations square the condition number of X, so the Cholesky solution is refined
     with the residual gradient X^T W (X theta - I) taken from the direct loops (each refinement
     is one exact Newton step on the quadratic)."""
     Iv = _f64(valid(_f64(I), m))
     A, b = normal_matrix(R, m, w, Iv)
+    Hp = penalty(np.zeros(m * m + 1), m, lam, n_data(I, m))[2] if lam > 0.0 else None
+    if Hp is not None:
+        A = A + Hp
     cf = scipy.linalg.cho_factor(A, lower=True)
     theta = scipy.linalg.cho_solve(cf, b)
     for _ in range(refine):
         gv = w * (model(R, theta, m) - Iv)
         g = np.concatenate([grad_kernel(R, gv, m), [np.sum(gv)]])
+        if Hp is not None:
+            g = g + Hp @ theta
         theta = theta - scipy.linalg.cho_solve(cf, g)
     return theta
 
 
 def hessian(R, I, theta, m, obj: Objective):
+    """X^T diag(l'') X, plus 2 lambda N_data L^T L when obj.lam > 0 (Sec. 2.5, Sec. 2.7)."""
     Iv = _f64(valid(_f64(I), m))
     M = model(R, theta, m)
     _, _, h = pixel_terms(obj, Iv, M, m)
     A, _ = normal_matrix(R, m, h)
+    if obj.lam > 0.0:
+        A = A + penalty(theta, m, obj.lam, n_data(I, m))[2]
     return A
 
 
@@ -365,8 +419,9 @@ def solve(R, I, m, obj: Objective, theta0=None, max_iter: int = 100, verbose: bo
     definite the IRLS surrogate X^T diag(psi/(z sigma^2)) X is used; Armijo backtracking.  Stops when
     the step is below 1e-13 of |theta| or the loss stops decreasing."""
     if obj.rho == "gauss" and not obj.model_sigma:
-        return solve_chi2(R, I, m, fixed_weights(obj, I, m))
+        return solve_chi2(R, I, m, fixed_weights(obj, I, m), lam=obj.lam)
     Iv = _f64(valid(_f64(I), m))
+    Hp = penalty(np.zeros(m * m + 1), m, obj.lam, n_data(I, m))[2] if obj.lam > 0.0 else 0.0
     if theta0 is None:
         if obj.model_sigma:
             start = Objective(rho="gauss", var=obj.var.replace("model", "data"), sigma0=obj.sigma0,
@@ -376,7 +431,7 @@ def solve(R, I, m, obj: Objective, theta0=None, max_iter: int = 100, verbose: bo
             start = Objective(rho="gauss", var=obj.var, sigma0=obj.sigma0, gain=obj.gain,
                               excess=obj.excess, var_floor=obj.var_floor, weights=obj.weights,
                               flat=obj.flat, mask=obj.mask)
-        theta = solve_chi2(R, I, m, fixed_weights(start, I, m))
+        theta = solve_chi2(R, I, m, fixed_weights(start, I, m), lam=obj.lam)
     else:
         theta = _f64(theta0).copy()
     L, g = loss_grad(R, I, theta, m, obj)
@@ -385,10 +440,10 @@ def solve(R, I, m, obj: Objective, theta0=None, max_iter: int = 100, verbose: bo
         _, _, h = pixel_terms(obj, Iv, M, m)
         A, _ = normal_matrix(R, m, h)
         try:
-            step = -scipy.linalg.cho_solve(scipy.linalg.cho_factor(A, lower=True), g)
+            step = -scipy.linalg.cho_solve(scipy.linalg.cho_factor(A + Hp, lower=True), g)
         except np.linalg.LinAlgError:
             A, _ = normal_matrix(R, m, _irls_weights(obj, Iv, M, m))
-            step = -scipy.linalg.cho_solve(scipy.linalg.cho_factor(A, lower=True), g)
+            step = -scipy.linalg.cho_solve(scipy.linalg.cho_factor(A + Hp, lower=True), g)
         slope = float(g @ step)
         t = 1.0
         while True:

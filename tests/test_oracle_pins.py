@@ -527,3 +527,111 @@ def test_covariance_is_the_scatter_of_refitted_parameters():
     np.testing.assert_allclose(sd, out["sigma"], rtol=0.15)
     sdP = fits[:, :m * m].sum(axis=1).std(ddof=1)
     assert abs(sdP / out["sigma_P"] - 1.0) < 0.15
+
+
+# --------------------------------------------------------------------- kernel regulariser (Sec. 2.7)
+@pytest.mark.parametrize("m", [1, 3, 5, 9])
+def test_laplacian_spectrum_is_the_grid_graph_closed_form(m):
+    # eq. laplacian on the m x m grid with side-sharing adjacency is the Kronecker sum of two path
+    # graphs, whose Laplacian eigenvalues are 2 - 2 cos(pi j / m), j = 0 .. m-1
+    L = oracle.laplacian(m)
+    n = m * m
+    assert L.shape == (n + 1, n + 1)
+    assert np.array_equal(L, L.T)
+    assert not L[n].any() and not L[:, n].any()
+    assert np.allclose(L[:n, :n].sum(axis=1), 0.0)
+    deg = np.diag(L)[:n].reshape(m, m)
+    if m > 1:
+        assert deg[0, 0] == 2 and deg[-1, -1] == 2
+        if m > 2:
+            assert deg[0, 1] == 3 and deg[1, 1] == 4
+    path = 2.0 - 2.0 * np.cos(np.pi * np.arange(m) / m)
+    want = np.sort((path[:, None] + path[None, :]).ravel())
+    got = np.linalg.eigvalsh(L[:n, :n])
+    assert np.allclose(got, want, atol=1e-12)
+
+
+def test_penalty_of_a_single_pixel_and_a_constant_kernel():
+    m, lam, N = 5, 0.7, 123
+    th = np.zeros(m * m + 1)
+    th[m * m] = 42.0  # B0 is not penalised
+    assert oracle.penalty(th, m, lam, N)[0] == 0.0
+    th[:m * m] = 0.3  # constant kernel: the null space of L
+    assert abs(oracle.penalty(th, m, lam, N)[0]) < 1e-12
+    for (a, b), deg in (((2, 2), 4), ((0, 0), 2), ((0, 2), 3)):
+        th = np.zeros(m * m + 1)
+        th[a * m + b] = 1.0
+        # L e_u has deg at u and -1 at each of the deg neighbours: |L e_u|^2 = deg^2 + deg
+        assert oracle.penalty(th, m, lam, N)[0] == pytest.approx(lam * N * (deg * deg + deg), rel=1e-14)
+
+
+def test_penalty_gradient_and_hessian_are_derivatives():
+    rng = np.random.default_rng(5)
+    m, lam, N = 5, 2.5, 77
+    th = rng.normal(size=m * m + 1)
+    p, g, H = oracle.penalty(th, m, lam, N)
+    h = 1e-3
+    for k in (0, 7, 12, 24, 25):
+        e = np.zeros_like(th)
+        e[k] = h
+        fd = (oracle.penalty(th + e, m, lam, N)[0] - oracle.penalty(th - e, m, lam, N)[0]) / (2 * h)
+        assert fd == pytest.approx(g[k], rel=1e-9, abs=1e-9)  # exact for a quadratic up to rounding
+        assert np.allclose((oracle.penalty(th + e, m, lam, N)[1] - oracle.penalty(th - e, m, lam, N)[1]) / (2 * h),
+                           H[:, k], rtol=1e-9, atol=1e-9)
+    assert p == pytest.approx(0.5 * th @ H @ th, rel=1e-12)
+
+
+@pytest.fixture(scope="module")
+def c1_pair():
+    return sf.config1()
+
+
+def test_regularised_solve_limits(c1_pair):
+    p = c1_pair
+    m = p.m
+    obj = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
+    t0 = oracle.solve(p.R, p.I, m, obj)
+    # lambda = 0 is the maximum-likelihood fit
+    obj0 = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain, lam=0.0)
+    assert np.array_equal(oracle.solve(p.R, p.I, m, obj0), t0)
+    # lambda -> infinity: the kernel is forced into the null space of L (a constant), and the fit
+    # tends, as 1/lambda, to the two-parameter weighted least squares of I on (box sum of R, 1)
+    w = oracle.fixed_weights(obj, p.I, m).ravel()
+    box = scipy.signal.correlate(p.R.astype(np.float64), np.ones((m, m)), mode="valid").ravel()
+    A = np.stack([box, np.ones_like(box)], 1) * np.sqrt(w)[:, None]
+    y = oracle.valid(p.I.astype(np.float64), m).ravel() * np.sqrt(w)
+    c, B0 = np.linalg.lstsq(A, y, rcond=None)[0]
+    dev = []
+    for lam in (1e8, 1e10):
+        tL = oracle.solve(p.R, p.I, m, oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu,
+                                                         gain=p.gain, lam=lam))
+        K = tL[:m * m]
+        dev.append((np.ptp(K) / abs(K.mean()), abs(K.mean() / c - 1.0), abs(tL[m * m] / B0 - 1.0)))
+    assert dev[1][0] <= 1e-4 and dev[1][1] <= 1e-5 and dev[1][2] <= 1e-6
+    for a, b in zip(dev[0], dev[1]):
+        assert 50.0 <= a / b <= 200.0
+    # in between, the penalty trades smoothness for fit: |L K| falls and the data loss rises with lambda
+    Lap = oracle.laplacian(m)
+    prev_s, prev_d = np.inf, -np.inf
+    for lam in (1e-3, 1e-1, 10.0):
+        t = oracle.solve(p.R, p.I, m, oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu,
+                                                        gain=p.gain, lam=lam))
+        s = np.linalg.norm(Lap @ t)
+        d = oracle.loss_grad(p.R, p.I, t, m, obj)[0]
+        assert s < prev_s and d > prev_d
+        prev_s, prev_d = s, d
+
+
+@pytest.mark.parametrize("rho,var", [("gauss", "ccd_data"), ("huber", "emccd_model")])
+def test_regularised_solution_is_stationary(c1_pair, rho, var):
+    p = c1_pair
+    m = p.m
+    obj = oracle.Objective(rho=rho, var=var, sigma0=p.sigma0_adu, gain=p.gain, lam=0.5)
+    th = oracle.solve(p.R, p.I, m, obj)
+    L, g = oracle.loss_grad(p.R, p.I, th, m, obj)
+    # the gradient of the regularised loss vanishes against the size of its two parts
+    obj0 = oracle.Objective(rho=rho, var=var, sigma0=p.sigma0_adu, gain=p.gain)
+    g0 = oracle.loss_grad(p.R, p.I, th, m, obj0)[1]
+    gp = oracle.penalty(th, m, obj.lam, oracle.n_data(p.I, m))[1]
+    assert np.max(np.abs(g)) <= 1e-7 * (np.max(np.abs(g0)) + np.max(np.abs(gp)))
+    assert np.max(np.abs(gp)) > 1e-3 * np.max(np.abs(g0))  # the penalty is active
