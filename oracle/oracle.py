@@ -103,6 +103,8 @@ def valid(a: np.ndarray, m: int) -> np.ndarray:
 
 
 def n_data(rows: int, cols: int, m: int) -> int:
+    """Pixels of the valid region; also N_data of eq. regularised_loss (the reading of "number of
+    target image pixels" consistent with the data term the penalty is weighed against)."""
     return (rows - m + 1) * (cols - m + 1)
 
 
@@ -250,7 +252,7 @@ def loss_grad(R, I, theta, m, obj: Objective):
     grad[m * m] = np.sum(g)
     L = float(np.sum(l))
     if obj.lam > 0.0:
-        p, pg, _ = penalty(theta, m, obj.lam, n_data(I, m))
+        p, pg, _ = penalty(theta, m, obj.lam, n_data(*np.shape(I), m))
         L += p
         grad += pg
     return L, grad
@@ -272,13 +274,6 @@ def laplacian(m) -> np.ndarray:
                     L[u, (a + da) * m + (b + db)] = -1.0
                     L[u, u] += 1.0
     return L
-
-
-def n_data(I, m) -> int:
-    """N_data of eq. regularised_loss: the number of pixels in the valid region the loss sums
-    over (the reading of "number of target image pixels" consistent with the data term)."""
-    H, W = np.shape(I)
-    return (H - m + 1) * (W - m + 1)
 
 
 def penalty(theta, m, lam, N):
@@ -346,7 +341,7 @@ def solve_chi2(R, I, m, w, refine: int = 3, lam: float = 0.0) -> np.ndarray:
     is one exact Newton step on the quadratic)."""
     Iv = _f64(valid(_f64(I), m))
     A, b = normal_matrix(R, m, w, Iv)
-    Hp = penalty(np.zeros(m * m + 1), m, lam, n_data(I, m))[2] if lam > 0.0 else None
+    Hp = penalty(np.zeros(m * m + 1), m, lam, n_data(*np.shape(I), m))[2] if lam > 0.0 else None
     if Hp is not None:
         A = A + Hp
     cf = scipy.linalg.cho_factor(A, lower=True)
@@ -367,7 +362,7 @@ def hessian(R, I, theta, m, obj: Objective):
     _, _, h = pixel_terms(obj, Iv, M, m)
     A, _ = normal_matrix(R, m, h)
     if obj.lam > 0.0:
-        A = A + penalty(theta, m, obj.lam, n_data(I, m))[2]
+        A = A + penalty(theta, m, obj.lam, n_data(*np.shape(I), m))[2]
     return A
 
 
@@ -421,7 +416,7 @@ def solve(R, I, m, obj: Objective, theta0=None, max_iter: int = 100, verbose: bo
     if obj.rho == "gauss" and not obj.model_sigma:
         return solve_chi2(R, I, m, fixed_weights(obj, I, m), lam=obj.lam)
     Iv = _f64(valid(_f64(I), m))
-    Hp = penalty(np.zeros(m * m + 1), m, obj.lam, n_data(I, m))[2] if obj.lam > 0.0 else 0.0
+    Hp = penalty(np.zeros(m * m + 1), m, obj.lam, n_data(*np.shape(I), m))[2] if obj.lam > 0.0 else 0.0
     if theta0 is None:
         if obj.model_sigma:
             start = Objective(rho="gauss", var=obj.var.replace("model", "data"), sigma0=obj.sigma0,

@@ -632,6 +632,6 @@ def test_regularised_solution_is_stationary(c1_pair, rho, var):
     # the gradient of the regularised loss vanishes against the size of its two parts
     obj0 = oracle.Objective(rho=rho, var=var, sigma0=p.sigma0_adu, gain=p.gain)
     g0 = oracle.loss_grad(p.R, p.I, th, m, obj0)[1]
-    gp = oracle.penalty(th, m, obj.lam, oracle.n_data(p.I, m))[1]
+    gp = oracle.penalty(th, m, obj.lam, oracle.n_data(*p.I.shape, m))[1]
     assert np.max(np.abs(g)) <= 1e-7 * (np.max(np.abs(g0)) + np.max(np.abs(gp)))
     assert np.max(np.abs(gp)) > 1e-3 * np.max(np.abs(g0))  # the penalty is active
