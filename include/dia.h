@@ -91,6 +91,14 @@ typedef struct {
     const float* weights;  /* 1/sigma^2; required for DIA_VAR_WEIGHTS, else NULL */
     const float* flat;     /* master flat F; NULL means F = 1                    */
     const uint8_t* mask;   /* nonzero = pixel used; NULL means every valid pixel */
+    /* Kernel-smoothness penalty of Section 2.7 (eq. regularised_loss): the loss
+     * gains lambda N_data theta^T L^T L theta, L the Laplacian of eq. laplacian
+     * over the kernel pixels (pixels sharing a side are adjacent; B0 is not
+     * penalised) and N_data the number of valid-region pixels.  lambda >= 0;
+     * 0 is the maximum-likelihood fit.  The single-pair entry points
+     * (dia_loss_grad, dia_hessian, dia_fit) include it in the loss, gradient and
+     * Hessian; the batched ones require lambda = 0 (DIA_E_ARG otherwise). */
+    double lambda;
 } dia_objective;
 
 /* Operations for dia_workspace_size. */

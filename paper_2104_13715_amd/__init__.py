@@ -49,7 +49,7 @@ class _Objective(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_int32), ("var", ctypes.c_int32), ("sigma0", ctypes.c_double),
                 ("gain", ctypes.c_double), ("excess", ctypes.c_double), ("var_floor", ctypes.c_double),
                 ("c", ctypes.c_double), ("weights", ctypes.c_void_p), ("flat", ctypes.c_void_p),
-                ("mask", ctypes.c_void_p)]
+                ("mask", ctypes.c_void_p), ("lam", ctypes.c_double)]
 
 
 class _Epoch(ctypes.Structure):
@@ -148,7 +148,8 @@ def _stream(device) -> int:
 @dataclass
 class Objective:
     """rho in {'gauss', 'huber', 'cauchy'}; var in {'weights', 'ccd_data', 'ccd_model', 'emccd_data',
-    'emccd_model'} (see include/dia.h).  weights / flat / mask are tensors laid out like the target."""
+    'emccd_model'} (see include/dia.h).  weights / flat / mask are tensors laid out like the target.
+    lam: lambda of the kernel-smoothness penalty (single-pair calls only; 0 = none)."""
     rho: str = "gauss"
     var: str = "ccd_data"
     sigma0: float = 0.0
@@ -159,13 +160,14 @@ class Objective:
     weights: Optional[torch.Tensor] = None
     flat: Optional[torch.Tensor] = None
     mask: Optional[torch.Tensor] = None
+    lam: float = 0.0
 
     def _c(self, I: torch.Tensor) -> _Objective:
         return _Objective(RHO[self.rho], VAR[self.var], float(self.sigma0), float(self.gain), float(self.excess),
                           float(self.var_floor), float(self.c),
                           _like_target(self.weights, I, torch.float32, "weights"),
                           _like_target(self.flat, I, torch.float32, "flat"),
-                          _like_target(self.mask, I, torch.uint8, "mask"))
+                          _like_target(self.mask, I, torch.uint8, "mask"), float(self.lam))
 
 
 def workspace_size(op: int, rows: int, cols: int, ld: int, m: int) -> int:

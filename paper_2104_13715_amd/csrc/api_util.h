@@ -43,6 +43,7 @@ inline int check_obj(const dia_objective* o, bool need_weights_ptr = true) {
     if (o->rho < DIA_RHO_GAUSS || o->rho > DIA_RHO_CAUCHY) return DIA_E_ARG;
     if (o->var < DIA_VAR_WEIGHTS || o->var > DIA_VAR_EMCCD_MODEL) return DIA_E_ARG;
     if (o->rho != DIA_RHO_GAUSS && !(o->c > 0.0 && is_fin(o->c))) return DIA_E_ARG;
+    if (!(o->lambda >= 0.0) || !is_fin(o->lambda)) return DIA_E_ARG;
     if (o->var == DIA_VAR_WEIGHTS) {
         if (need_weights_ptr && o->weights == nullptr) return DIA_E_ARG;
     } else {
@@ -55,6 +56,12 @@ inline int check_obj(const dia_objective* o, bool need_weights_ptr = true) {
         if (!em && !(o->sigma0 != 0.0 || o->var_floor > 0.0)) return DIA_E_ARG;
     }
     return DIA_OK;
+}
+
+// lambda N_data of the kernel-smoothness penalty (Section 2.7, eq. regularised_loss), N_data the
+// number of valid-region pixels of the target.
+inline double penalty_weight(const dia_objective& o, const dia_image& I, int m) {
+    return o.lambda * (double)(I.rows - m + 1) * (double)(I.cols - m + 1);
 }
 
 inline int check_ws(const void* ws, size_t ws_bytes, size_t need) {

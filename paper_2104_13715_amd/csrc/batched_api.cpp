@@ -218,6 +218,7 @@ int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32
     int c = check_image(R);
     if (c != DIA_OK) return c;
     if ((c = check_obj(obj, false)) != DIA_OK) return c;
+    if (obj->lambda != 0.0) return DIA_E_ARG;  // the smoothness penalty is a single-pair option
     if ((c = check_epochs(R, epochs, n, m, obj, precision)) != DIA_OK) return c;
     if (theta == nullptr || loss == nullptr || grad == nullptr) return DIA_E_ARG;
     const BLayout L = make_blayout(epochs, n, m, precision, false);
@@ -277,6 +278,7 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
     int c = check_image(R);
     if (c != DIA_OK) return c;
     if ((c = check_obj(obj, false)) != DIA_OK) return c;
+    if (obj->lambda != 0.0) return DIA_E_ARG;  // the smoothness penalty is a single-pair option
     if ((c = check_epochs(R, epochs, n, m, obj, precision)) != DIA_OK) return c;
     if ((c = check_opts(opts)) != DIA_OK) return c;
     if (opts->max_outer != 1 || theta == nullptr) return DIA_E_ARG;
@@ -422,7 +424,7 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
                     const NewtonLayout NL = newton_layout(m, Ie.rows, Ie.cols, true, true);
                     char* nb = base + L.newton;
                     const int ge = eval_grid(m, tile_grid_tiles(m, Ie.rows, Ie.cols, 0), 0);
-                    const int pr = newton_polish(Re, Ie, to_params(oe), m, ge, 0, st,
+                    const int pr = newton_polish(Re, Ie, to_params(oe), 0.0, m, ge, 0, st,
                                                  offset_vecs(v0, (long long)e * L.stride),
                                                  reinterpret_cast<double*>(nb + NL.part), nb, NL, o.max_newton, quad,
                                                  cs, &nw[e]);

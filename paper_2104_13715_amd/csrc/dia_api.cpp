@@ -188,6 +188,8 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
             ra.n = L.n;
             ra.m = m;
             ra.done = &st->done;
+            ra.reg = penalty_weight(obj, I, m);
+            ra.th64 = v.theta_eval64;
             const int r = run_fit_graph(ta, m, grid, variant, ra, o.poll_every, o.max_eval, cs, st, &fs);
             if (r != DIA_OK) {
                 rc = r;
@@ -202,8 +204,8 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
                 const bool quad = cur.rho == DIA_RHO_GAUSS && cur.var != DIA_VAR_CCD_MODEL &&
                                   cur.var != DIA_VAR_EMCCD_MODEL;
                 NewtonOutcome no;
-                const int pr = newton_polish(R, I, to_params(cur), m, grid, variant, st, v, ta.partial,
-                                             base + L.newton, L.NL, o.max_newton, quad, cs, &no);
+                const int pr = newton_polish(R, I, to_params(cur), penalty_weight(obj, I, m), m, grid, variant, st, v,
+                                             ta.partial, base + L.newton, L.NL, o.max_newton, quad, cs, &no);
                 if (pr != DIA_OK) {
                     rc = pr;
                     break;
@@ -350,6 +352,8 @@ int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const floa
     ra.out_grad = grad;
     ra.n = L.n;
     ra.m = m;
+    ra.reg = penalty_weight(*obj, I, m);
+    ra.th64 = th64;
     return launch_reduce(ra, s) == hipSuccess ? DIA_OK : DIA_E_HIP;
 }
 
@@ -369,7 +373,7 @@ int dia_hessian(dia_image R, dia_image I, const dia_objective* obj, const float*
     double* th64 = reinterpret_cast<double*>(base + L.th64);
     if (launch_widen(theta, th64, L.n, s) != hipSuccess) return DIA_E_HIP;
     try {
-        return hessian_into(R, I, to_params(*obj), m, theta, th64, /*exact=*/1,
+        return hessian_into(R, I, to_params(*obj), penalty_weight(*obj, I, m), m, theta, th64, /*exact=*/1,
                             reinterpret_cast<double*>(base + L.partial), base + L.newton, L.NL, H, s);
     } catch (...) {
         return DIA_E_HIP;

@@ -377,6 +377,31 @@ __device__ __forceinline__ double reduce_columns(const double* partial, int npp,
     return tot;
 }
 
+// (L t)_u for kernel pixel u = a m + b: Laplacian of the pixel graph whose edges join pixels
+// sharing a side (Section 2.7, eq. laplacian): degree times t_u minus the neighbours' values.
+__device__ __forceinline__ double lap_apply(const double* t, int u, int m) {
+    const int a = u / m, b = u - a * m;
+    double s = 0.0;
+    int deg = 0;
+    if (a > 0) s += t[u - m], ++deg;
+    if (a + 1 < m) s += t[u + m], ++deg;
+    if (b > 0) s += t[u - 1], ++deg;
+    if (b + 1 < m) s += t[u + 1], ++deg;
+    return deg * t[u] - s;
+}
+
+// (L L t)_u: the same stencil applied to (L t) at u and its neighbours (L is symmetric).
+__device__ __forceinline__ double lap2_apply(const double* t, int u, int m) {
+    const int a = u / m, b = u - a * m;
+    double s = 0.0;
+    int deg = 0;
+    if (a > 0) s += lap_apply(t, u - m, m), ++deg;
+    if (a + 1 < m) s += lap_apply(t, u + m, m), ++deg;
+    if (b > 0) s += lap_apply(t, u - 1, m), ++deg;
+    if (b + 1 < m) s += lap_apply(t, u + 1, m), ++deg;
+    return deg * lap_apply(t, u, m) - s;
+}
+
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
     __shared__ double red[kReducePhases][kReduceCols];
     __shared__ double sh[16];
@@ -384,7 +409,23 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
     if (ra.done != nullptr && *ra.done != 0) return;
     const int tid = threadIdx.x;
     const int col = blockIdx.x * kReduceCols + (tid % kReduceCols);
-    const double tot = reduce_columns(ra.partial, ra.npp, 0, ra.nblk, col, red);
+    double tot = reduce_columns(ra.partial, ra.npp, 0, ra.nblk, col, red);
+    if (ra.reg > 0.0) {
+        // kernel-smoothness penalty reg t^T L^T L t (Section 2.7, eq. regularised_loss): its gradient
+        // 2 reg (L L t) on the kernel columns, its value on the loss column (summed by the whole
+        // workgroup that owns that column; the condition is uniform over the workgroup)
+        const int nk = ra.m * ra.m;
+        if (blockIdx.x == ra.n / kReduceCols) {
+            double q = 0.0;
+            for (int u = tid; u < nk; u += kReduceThreads) {
+                const double l = lap_apply(ra.th64, u, ra.m);
+                q += l * l;
+            }
+            q = block_sum(q, sh);
+            if (col == ra.n) tot += ra.reg * q;
+        }
+        if (tid < kReduceCols && col < nk) tot += 2.0 * ra.reg * lap2_apply(ra.th64, col, ra.m);
+    }
     if (tid < kReduceCols && col < ra.npp) {
         ra.gt[col] = tot;
         if (ra.out_grad != nullptr && col < ra.n) ra.out_grad[col] = (float)tot;
@@ -457,6 +498,8 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchRed
     ra.m = br.m;
     ra.done = nullptr;
     ra.n_done = br.n_done;
+    ra.reg = 0.0;
+    ra.th64 = nullptr;
     optimiser_step(ra, sh);
     if (tid == 0) st->counter = 0;
 }

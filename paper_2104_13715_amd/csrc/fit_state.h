@@ -71,6 +71,8 @@ struct ReduceArgs {
     int n, m;
     const int* done;
     int* n_done;            // incremented once when the fit finishes (batched polling)
+    double reg;             // lambda N_data of the kernel-smoothness penalty (0 = none)
+    const double* th64;     // the FP64 parameters the pass evaluated (read when reg > 0)
 };
 
 // Batched fits: epoch e's FitState, SelectState, vectors and theta_eval sit at byte offset

@@ -7,8 +7,9 @@ namespace dia {
 
 constexpr int kMaxTheta = DIA_MAX_M * DIA_MAX_M + 1;
 
+// reg = lambda N_data adds the smoothness penalty's Hessian 2 reg L L (Section 2.7) to the kernel block.
 hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
-                                hipStream_t s);
+                                double reg, hipStream_t s);
 hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, const double* th, double* d, double* info,
                              hipStream_t s);
 // Sigma = F^-1 with the validity flag (Section 2.5); A holds F on entry (factored in place),
@@ -32,8 +33,8 @@ NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own
 
 // Hessian of the loss at (theta, theta64) into H (n x n row-major, FP64).  exact = 1: d2L itself;
 // exact = 0: the positive Gauss-Newton / IRLS form used for Newton steps.  partial: partial rows
-// with room for the default tile shape's grid.
-int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, const float* theta,
+// with room for the default tile shape's grid.  reg = lambda N_data of the smoothness penalty.
+int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, const float* theta,
                  const double* theta64, int exact, double* partial, char* nbase, const NewtonLayout& NL, double* H,
                  hipStream_t s);
 
@@ -47,7 +48,8 @@ struct NewtonOutcome {
 // Newton steps from the optimiser point x of a finished fit (st, v) until the Newton decrement is
 // negligible (at most max_steps).  Leaves x and st->L at the result.  quadratic: the Hessian does
 // not depend on theta (Gaussian objective, variance fixed), so it is factored once.
-int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, int grid, int variant,
+int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int grid,
+                  int variant,
                   FitState* st, const FitVecs& v, double* partial, char* nbase, const NewtonLayout& NL,
                   int max_steps, bool quadratic, hipStream_t s, NewtonOutcome* out);
 

@@ -43,8 +43,8 @@ NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own
 namespace {
 
 // One fused pass at (theta, theta64) reduced into gt (gradient, then the loss at gt[n]).
-bool eval_into(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, int grid, int variant,
-               const float* theta, const double* theta64, double* partial, double* gt, hipStream_t s) {
+bool eval_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int grid,
+               int variant, const float* theta, const double* theta64, double* partial, double* gt, hipStream_t s) {
     TileArgs a = base_args(R, I, theta);
     a.theta64 = theta64;
     a.obj = obj;
@@ -58,6 +58,8 @@ bool eval_into(const dia_image& R, const dia_image& I, const ObjParams& obj, int
     ra.gt = gt;
     ra.n = m * m + 1;
     ra.m = m;
+    ra.reg = reg;
+    ra.th64 = theta64;
     return launch_reduce(ra, s) == hipSuccess;
 }
 
@@ -68,7 +70,7 @@ bool read_back(void* dst, const void* src, size_t bytes, hipStream_t s) {
 
 }  // namespace
 
-int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, const float* theta,
+int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, const float* theta,
                  const double* theta64, int exact, double* partial, char* nbase, const NewtonLayout& NL, double* H,
                  hipStream_t s) {
     const int grid0 = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, 0), 0);
@@ -97,13 +99,15 @@ int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, i
     ha.cols = R.cols;
     ha.partial = reinterpret_cast<double*>(nbase + NL.hpart);
     if (launch_hess(m, ha, s) != hipSuccess) return DIA_E_HIP;
-    if (launch_hess_assemble(ha.partial, NL.splits, NL.npb, m, reinterpret_cast<const double*>(nbase + NL.hv), H, s) !=
+    if (launch_hess_assemble(ha.partial, NL.splits, NL.npb, m, reinterpret_cast<const double*>(nbase + NL.hv), H, reg,
+                             s) !=
         hipSuccess)
         return DIA_E_HIP;
     return DIA_OK;
 }
 
-int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, int m, int grid, int variant,
+int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int grid,
+                  int variant,
                   FitState* st, const FitVecs& v, double* partial, char* nbase, const NewtonLayout& NL,
                   int max_steps, bool quadratic, hipStream_t s, NewtonOutcome* out) {
     const int n = m * m + 1;
@@ -117,7 +121,7 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
     if (launch_theta_from_x(st, v, n, s) != hipSuccess) return DIA_E_HIP;
     if (hipMemcpyAsync(th, v.theta_eval64, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return DIA_E_HIP;
-    if (!eval_into(R, I, obj, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s)) return DIA_E_HIP;
+    if (!eval_into(R, I, obj, reg, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s)) return DIA_E_HIP;
     ++out->evals;
     double L = 0.0;
     if (!read_back(&L, gt + n, sizeof(double), s)) return DIA_E_HIP;
@@ -125,7 +129,7 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
     for (int it = 0; it < max_steps; ++it) {
         const bool factor = (it == 0) || !quadratic;
         if (factor) {
-            const int rc = hessian_into(R, I, obj, m, v.theta_eval, v.theta_eval64, 0, partial, nbase, NL, H, s);
+            const int rc = hessian_into(R, I, obj, reg, m, v.theta_eval, v.theta_eval64, 0, partial, nbase, NL, H, s);
             if (rc != DIA_OK) return rc;
             ++out->evals;
             ++out->hessians;
@@ -145,7 +149,7 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
         double alpha = 1.0;
         for (int ls = 0; ls < 8; ++ls, alpha *= 0.5) {
             if (launch_newton_trial(th, d, alpha, v.theta_eval, v.theta_eval64, n, s) != hipSuccess) return DIA_E_HIP;
-            if (!eval_into(R, I, obj, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s))
+            if (!eval_into(R, I, obj, reg, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s))
                 return DIA_E_HIP;
             ++out->evals;
             double Lt = 0.0;

@@ -15,8 +15,24 @@ constexpr int kCholThreads = 1024;
 // H[t1][t2] for the kernel taps from the split partials (fixed order; element (min, max) of the
 // region-pair blocks of 64 x 64, so H is exactly symmetric), the background row from
 // hv = [sum h R_(p+t) (t < m*m), sum h].
+// Entry (u, v) of L L, L the kernel-pixel Laplacian (Section 2.7, eq. laplacian; pixels sharing a
+// side are adjacent): sum over w of L_uw L_wv.  On the grid: deg^2 + deg on the diagonal, -(deg u +
+// deg v) for neighbours (they share no neighbour), the number of common neighbours at distance two.
+__device__ __forceinline__ double lap2_entry(int u, int v, int m) {
+    const int au = u / m, bu = u - au * m, av = v / m, bv = v - av * m;
+    auto deg = [m](int a, int b) { return (a > 0) + (a + 1 < m) + (b > 0) + (b + 1 < m); };
+    const int da = au > av ? au - av : av - au, db = bu > bv ? bu - bv : bv - bu;
+    if (da + db == 0) {
+        const int d = deg(au, bu);
+        return (double)(d * d + d);
+    }
+    if (da + db == 1) return -(double)(deg(au, bu) + deg(av, bv));
+    if (da + db == 2) return (da == 1) ? 2.0 : 1.0;
+    return 0.0;
+}
+
 __global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partial, int splits, int npb, int m,
-                                                            const double* hv, double* H) {
+                                                            const double* hv, double* H, double reg) {
     constexpr int RG = 64;
     const int n = m * m + 1, T = m * m;
     const int nr = (T + RG - 1) / RG;
@@ -29,6 +45,7 @@ __global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partia
         const int k = (lo - ra * RG) * RG + (hi - rb * RG);
         double s = 0.0;
         for (int sp = 0; sp < splits; ++sp) s += partial[((long long)sp * npb + pb) * (RG * RG) + k];
+        if (reg > 0.0) s += 2.0 * reg * lap2_entry(t1, t2, m);  // Hessian of the smoothness penalty
         H[(long long)t1 * n + t2] = s;
     }
     if (gid < n) {
@@ -313,10 +330,10 @@ __global__ __launch_bounds__(256) void theta_from_x_kernel(const FitState* st, F
 }
 
 hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
-                                hipStream_t s) {
+                                double reg, hipStream_t s) {
     const long long work = std::max<long long>((long long)m * m * m * m, m * m + 1);
     const int blocks = (int)((work + 255) / 256);
-    hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, hv, H);
+    hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, hv, H, reg);
     return hipGetLastError();
 }
 
