@@ -150,12 +150,30 @@ def emccd_section(args, b, dia, torch, dev, np):
         Fc = torch.from_numpy(np.ascontiguousarray(b.meta["flat"][sl])).to(dev)
         Is = [torch.from_numpy(np.ascontiguousarray(e.I[sl])).to(dev) for e in b.epochs]
         obj = dia.Objective(rho="huber", var="emccd_model", gain=b.gain, excess=b.meta["excess"], flat=Fc)
+        objr = dia.Objective(rho="huber", var="emccd_model", gain=b.gain, excess=b.meta["excess"], flat=Fc,
+                             lam=args.emccd_lambda)
         for m in [int(x) for x in args.emccd_m.split(",")]:
             case = {"size": size, "m": m}
             dia.fit(R, Is[0], m, obj, workspace=ws)  # warm the tile-shape choice and the workspace
             torch.cuda.synchronize()
+            if args.emccd_lambda > 0:
+                # the Laplacian-regularised (MAP) fit of Section 2.7 from the box-car start
+                t_ms, n_ev, knorm = [], [], []
+                for k, I in enumerate(Is):
+                    a, z = ev()
+                    a.record()
+                    r = dia.fit(R, I, m, objr, workspace=ws)
+                    z.record()
+                    torch.cuda.synchronize()
+                    t_ms.append(a.elapsed_time(z))
+                    n_ev.append(r.n_eval)
+                    knorm.append(float(r.theta[:m * m].norm()))
+                case["single_flat_lambda"] = {"lambda": args.emccd_lambda, "median_ms": round(_pct(t_ms, 50), 2),
+                                              "p16_ms": round(_pct(t_ms, 16), 2), "p84_ms": round(_pct(t_ms, 84), 2),
+                                              "evals_median": int(_pct(n_ev, 50)),
+                                              "kernel_norm_median": round(_pct(knorm, 50), 4)}
             for init in ("flat", "gauss"):
-                t_ms, n_ev = [], []
+                t_ms, n_ev, knorm = [], [], []
                 for k, I in enumerate(Is):
                     a, z = ev()
                     a.record()
@@ -164,11 +182,13 @@ def emccd_section(args, b, dia, torch, dev, np):
                     torch.cuda.synchronize()
                     t_ms.append(a.elapsed_time(z))
                     n_ev.append(r.n_eval)
+                    knorm.append(float(r.theta[:m * m].norm()))
                 rho_s = spearmanr(t_ms, phi_I).statistic
                 case[f"single_{init}"] = {"median_ms": round(_pct(t_ms, 50), 2), "p16_ms": round(_pct(t_ms, 16), 2),
                                           "p84_ms": round(_pct(t_ms, 84), 2),
                                           "evals_median": int(_pct(n_ev, 50)), "evals_p16": int(_pct(n_ev, 16)),
-                                          "evals_p84": int(_pct(n_ev, 84)), "spearman_time_phi_I": round(float(rho_s), 2)}
+                                          "evals_p84": int(_pct(n_ev, 84)), "spearman_time_phi_I": round(float(rho_s), 2),
+                                          "kernel_norm_median": round(_pct(knorm, 50), 4)}
             eps = [dia.Epoch(I=I, flat=Fc) for I in Is]
             n = len(eps)
             yy, xx = np.mgrid[:m, :m] - (m - 1) / 2.0
@@ -187,9 +207,12 @@ def emccd_section(args, b, dia, torch, dev, np):
                     torch.cuda.synchronize()
                     t = a.elapsed_time(z) / 1e3
                     e_ = [r.n_eval for r in res]
+                    stops = {}
+                    for r in res:
+                        stops[r.stop] = stops.get(r.stop, 0) + 1
                     case[f"batched_{prec}_{init}"] = {"fits_per_s": round(n / t, 1), "fit_s": round(t, 3),
                                                       "evals_median": int(_pct(e_, 50)), "evals_max": int(max(e_)),
-                                                      "status": st}
+                                                      "status": st, "stops": stops}
             out["cases"].append(case)
             print(f"# emccd {case}", file=sys.stderr, flush=True)
     return out
@@ -237,6 +260,8 @@ def main() -> int:
     ap.add_argument("--emccd-epochs", type=int, default=158)
     ap.add_argument("--emccd-sizes", default="482,242", help="central crop sides of the emccd workload")
     ap.add_argument("--emccd-m", default="19,25", help="kernel sizes of the emccd workload")
+    ap.add_argument("--emccd-lambda", type=float, default=1.0,
+                    help="also time the Laplacian-regularised fit with this lambda (0 skips it)")
     ap.add_argument("--only-batched", action="store_true", help="print the batched section alone")
     ap.add_argument("--profile-batched", default="",
                     help="only run --kernel-reps batched evaluations in this precision (for hardware-counter runs)")

@@ -1,9 +1,9 @@
 // Exact-Hessian Newton steps (the Newton form of eq. newtonupdate) and the observed
 // Fisher information of Section 2.5, in FP64:
 //   * assemble H from the kernel-kernel pair blocks and the curvature-weighted correlation row;
-//   * factor H = L L^T (left-looking Cholesky in one workgroup; column k of L is kept in row k
-//     of the storage, so every column read is coalesced) and solve H d = -g;
-//   * trial points theta + alpha d written as the FP32 parameters the fused pass evaluates.
+//   * factor H = L L^T (blocked right-looking Cholesky over many workgroups; column k of L is
+//     kept in row k of the storage, so every column read is coalesced) and solve H d = -g;
+//   * trial points theta + alpha d, in FP64 for the fused pass and rounded to FP32.
 #include <algorithm>
 
 #include "newton.h"
@@ -81,48 +81,143 @@ __device__ double chol_block_max(double v, double* sh) {
 // when factor != 0; then d = -(L L^T)^-1 g.  info[0] = 1 if A was not positive definite,
 // info[1] = -g.d (the Newton decrement squared), info[2] = max|d_i| / max|th_i|,
 // info[3] = max_i |d_i| / (FP32 spacing at th_i).
-// In place: column k of L (A = L L^T) into row k of A (A[k*n + i] = L[i][k], i >= k), one
-// workgroup, left-looking.  Returns false (in every thread) when A is not positive definite.
-// col: shared scratch of n doubles.
-__device__ bool chol_factor_block(double* A, int n, double* col, int* bad) {
+// Blocked right-looking Cholesky A = L L^T in place, column k of L into row k of A
+// (A[k*n + i] = L[i][k], i >= k; A symmetric on entry, so that row holds column k of the lower
+// triangle).  Panels of kCB columns: the diagonal block is factored in LDS by one workgroup, the
+// rows below it are solved against it one row per thread, and the trailing lower triangle takes
+// the rank-kCB update in 32 x 32 tiles across many workgroups.  flag (device double): 0 on
+// success, 1 when a pivot is not positive (A is not positive definite); later kernels of the
+// same factorisation see it and return.
+constexpr int kCB = 32;
+
+__global__ __launch_bounds__(256) void chol_diag_kernel(double* A, int n, int k0, double* flag) {
+    __shared__ double D[kCB][kCB + 1];
     const int tid = threadIdx.x;
-    if (tid == 0) *bad = 0;
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        for (int k = tid; k < j; k += kCholThreads) col[k] = A[(long long)k * n + j];
-        __syncthreads();
-        for (int i = j + tid; i < n; i += kCholThreads) {
-            double s = A[(long long)j * n + i];
-            for (int k = 0; k < j; ++k) s -= A[(long long)k * n + i] * col[k];
-            A[(long long)j * n + i] = s;
-        }
-        __syncthreads();
-        const double dj = A[(long long)j * n + j];
-        if (!(dj > 0.0)) {
-            if (tid == 0) *bad = 1;
-            break;
-        }
-        const double sq = sqrt(dj);
-        __syncthreads();
-        for (int i = j + tid; i < n; i += kCholThreads)
-            A[(long long)j * n + i] = (i == j) ? sq : A[(long long)j * n + i] / sq;
-        __syncthreads();
+    if (k0 == 0) {
+        if (tid == 0) *flag = 0.0;
+    } else if (*flag != 0.0) {
+        return;
+    }
+    const int bw = n - k0 < kCB ? n - k0 : kCB;
+    for (int e = tid; e < kCB * kCB; e += 256) {
+        const int c = e / kCB, r = e % kCB;
+        D[r][c] = (r < bw && c < bw && r >= c) ? A[(long long)(k0 + c) * n + k0 + r] : 0.0;
     }
     __syncthreads();
-    return *bad == 0;
+    bool ok = true;
+    for (int c = 0; c < bw; ++c) {
+        const double p = D[c][c];  // the same value in every thread: the exit is uniform
+        if (!(p > 0.0)) {
+            ok = false;
+            break;
+        }
+        const double sq = sqrt(p);
+        __syncthreads();
+        if (tid == 0) D[c][c] = sq;
+        for (int r = c + 1 + tid; r < bw; r += 256) D[r][c] /= sq;
+        __syncthreads();
+        const int rem = bw - c - 1;
+        for (int e = tid; e < rem * rem; e += 256) {
+            const int r = c + 1 + e / rem, q = c + 1 + e % rem;
+            if (q <= r) D[r][q] -= D[r][c] * D[q][c];
+        }
+        __syncthreads();
+    }
+    if (!ok) {
+        if (tid == 0) *flag = 1.0;
+        return;
+    }
+    for (int e = tid; e < kCB * kCB; e += 256) {
+        const int c = e / kCB, r = e % kCB;
+        if (r < bw && c < bw && r >= c) A[(long long)(k0 + c) * n + k0 + r] = D[r][c];
+    }
 }
 
-__global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int n, int factor, const double* g,
+// Rows i >= k0 + kCB of the panel: L[i][k0 .. k0+kCB) solves L11 l^T = a^T (forward substitution).
+__global__ __launch_bounds__(256) void chol_trsm_kernel(double* A, int n, int k0, const double* flag) {
+    __shared__ double Ls[kCB][kCB + 1];
+    if (*flag != 0.0) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kCB * kCB; e += 256) {
+        const int c = e / kCB, r = e % kCB;
+        Ls[r][c] = (c <= r) ? A[(long long)(k0 + c) * n + k0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int i = k0 + kCB + blockIdx.x * 256 + tid;
+    if (i >= n) return;
+    double x[kCB];
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) x[c] = A[(long long)(k0 + c) * n + i];
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) {
+        double v = x[c];
+#pragma unroll
+        for (int q = 0; q < c; ++q) v -= Ls[c][q] * x[q];
+        x[c] = v / Ls[c][c];
+    }
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) A[(long long)(k0 + c) * n + i] = x[c];
+}
+
+// Trailing update A22 -= L21 L21^T on the lower triangle of rows and columns >= k0 + kCB: one
+// 32 x 32 tile (ti >= tj) per workgroup, the linear block index mapped to (ti, tj).
+__global__ __launch_bounds__(256) void chol_syrk_kernel(double* A, int n, int k0, const double* flag) {
+    __shared__ double Li[kCB][kCB + 1];
+    __shared__ double Lj[kCB][kCB + 1];
+    if (*flag != 0.0) return;
+    const int b = blockIdx.x;
+    int ti = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= b) ++ti;
+    while (ti * (ti + 1) / 2 > b) --ti;
+    const int tj = b - ti * (ti + 1) / 2;
+    const int k1 = k0 + kCB;
+    const int i0 = k1 + ti * kCB, j0 = k1 + tj * kCB;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kCB * kCB; e += 256) {
+        const int c = e / kCB, r = e % kCB;
+        Li[r][c] = (i0 + r < n) ? A[(long long)(k0 + c) * n + i0 + r] : 0.0;
+        Lj[r][c] = (j0 + r < n) ? A[(long long)(k0 + c) * n + j0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int tx = tid % kCB, ty = tid / kCB;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+    for (int c = 0; c < kCB; ++c) {
+        const double a = Li[tx][c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += a * Lj[ty + 8 * q][c];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + tx, j = j0 + ty + 8 * q;
+        if (i < n && j < n && i >= j) A[(long long)j * n + i] -= acc[q];
+    }
+}
+
+hipError_t launch_chol_factor(double* A, int n, double* flag, hipStream_t s) {
+    for (int k0 = 0; k0 < n; k0 += kCB) {
+        hipLaunchKernelGGL(chol_diag_kernel, dim3(1), dim3(256), 0, s, A, n, k0, flag);
+        const int below = n - k0 - kCB;
+        if (below > 0) {
+            hipLaunchKernelGGL(chol_trsm_kernel, dim3((below + 255) / 256), dim3(256), 0, s, A, n, k0,
+                               (const double*)flag);
+            const int T = (below + kCB - 1) / kCB;
+            hipLaunchKernelGGL(chol_syrk_kernel, dim3(T * (T + 1) / 2), dim3(256), 0, s, A, n, k0,
+                               (const double*)flag);
+        }
+    }
+    return hipGetLastError();
+}
+
+// Newton step d = -A^-1 g from the factor in A (launch_chol_factor), with info[0] its flag:
+// info = [not positive definite, decrement -g.d, max |d| / max |th|, max |d| in FP32 spacings of th].
+__global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(const double* A, int n, const double* g,
                                                                   const double* th, double* d, double* info) {
     __shared__ double col[kMaxTheta];
     __shared__ double sh[32];
-    __shared__ int bad;
     const int tid = threadIdx.x;
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    if (factor) chol_factor_block(A, n, col, &bad);
-    __syncthreads();
-    if (bad) {
+    if (info[0] != 0.0) {
+        __syncthreads();
         if (tid == 0) {
             info[0] = 1.0;
             info[1] = 0.0;
@@ -178,11 +273,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(double* A, int
 // test of Sigma (a positive definite matrix has every eigenvalue and its determinant positive);
 // info[1] = ln det Sigma = -2 sum_k ln L_kk; info[2] = the smallest pivot L_kk^2.  When F is not
 // positive definite the outputs are NaN.
-__global__ __launch_bounds__(kCholThreads) void chol_factor_kernel(double* A, int n, double* info) {
-    __shared__ double col[kMaxTheta];
+__global__ __launch_bounds__(kCholThreads) void chol_info_kernel(const double* A, int n, const double* flag,
+                                                                 double* info) {
     __shared__ double sh[32];
-    __shared__ int bad;
-    const bool ok = chol_factor_block(A, n, col, &bad);
+    const bool ok = *flag == 0.0;
     double ld = 0.0, inv_pmin = 0.0;  // the smallest pivot through the largest reciprocal (all positive)
     if (ok)
         for (int k = threadIdx.x; k < n; k += kCholThreads) {
@@ -339,13 +433,17 @@ hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int 
 
 hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, const double* th, double* d, double* info,
                              hipStream_t s) {
-    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(kCholThreads), 0, s, A, n, factor, g, th, d, info);
+    if (factor && launch_chol_factor(A, n, info, s) != hipSuccess) return hipGetLastError();
+    hipLaunchKernelGGL(chol_solve_kernel, dim3(1), dim3(kCholThreads), 0, s, (const double*)A, n, g, th, d, info);
     return hipGetLastError();
 }
 
 hipError_t launch_covariance(double* A, int n, double* W, double* S, double* sigma, double* sigma_P, double* info,
                              hipStream_t s) {
-    hipLaunchKernelGGL(chol_factor_kernel, dim3(1), dim3(kCholThreads), 0, s, A, n, info);
+    // W's first element holds the factorisation's flag until chol_info_kernel has read it
+    if (launch_chol_factor(A, n, W, s) != hipSuccess) return hipGetLastError();
+    hipLaunchKernelGGL(chol_info_kernel, dim3(1), dim3(kCholThreads), 0, s, (const double*)A, n, (const double*)W,
+                       info);
     hipLaunchKernelGGL(tri_inverse_kernel, dim3(n), dim3(256), 0, s, (const double*)A, n, W, (const double*)info);
     const int nt = (n + kCovTile - 1) / kCovTile;
     hipLaunchKernelGGL(cov_syrk_kernel, dim3(nt, nt), dim3(256), 0, s, (const double*)W, n, S);
