@@ -121,6 +121,11 @@ def batched_section(args, b, dia, torch, dev, np):
     return out
 
 
+def sf_fwhm_per_sigma():
+    import math
+    return 2.0 * math.sqrt(2.0 * math.log(2.0))
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else float("nan")
@@ -137,9 +142,10 @@ def emccd_section(args, b, dia, torch, dev, np):
     from scipy.stats import spearmanr
     full = b.R.shape[0]
     phi_I = np.asarray(b.meta["phi_I"])
-    phi_K = np.sqrt(np.maximum(phi_I ** 2 - b.meta["phi_R"] ** 2, 0.25))
+    # the Gaussian start's standard deviation from the FWHM difference sqrt(phi_I^2 - phi_R^2)
+    phi_K = np.sqrt(np.maximum(phi_I ** 2 - b.meta["phi_R"] ** 2, 0.25)) / sf_fwhm_per_sigma()
     ws = dia.Workspace(dev)
-    out = {"workload": (f"{len(b.epochs)} targets of one {full}x{full} field (2000 stars, Gaussian PSF of width "
+    out = {"workload": (f"{len(b.epochs)} targets of one {full}x{full} field (2000 stars, Gaussian PSF of FWHM "
                         f"{b.meta['phi_R']}) and the shared flat, Huber loss with EMCCD model variance "
                         f"(E = {b.meta['excess']}, G = {b.gain})"), "cases": []}
     ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

@@ -196,8 +196,8 @@ int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, doubl
  * first-order optimisers stop on the paper's rule well before the kernel's
  * weak directions have converged.  Each Newton step solves H d = -g with the
  * FP64 Hessian H = sum_p h_p x_p x_p^T (x_p the pixel's design row, h_p the
- * per-pixel curvature: exact for a Gaussian objective with fixed variance,
- * the Gauss-Newton / IRLS weight otherwise) by Cholesky, with a backtracking
+ * exact per-pixel curvature; where that H is not positive definite, the
+ * Gauss-Newton / IRLS weight) by Cholesky, with a backtracking
  * line search on the loss (trial points evaluated at their unrounded FP64
  * values); it stops when the Newton decrement -g.d is below
  * the FP64 resolution of the loss, the step below the FP32 resolution of

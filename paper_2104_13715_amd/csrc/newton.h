@@ -7,9 +7,10 @@ namespace dia {
 
 constexpr int kMaxTheta = DIA_MAX_M * DIA_MAX_M + 1;
 
-// reg = lambda N_data adds the smoothness penalty's Hessian 2 reg L L (Section 2.7) to the kernel block.
+// reg = lambda N_data adds the smoothness penalty's Hessian 2 reg L L (Section 2.7) to the kernel block;
+// damp scales the diagonal by 1 + damp (Levenberg-Marquardt damping of a numerically singular H).
 hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
-                                double reg, hipStream_t s);
+                                double reg, double damp, hipStream_t s);
 hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, const double* th, double* d, double* info,
                              hipStream_t s);
 // Sigma = F^-1 with the validity flag (Section 2.5); A holds F on entry (factored in place),
@@ -33,10 +34,11 @@ NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own
 
 // Hessian of the loss at (theta, theta64) into H (n x n row-major, FP64).  exact = 1: d2L itself;
 // exact = 0: the positive Gauss-Newton / IRLS form used for Newton steps.  partial: partial rows
-// with room for the default tile shape's grid.  reg = lambda N_data of the smoothness penalty.
+// with room for the default tile shape's grid.  reg = lambda N_data of the smoothness penalty; damp
+// scales the diagonal by 1 + damp (0 for the Hessian itself).
 int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, const float* theta,
                  const double* theta64, int exact, double* partial, char* nbase, const NewtonLayout& NL, double* H,
-                 hipStream_t s);
+                 hipStream_t s, double damp = 0.0);
 
 struct NewtonOutcome {
     int steps = 0;      // accepted Newton steps

@@ -72,7 +72,7 @@ bool read_back(void* dst, const void* src, size_t bytes, hipStream_t s) {
 
 int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, const float* theta,
                  const double* theta64, int exact, double* partial, char* nbase, const NewtonLayout& NL, double* H,
-                 hipStream_t s) {
+                 hipStream_t s, double damp) {
     const int grid0 = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, 0), 0);
     TileArgs c = base_args(R, I, theta);
     c.theta64 = theta64;
@@ -100,7 +100,7 @@ int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, d
     ha.partial = reinterpret_cast<double*>(nbase + NL.hpart);
     if (launch_hess(m, ha, s) != hipSuccess) return DIA_E_HIP;
     if (launch_hess_assemble(ha.partial, NL.splits, NL.npb, m, reinterpret_cast<const double*>(nbase + NL.hv), H, reg,
-                             s) !=
+                             damp, s) !=
         hipSuccess)
         return DIA_E_HIP;
     return DIA_OK;
@@ -126,17 +126,33 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
     double L = 0.0;
     if (!read_back(&L, gt + n, sizeof(double), s)) return DIA_E_HIP;
     if (!std::isfinite(L)) return DIA_E_NONFINITE;
+    int form0 = quadratic ? 1 : 0;  // the first Hessian form to try; later steps start at the last that factored
     for (int it = 0; it < max_steps; ++it) {
         const bool factor = (it == 0) || !quadratic;
-        if (factor) {
-            const int rc = hessian_into(R, I, obj, reg, m, v.theta_eval, v.theta_eval64, 0, partial, nbase, NL, H, s);
-            if (rc != DIA_OK) return rc;
-            ++out->evals;
-            ++out->hessians;
-        }
-        if (launch_chol_solve(H, n, factor ? 1 : 0, gt, th, d, info, s) != hipSuccess) return DIA_E_HIP;
         double hinfo[4];
-        if (!read_back(hinfo, info, sizeof(hinfo), s)) return DIA_E_HIP;
+        // The exact Hessian (quadratic convergence; a Huber or model-variance loss makes the
+        // Gauss-Newton form only linearly convergent); where it is not positive definite, the
+        // positive Gauss-Newton / IRLS form (a quadratic loss has one form: exact == Gauss-Newton);
+        // where even that fails in FP64 (a reference PSF so wide that the kernel's high-frequency
+        // modes have curvature below the rounding of the rest), that form with its diagonal scaled
+        // by 1 + 1e-12, 1e-9, 1e-6 (Levenberg-Marquardt).  The FP64 line search keeps every accepted
+        // step a decrease of the true loss.
+        static const double kDamp[] = {0.0, 1e-12, 1e-9, 1e-6};
+        for (int form = form0; form < 5; ++form) {
+            if (factor) {
+                const int rc = hessian_into(R, I, obj, reg, m, v.theta_eval, v.theta_eval64, form == 0 ? 1 : 0,
+                                            partial, nbase, NL, H, s, form == 0 ? 0.0 : kDamp[form - 1]);
+                if (rc != DIA_OK) return rc;
+                ++out->evals;
+                ++out->hessians;
+            }
+            if (launch_chol_solve(H, n, factor ? 1 : 0, gt, th, d, info, s) != hipSuccess) return DIA_E_HIP;
+            if (!read_back(hinfo, info, sizeof(hinfo), s)) return DIA_E_HIP;
+            if (hinfo[0] == 0.0 || !factor) {
+                form0 = form;
+                break;
+            }
+        }
         if (hinfo[0] != 0.0) break;  // not positive definite: keep the current point
         const double dec = hinfo[1];
         // negligible predicted decrease, or a step that moves every parameter by at most two FP32

@@ -32,7 +32,8 @@ __device__ __forceinline__ double lap2_entry(int u, int v, int m) {
 }
 
 __global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partial, int splits, int npb, int m,
-                                                            const double* hv, double* H, double reg) {
+                                                            const double* hv, double* H, double reg,
+                                                            double damp) {
     constexpr int RG = 64;
     const int n = m * m + 1, T = m * m;
     const int nr = (T + RG - 1) / RG;
@@ -46,12 +47,14 @@ __global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partia
         double s = 0.0;
         for (int sp = 0; sp < splits; ++sp) s += partial[((long long)sp * npb + pb) * (RG * RG) + k];
         if (reg > 0.0) s += 2.0 * reg * lap2_entry(t1, t2, m);  // Hessian of the smoothness penalty
+        if (t1 == t2) s *= 1.0 + damp;
         H[(long long)t1 * n + t2] = s;
     }
     if (gid < n) {
         const int t = (int)gid;
-        H[(long long)t * n + (n - 1)] = hv[t];
-        H[(long long)(n - 1) * n + t] = hv[t];
+        const double b = (t == n - 1) ? hv[t] * (1.0 + damp) : hv[t];
+        H[(long long)t * n + (n - 1)] = b;
+        H[(long long)(n - 1) * n + t] = b;
     }
 }
 
@@ -424,10 +427,11 @@ __global__ __launch_bounds__(256) void theta_from_x_kernel(const FitState* st, F
 }
 
 hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
-                                double reg, hipStream_t s) {
+                                double reg, double damp, hipStream_t s) {
     const long long work = std::max<long long>((long long)m * m * m * m, m * m + 1);
     const int blocks = (int)((work + 255) / 256);
-    hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, hv, H, reg);
+    hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, hv, H, reg,
+                       damp);
     return hipGetLastError();
 }
 

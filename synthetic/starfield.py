@@ -281,19 +281,20 @@ def config5(noise=True, n_epochs=256, ref_size=2048, workers=1) -> Batch:
 
 
 # ------------------------------------------------- many small aligned pairs (the EMCCD speed test)
-EMCCD_PHI_R = 1.82   # reference PSF width (Gaussian standard deviation, pixels; Section 5.1)
+EMCCD_PHI_R = 1.82   # reference PSF width (FWHM, pixels; Section 5.1)
 EMCCD_GAIN = 1.0     # ADU per detected photon after the EM stage
 EMCCD_EXCESS = 2.0   # excess noise factor E of the EM register
 
 
 def _emccd_epoch(e: int, R64: np.ndarray, F: np.ndarray, m: int, noise: bool):
     """Target e: the reference broadened to a target PSF width phi_I ~ U(2.2, 4.2) px (median ~3.2;
-    widths are Gaussian standard deviations, as in Section 3.1) by a Gaussian kernel of width
-    sqrt(phi_I^2 - phi_R^2), sum ~ U(0.8, 1.2), subpixel offset ~ U(-0.3, 0.3)^2, B0 ~ U(-20, 20);
-    noise with the EMCCD variance E max(I, 0) / (G F)."""
+    widths are FWHM, the usual measure of an observed PSF) by a Gaussian kernel of FWHM
+    sqrt(phi_I^2 - phi_R^2) (0.5 to 1.5 px standard deviation: from under-sampled to broad), sum
+    ~ U(0.8, 1.2), subpixel offset ~ U(-0.3, 0.3)^2, B0 ~ U(-20, 20); noise with the EMCCD
+    variance E max(I, 0) / (G F)."""
     er = rng_for(6, e + 1)
     phi_I = float(er.uniform(2.2, 4.2))
-    K = kernel_gaussian(m, FWHM_PER_SIGMA * math.sqrt(phi_I ** 2 - EMCCD_PHI_R ** 2), dx=er.uniform(-0.3, 0.3),
+    K = kernel_gaussian(m, math.sqrt(phi_I ** 2 - EMCCD_PHI_R ** 2), dx=er.uniform(-0.3, 0.3),
                         dy=er.uniform(-0.3, 0.3), total=er.uniform(0.8, 1.2))
     B0 = float(er.uniform(-20.0, 20.0))
     I = correlate_target(R64, K, B0)
@@ -308,11 +309,11 @@ def _pool_emccd(a):
 
 def config_emccd(n_epochs: int = 158, size: int = 482, m: int = 19, noise: bool = True, workers: int = 1) -> Batch:
     """Many small aligned pairs shaped like the EMCCD speed test (Section 5.1): a size^2 field of
-    2,000 stars (fluxes log-uniform 1e2..1e5, Gaussian PSF of width phi_R, sky 200) as the shared
+    2,000 stars (fluxes log-uniform 1e2..1e5, Gaussian PSF of FWHM phi_R, sky 200) as the shared
     reference, one flat field F ~ U(0.95, 1.05) per pixel used by every target, and n_epochs
     targets of the whole field.  meta holds phi_R, each target's phi_I, the flat, gain and E."""
     n_stars = int(round(2000 * (size / 482) ** 2))
-    R = star_field(rng_for(6, 0), size, size, n_stars, 1e2, 1e5, "gauss", FWHM_PER_SIGMA * EMCCD_PHI_R, 200.0).astype(np.float32)
+    R = star_field(rng_for(6, 0), size, size, n_stars, 1e2, 1e5, "gauss", EMCCD_PHI_R, 200.0).astype(np.float32)
     F = rng_for(6, 100000).uniform(0.95, 1.05, (size, size))
     R64 = R.astype(np.float64)
     if workers > 1 and n_epochs > 1:

@@ -7,9 +7,9 @@ box-car and from the Gaussian start of width sqrt(phi_I^2 - phi_R^2), must land 
 minimiser: the reported FP64 P, B0 and loss of the final iterate to 1e-4, 1e-4 and 1e-10
 (relative), the returned FP32 kernel to 1e-4 in norm.
 
-These unregularised kernels are far from smooth: their poorly constrained modes reach |K| ~ 1e3
-while P ~ 1, so rounding the kernel to FP32 alone moves sum K by up to 2^-24 sum |K| (~1e-4 of P
-here); the bar on the sum of the returned kernel carries that term.
+Rounding the kernel to FP32 alone moves sum K by up to 2^-24 sum |K|, which can be large against
+P when an unregularised kernel has big poorly constrained modes; the bar on the sum of the
+returned kernel carries that term.
 """
 import numpy as np
 import pytest
@@ -62,7 +62,8 @@ def check(r, th, ref, L_ref, what):
 
 
 def gauss_start(b, m):
-    phi_K = np.sqrt(np.asarray(b.meta["phi_I"]) ** 2 - b.meta["phi_R"] ** 2)
+    # widths are FWHM; the start's Gaussian takes the standard deviation
+    phi_K = np.sqrt(np.asarray(b.meta["phi_I"]) ** 2 - b.meta["phi_R"] ** 2) / sf.FWHM_PER_SIGMA
     yy, xx = np.mgrid[:m, :m] - (m - 1) / 2.0
     rows = []
     for k, e in enumerate(b.epochs):
