@@ -30,6 +30,10 @@ What it computes, with the passage each part follows:
 * ``covariance``     Sec. 2.5: Sigma = F^-1 of the observed Fisher information F (eq. covmatrix),
                      standard errors sqrt(Sigma_pp) (eq. deltatheta), the error of P, and the
                      paper's validity tests of Sigma (determinant and eigenvalues positive)
+* ``poly_terms``, ``norm_coords``, ``model_poly``, ``loss_grad_poly``, ``solve_chi2_poly``
+                     Sec. 2.6: the background B(x, y) = sum b_ab eta^a xi^b of degree d
+                     (eq. polybackground) in the normalised coordinates of eq. normcoords,
+                     replacing the constant B0 (the coefficient b_00 sits where B0 did)
 * ``laplacian``, ``penalty``  Sec. 2.7: the kernel-pixel Laplacian L (eq. laplacian) and the MAP
                      penalty lambda N_data theta^T L^T L theta added to the loss (eq. regularised_loss);
                      ``loss_grad``, ``hessian``, ``solve`` and ``solve_chi2`` include it when
@@ -256,6 +260,88 @@ def loss_grad(R, I, theta, m, obj: Objective):
         L += p
         grad += pg
     return L, grad
+
+
+# ----------------------------------------------------------------------------- spatially varying background
+def poly_terms(d: int):
+    """Exponents (a, b) of the terms eta^a xi^b of eq. polybackground, in its summation order
+    (a = 0..d outer, b = 0..d-a inner); b_00 is the constant background B0."""
+    if d < 0:
+        raise ValueError("degree must be >= 0")
+    return [(a, b) for a in range(d + 1) for b in range(d - a + 1)]
+
+
+def norm_coords(rows: int, cols: int, m: int):
+    """eq. normcoords on the valid region: eta = (x - x_c) / N_x along the columns, xi = (y - y_c) / N_y
+    along the rows, (x, y) the pixel's coordinates on the target grid and (x_c, y_c) = ((N_x - 1)/2,
+    (N_y - 1)/2) its centre (the reading of "image centre" for pixel-centred integer coordinates)."""
+    h = half(m)
+    x = np.arange(h, cols - h, dtype=np.float64)
+    y = np.arange(h, rows - h, dtype=np.float64)
+    eta = (x - (cols - 1) / 2.0) / cols
+    xi = (y - (rows - 1) / 2.0) / rows
+    return (np.broadcast_to(eta[None, :], (y.size, x.size)).copy(),
+            np.broadcast_to(xi[:, None], (y.size, x.size)).copy())
+
+
+def poly_columns(rows: int, cols: int, m: int, d: int) -> np.ndarray:
+    """The background's design columns on the valid region, (Hv, Wv, n_b): eta^a xi^b per term."""
+    eta, xi = norm_coords(rows, cols, m)
+    return np.stack([eta ** a * xi ** b for a, b in poly_terms(d)], axis=-1)
+
+
+def model_poly(R, theta, m, d):
+    """M = R (x) K + B(x, y) on the valid region (eq. model_image with eq. polybackground);
+    theta = [K (m*m, a-major), b in poly_terms(d) order]."""
+    theta = _f64(theta)
+    nb = len(poly_terms(d))
+    if theta.size != m * m + nb:
+        raise ValueError("theta must hold m*m kernel values and the background coefficients")
+    M = model(R, np.concatenate([theta[:m * m], [0.0]]), m)
+    return M + poly_columns(*np.shape(R), m, d) @ theta[m * m:]
+
+
+def loss_grad_poly(R, I, theta, m, obj: Objective, d):
+    """L(theta) and [dL/dK, dL/db] with the polynomial background; the penalty of eq.
+    regularised_loss acts on the kernel only (L is zero on every background coefficient)."""
+    theta = _f64(theta)
+    Iv = _f64(valid(_f64(I), m))
+    M = model_poly(R, theta, m, d)
+    l, g, _ = pixel_terms(obj, Iv, M, m)
+    P = poly_columns(*np.shape(R), m, d)
+    grad = np.concatenate([grad_kernel(R, g, m), np.tensordot(g, P, axes=([0, 1], [0, 1]))])
+    L = float(np.sum(l))
+    if obj.lam > 0.0:
+        p, pg, _ = penalty(np.concatenate([theta[:m * m], [0.0]]), m, obj.lam, n_data(*np.shape(I), m))
+        L += p
+        grad[:m * m] += pg[:m * m]
+    return L, grad
+
+
+def normal_matrix_poly(R, m, d, w, y=None):
+    """X^T diag(w) X and X^T (w y) for the design [R windows (m*m), background terms (n_b)]."""
+    R = _f64(R)
+    Hv, Wv = R.shape[0] - m + 1, R.shape[1] - m + 1
+    P = poly_columns(*R.shape, m, d).reshape(Hv * Wv, -1)
+    win = np.lib.stride_tricks.sliding_window_view(R, (m, m)).reshape(Hv * Wv, m * m)
+    X = np.concatenate([win, P], axis=1)
+    WX = X * w.reshape(-1)[:, None]
+    return X.T @ WX, (None if y is None else WX.T @ y.reshape(-1))
+
+
+def solve_chi2_poly(R, I, m, w, d, refine: int = 3) -> np.ndarray:
+    """Exact minimiser of 1/2 sum w (I - M)^2 with the polynomial background, by Cholesky with
+    residual refinement (each refinement an exact Newton step on the quadratic)."""
+    Iv = _f64(valid(_f64(I), m))
+    A, b = normal_matrix_poly(R, m, d, w, Iv)
+    cf = scipy.linalg.cho_factor(A, lower=True)
+    theta = scipy.linalg.cho_solve(cf, b)
+    P = poly_columns(*np.shape(R), m, d)
+    for _ in range(refine):
+        gv = w * (model_poly(R, theta, m, d) - Iv)
+        g = np.concatenate([grad_kernel(R, gv, m), np.tensordot(gv, P, axes=([0, 1], [0, 1]))])
+        theta = theta - scipy.linalg.cho_solve(cf, g)
+    return theta
 
 
 # ----------------------------------------------------------------------------- kernel regulariser

@@ -635,3 +635,81 @@ def test_regularised_solution_is_stationary(c1_pair, rho, var):
     gp = oracle.penalty(th, m, obj.lam, oracle.n_data(*p.I.shape, m))[1]
     assert np.max(np.abs(g)) <= 1e-7 * (np.max(np.abs(g0)) + np.max(np.abs(gp)))
     assert np.max(np.abs(gp)) > 1e-3 * np.max(np.abs(g0))  # the penalty is active
+
+
+# --------------------------------------------------------------------- spatially varying background (Sec. 2.6)
+def test_poly_terms_and_normalised_coordinates():
+    assert oracle.poly_terms(0) == [(0, 0)]
+    assert len(oracle.poly_terms(3)) == 10  # (d + 1)(d + 2) / 2
+    assert all(a + b <= 3 for a, b in oracle.poly_terms(3))
+    rows, cols, m = 41, 60, 5
+    eta, xi = oracle.norm_coords(rows, cols, m)
+    assert eta.shape == (rows - m + 1, cols - m + 1)
+    # centred on the image centre (the valid region is symmetric about it), steps of 1/N
+    assert abs(eta.sum()) < 1e-12 and abs(xi.sum()) < 1e-12
+    assert np.allclose(np.diff(eta[0]), 1.0 / cols) and np.allclose(np.diff(xi[:, 0]), 1.0 / rows)
+    assert np.all(np.abs(eta) < 0.5) and np.all(np.abs(xi) < 0.5)
+
+
+def test_poly_background_of_degree_zero_is_the_constant_background(c1_pair):
+    p = c1_pair
+    th = oracle.init_theta(p.I, p.m)
+    assert np.array_equal(oracle.model_poly(p.R, th, p.m, 0), oracle.model(p.R, th, p.m))
+    obj = oracle.Objective(rho="huber", var="ccd_model", sigma0=p.sigma0_adu, gain=p.gain)
+    L0, g0 = oracle.loss_grad(p.R, p.I, th, p.m, obj)
+    L1, g1 = oracle.loss_grad_poly(p.R, p.I, th, p.m, obj, 0)
+    assert L0 == pytest.approx(L1, rel=1e-14) and np.allclose(g0, g1, rtol=1e-12, atol=0)
+
+
+def _tilted_target(p, coeffs, d):
+    # the noiseless target with a background written out pixel by pixel from eq. polybackground
+    # and eq. normcoords on the full target grid (independent of the oracle's design columns)
+    H, W = p.R.shape
+    I = sf.correlate_target(p.R.astype(np.float64), p.K_true, 0.0)
+    xc, yc = (W - 1) / 2.0, (H - 1) / 2.0
+    B = np.zeros((H, W))
+    for y in range(H):
+        for x in range(W):
+            eta, xi = (x - xc) / W, (y - yc) / H
+            B[y, x] = sum(c * eta ** a * xi ** b for c, (a, b) in zip(coeffs, oracle.poly_terms(d)))
+    return I + B
+
+
+def test_poly_background_noiseless_recovery(c1_pair):
+    p = c1_pair
+    m, d = p.m, 2
+    coeffs = [40.0, 25.0, -60.0, -35.0, 80.0, 15.0]
+    I = _tilted_target(p, coeffs, d)
+    w = np.ones((p.R.shape[0] - m + 1, p.R.shape[1] - m + 1))
+    th = oracle.solve_chi2_poly(p.R, I, m, w, d)
+    assert np.allclose(th[:m * m], p.K_true.ravel(), rtol=0, atol=1e-9 * np.abs(p.K_true).max())
+    assert np.allclose(th[m * m:], coeffs, rtol=1e-7, atol=1e-7)
+    # a constant background cannot absorb the tilt: the fit is biased and leaves a residual
+    th0 = oracle.solve_chi2(p.R, I, m, w)
+    assert np.max(np.abs(th0[:m * m] - p.K_true.ravel())) > 1e-4 * np.abs(p.K_true).max()
+
+
+def test_normalised_coordinates_condition_the_background_terms():
+    # the paper's reason for eq. normcoords: the terms are closer to orthogonal than in raw pixel
+    # coordinates (the normal matrix of the background columns is far better conditioned)
+    rows, cols, m, d = 200, 300, 9, 3
+    P = oracle.poly_columns(rows, cols, m, d).reshape(-1, len(oracle.poly_terms(d)))
+    h = oracle.half(m)
+    y, x = np.mgrid[h:rows - h, h:cols - h].astype(np.float64)
+    Q = np.stack([x.ravel() ** a * y.ravel() ** b for a, b in oracle.poly_terms(d)], axis=1)
+    assert np.linalg.cond(P.T @ P) < 1e-6 * np.linalg.cond(Q.T @ Q)
+
+
+@pytest.mark.parametrize("rho,var", [("gauss", "ccd_data"), ("huber", "ccd_model")])
+def test_poly_background_gradient_is_the_derivative(c1_pair, rho, var):
+    p = c1_pair
+    m, d = p.m, 2
+    obj = oracle.Objective(rho=rho, var=var, sigma0=p.sigma0_adu, gain=p.gain)
+    th = np.concatenate([p.K_true.ravel(), [5.0, 3.0, -2.0, 4.0, 1.0, -6.0]])
+    _, g = oracle.loss_grad_poly(p.R, p.I, th, m, obj, d)
+    for k in range(m * m, m * m + 6):
+        e = np.zeros_like(th)
+        e[k] = 1e-3
+        fd = (oracle.loss_grad_poly(p.R, p.I, th + e, m, obj, d)[0]
+              - oracle.loss_grad_poly(p.R, p.I, th - e, m, obj, d)[0]) / 2e-3
+        assert fd == pytest.approx(g[k], rel=1e-5, abs=1e-6 * np.abs(g).max())
