@@ -126,3 +126,43 @@ def test_batched_entry_points_reject_the_penalty(dia, c1):
         dia.loss_grad_batched(gpu(p.R), ep, th, p.m, o)
     with pytest.raises(dia.DIAError):
         dia.fit_batched(gpu(p.R), ep, p.m, o)
+
+
+def test_map_uncertainty_matches_oracle(dia, c1):
+    # Section 2.5 at the MAP fit: the observed information includes the penalty's curvature
+    # 2 lambda N_data L L, so the covariance is that of the posterior's Laplace approximation
+    p = c1
+    m = p.m
+    o_or, o_gpu = objs(dia, p, "gauss", "ccd_data", 5.0)
+    th = oracle.solve(p.R, p.I, m, o_or)
+    F = oracle.hessian(p.R, p.I, th, m, o_or)
+    ref = oracle.covariance(F)
+    out = dia.uncertainty(gpu(p.R), gpu(p.I), gpu(th), m, o_gpu)
+    cov = out.cov.cpu().numpy()
+    tol = max(1e-13 * np.linalg.cond(F), 1e-12) + 1e-9  # plus the Hessian's own 1e-9 of max |H|
+    assert out.valid and ref["valid"]
+    assert np.linalg.norm(cov - ref["cov"]) <= 10 * tol * np.linalg.norm(ref["cov"])
+    # the penalty shrinks the kernel's uncertainty against the maximum-likelihood fit
+    o0, g0 = objs(dia, p, "gauss", "ccd_data", 0.0)
+    th0 = oracle.solve(p.R, p.I, m, o0)
+    out0 = dia.uncertainty(gpu(p.R), gpu(p.I), gpu(th0), m, g0)
+    assert np.all(out.sigma.cpu().numpy()[:m * m] < out0.sigma.cpu().numpy()[:m * m])
+
+
+def test_penalty_with_mask_and_one_tap_kernel(dia, c1):
+    p = c1
+    # a mask leaves N_data (the valid-region count) unchanged
+    mask = (np.random.default_rng(9).uniform(size=p.I.shape) > 0.2).astype(np.uint8)
+    kw = dict(rho="cauchy", var="ccd_model", sigma0=p.sigma0_adu, gain=p.gain, lam=2.0)
+    th = theta_off(p, 6)
+    L, g = dia.loss_grad(gpu(p.R), gpu(p.I), gpu(th), p.m, dia.Objective(mask=gpu(mask, torch.uint8), **kw))
+    Lr, gr = oracle.loss_grad(p.R, p.I, th.astype(np.float64), p.m, oracle.Objective(mask=mask, **kw))
+    assert abs(float(L.item()) - Lr) <= 1e-10 * abs(Lr)
+    assert np.linalg.norm(g.cpu().double().numpy() - gr) <= 1e-5 * np.linalg.norm(gr)
+    # m = 1: the one-pixel kernel has no neighbours, so the penalty vanishes
+    th1 = np.array([1.02, -3.0], np.float32)
+    o1 = dia.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain, lam=7.0)
+    o0 = dia.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
+    L1, g1 = dia.loss_grad(gpu(p.R), gpu(p.I), gpu(th1), 1, o1)
+    L0, g0 = dia.loss_grad(gpu(p.R), gpu(p.I), gpu(th1), 1, o0)
+    assert float(L1.item()) == float(L0.item()) and torch.equal(g1, g0)
