@@ -1,6 +1,9 @@
 // C ABI of libdia, batched epochs: every epoch is an independent fit against a crop
 // of one shared reference; all epochs advance together, one persistent launch per
 // optimiser iteration.
+#include <atomic>
+#include <thread>
+
 #include "api_util.h"
 #include "bf16x3.h"
 #include "newton.h"
@@ -48,11 +51,17 @@ int max_chunks(int m, const dia_epoch* ep, int n) {
     return mx;
 }
 
+// Concurrent Newton polishes of a batched fit (each on its own stream and workspace region): the
+// per-epoch Hessian fills the chip for large epochs, but the factorisation, the substitutions and
+// the host round trips of one epoch leave it mostly idle for small ones.
+constexpr int kNewtonLanes = 4;
+
 struct BLayout {
     int n = 0, npp = 0, nld = 0, nchunks = 0;
     size_t partial = 0, gt = 0, th64 = 0, epochs = 0, chunks = 0, cbeg = 0, cend = 0, ints = 0;
     size_t blocks = 0, stride = 0, b_state = 0, b_sel = 0, b_vecs = 0;
     size_t newton = 0;
+    size_t newton_each = 0;  // one Newton region per concurrent polish
     size_t total = 0;
 };
 
@@ -86,12 +95,14 @@ BLayout make_blayout(const dia_epoch* ep, int n_ep, int m, int precision, bool f
         L.stride = L.b_vecs + align_up(vec_bytes(L.nld));
         L.blocks = off;
         off = align_up(off + L.stride * (size_t)n_ep);
-        // Newton polish, one epoch at a time, each with its own layout of this region
+        // Newton polish: kNewtonLanes epochs at a time on their own streams, each lane with its own
+        // region (laid out per epoch as that epoch's size needs)
         size_t need = 0;
         for (int e = 0; e < n_ep; ++e)
             need = std::max(need, newton_layout(m, ep[e].rows, ep[e].cols, /*own_partial=*/true, /*own_H=*/true).total);
+        L.newton_each = align_up(need);
         L.newton = off;
-        off = align_up(off + need);
+        off = align_up(off + L.newton_each * (size_t)std::min(kNewtonLanes, std::max(n_ep, 1)));
     }
     L.total = off;
     return L;
@@ -405,31 +416,64 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
             if (rc != DIA_OK) break;
             std::vector<NewtonOutcome> nw(n);
             if (o.max_newton > 0) {
-                // exact-Hessian polish of every epoch that finished without error, one after another
+                // exact-Hessian polish of every epoch that finished without error, kNewtonLanes at a
+                // time: each lane is a host thread with its own stream and workspace region, taking
+                // epochs from a shared counter (the epochs' states and vectors are disjoint)
                 const bool quad = obj->rho == DIA_RHO_GAUSS && obj->var != DIA_VAR_CCD_MODEL &&
                                   obj->var != DIA_VAR_EMCCD_MODEL;
-                for (int e = 0; e < n && rc == DIA_OK; ++e) {
-                    FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + e * L.stride);
-                    int status = 0;
-                    TRY(hipMemcpyAsync(&status, &st->status, sizeof(int), hipMemcpyDeviceToHost, cs) == hipSuccess);
-                    TRY(hipStreamSynchronize(cs) == hipSuccess);
-                    if (status < 0) continue;
-                    dia_image Re{R.data + (long long)epochs[e].ref_row0 * R.ld + epochs[e].ref_col0, epochs[e].rows,
-                                 epochs[e].cols, R.ld};
-                    dia_image Ie{epochs[e].I, epochs[e].rows, epochs[e].cols, epochs[e].ld};
-                    dia_objective oe = *obj;
-                    oe.weights = epochs[e].weights;
-                    oe.flat = epochs[e].flat;
-                    oe.mask = epochs[e].mask;
-                    const NewtonLayout NL = newton_layout(m, Ie.rows, Ie.cols, true, true);
-                    char* nb = base + L.newton;
-                    const int ge = eval_grid(m, tile_grid_tiles(m, Ie.rows, Ie.cols, 0), 0);
-                    const int pr = newton_polish(Re, Ie, to_params(oe), 0.0, m, ge, 0, st,
-                                                 offset_vecs(v0, (long long)e * L.stride),
-                                                 reinterpret_cast<double*>(nb + NL.part), nb, NL, o.max_newton, quad,
-                                                 cs, &nw[e]);
-                    if (pr != DIA_OK) rc = pr;
+                std::vector<int> status_h(n);
+                TRY(hipMemcpy2DAsync(status_h.data(), sizeof(int), &st0->status, (size_t)L.stride, sizeof(int), n,
+                                     hipMemcpyDeviceToHost, cs) == hipSuccess);
+                TRY(hipStreamSynchronize(cs) == hipSuccess);
+                int device = 0;
+                TRY(hipGetDevice(&device) == hipSuccess);
+                const int lanes = std::min(kNewtonLanes, n);
+                std::atomic<int> next{0};
+                std::vector<int> lane_rc(lanes, DIA_OK);
+                auto lane = [&](int w) {
+                    hipStream_t ls = nullptr;
+                    if (hipSetDevice(device) != hipSuccess ||
+                        hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) {
+                        lane_rc[w] = DIA_E_HIP;
+                        return;
+                    }
+                    char* nb = base + L.newton + (size_t)w * L.newton_each;
+                    for (;;) {
+                        const int e = next.fetch_add(1);
+                        if (e >= n) break;
+                        if (status_h[e] < 0) continue;
+                        FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + e * L.stride);
+                        dia_image Re{R.data + (long long)epochs[e].ref_row0 * R.ld + epochs[e].ref_col0,
+                                     epochs[e].rows, epochs[e].cols, R.ld};
+                        dia_image Ie{epochs[e].I, epochs[e].rows, epochs[e].cols, epochs[e].ld};
+                        dia_objective oe = *obj;
+                        oe.weights = epochs[e].weights;
+                        oe.flat = epochs[e].flat;
+                        oe.mask = epochs[e].mask;
+                        const NewtonLayout NL = newton_layout(m, Ie.rows, Ie.cols, true, true);
+                        const int ge = eval_grid(m, tile_grid_tiles(m, Ie.rows, Ie.cols, 0), 0);
+                        const int pr = newton_polish(Re, Ie, to_params(oe), 0.0, m, ge, 0, st,
+                                                     offset_vecs(v0, (long long)e * L.stride),
+                                                     reinterpret_cast<double*>(nb + NL.part), nb, NL, o.max_newton,
+                                                     quad, ls, &nw[e]);
+                        if (pr != DIA_OK) {
+                            lane_rc[w] = pr;
+                            break;
+                        }
+                    }
+                    (void)hipStreamSynchronize(ls);
+                    (void)hipStreamDestroy(ls);
+                };
+                std::vector<std::thread> pool;
+                try {
+                    for (int w = 1; w < lanes; ++w) pool.emplace_back(lane, w);
+                } catch (...) {
+                    // fewer lanes: the started ones and this thread take every epoch from the counter
                 }
+                lane(0);
+                for (auto& t : pool) t.join();
+                for (int w = 0; w < lanes; ++w)
+                    if (lane_rc[w] != DIA_OK && rc == DIA_OK) rc = lane_rc[w];
                 if (rc != DIA_OK) break;
             }
             TRY(launch_finalize(st0, v0, m, theta, cs, n, (long long)L.stride) == hipSuccess);
