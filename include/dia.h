@@ -286,7 +286,10 @@ int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs /*host[n]*/, int3
 /* Fit every epoch (see dia_fit; opts->max_outer must be 1).  theta is device
  * float[n][m*m+1] (start values when opts->init == DIA_INIT_USER, fits on
  * return); res is host dia_fit_result[n] or NULL.  Returns the most severe
- * status over the epochs; res[e].status holds each epoch's own. */
+ * status over the epochs; res[e].status holds each epoch's own.  Returns after
+ * the fits have finished; the Newton polishes run up to four epochs at a time,
+ * each on a host thread with a stream of its own (on the caller's device) and
+ * its own part of ws. */
 int dia_fit_batched(dia_image R, const dia_epoch* epochs /*host[n]*/, int32_t n, int32_t m,
                     const dia_objective* obj, const dia_fit_opts* opts, int32_t precision, float* theta,
                     dia_fit_result* res, void* ws, size_t ws_bytes, void* stream);
