@@ -256,10 +256,11 @@ struct Autotuner {
     }
 
     // time_fn(variant) returns the measured milliseconds (< 0 on failure).
-    int pick(int m, int sc, int kind, const std::function<float(int)>& time_fn) {
+    // Variants 0 .. n_variants - 1 are candidates (the batched kinds leave out the narrow shape).
+    int pick(int m, int sc, int kind, const std::function<float(int)>& time_fn, int n_variants = kNumVariants) {
         if (const char* pin = std::getenv("DIA_TILE_VARIANT")) {
             const int v = std::atoi(pin);
-            if (v >= 0 && v < kNumVariants && tile_variant_rb(m, v) != 0) return v;
+            if (v >= 0 && v < n_variants && tile_variant_rb(m, v) != 0) return v;
         }
         if (const char* at = std::getenv("DIA_AUTOTUNE"))
             if (std::atoi(at) == 0) return 0;
@@ -268,18 +269,18 @@ struct Autotuner {
             std::lock_guard<std::mutex> lk(mu);
             load_locked();
             auto it = cache.find({name, m, sc, kind});
-            if (it != cache.end() && tile_variant_rb(m, it->second) != 0) return it->second;
+            if (it != cache.end() && it->second < n_variants && tile_variant_rb(m, it->second) != 0) return it->second;
         }
-        // distinct effective shapes only
+        // distinct effective shapes (tile height and width) only
         std::vector<int> cand;
-        std::vector<int> seen_rb;
-        for (int v = 0; v < kNumVariants; ++v) {
-            const int rb = tile_variant_rb(m, v);
-            if (rb == 0) continue;
+        std::vector<std::pair<int, int>> seen;
+        for (int v = 0; v < n_variants; ++v) {
+            int ty = 0, tx = 0;
+            if (tile_dims(m, v, &ty, &tx) != 0) continue;
             bool dup = false;
-            for (int r : seen_rb) dup |= (r == rb);
+            for (const auto& d : seen) dup |= (d.first == ty && d.second == tx);
             if (dup) continue;
-            seen_rb.push_back(rb);
+            seen.emplace_back(ty, tx);
             cand.push_back(v);
         }
         int best = 0;

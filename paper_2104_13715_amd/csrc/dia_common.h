@@ -65,7 +65,11 @@ struct Geo {
     static constexpr int S = 8;
     static constexpr int SP = 10;                        // reference strip pitch (floats per 8 columns)
     static constexpr int GP = 9;                         // g strip pitch (doubles per 8 columns)
-    static constexpr int NS = (256 / M) < 32 ? (256 / M) : 32;
+    // RBV >= 8 asks for the narrow shape (RBV - 8 forward rows per thread): about one wave of column
+    // strips per workgroup, so that images too small to fill the chip with wide tiles still do
+    static constexpr bool NARROW = RBV >= 8;
+    static constexpr int RBR = NARROW ? RBV - 8 : RBV;
+    static constexpr int NS = NARROW ? ((64 / M) > 1 ? (64 / M) : 1) : ((256 / M) < 32 ? (256 / M) : 32);
     static constexpr int NA = M * NS;                    // active threads
     static constexpr int NT = ((NA + 63) / 64) * 64;     // launched threads (whole waves)
     static constexpr int TX = NS * S;
@@ -76,7 +80,7 @@ struct Geo {
     // FP32 reference tile + FP64 g tile
     static constexpr int lds_bytes(int rb) { return 4 * (M * rb + M - 1) * RS + 8 * M * rb * GS; }
     static constexpr int RB_AUTO = lds_bytes(4) <= kLdsBudget ? 4 : (lds_bytes(2) <= kLdsBudget ? 2 : 1);
-    static constexpr int RB = (RBV > 0 && lds_bytes(RBV) <= kLdsBudget) ? RBV : RB_AUTO;
+    static constexpr int RB = (RBR > 0 && lds_bytes(RBR) <= kLdsBudget) ? RBR : RB_AUTO;
     static constexpr int TY = M * RB;
     static constexpr int RH = TY + M - 1;                // reference tile height
     // word offset of column c within a reference row / double offset within a g row
@@ -285,7 +289,7 @@ __device__ __forceinline__ float model_variance(const ObjParams& o, float M, flo
 }
 
 // Launchers for the tiled kernels (tile_kernels.hip).  Return hipError_t.
-constexpr int kNumVariants = 4;  // tile-shape variants: RB = auto, 1, 2, 4
+constexpr int kNumVariants = 5;  // tile-shape variants: RB = auto, 1, 2, 4; narrow with RB = 1
 int tile_variant_rb(int m, int variant);               // effective RB of a variant (0 = not compiled)
 int tile_dims(int m, int variant, int* ty, int* tx);   // tile height / width of a variant
 int tile_grid_tiles(int m, int rows, int cols, int variant = 0);  // tiles of the valid region

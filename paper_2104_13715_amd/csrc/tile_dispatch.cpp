@@ -19,8 +19,14 @@ static int variant_rb_m(int v) {
         case 0: return Geo<M, 0>::RB;
         case 1: return Geo<M, 1>::RB;
         case 2: return Geo<M, 2>::RB;
-        default: return Geo<M, 4>::RB;
+        case 3: return Geo<M, 4>::RB;
+        default: return Geo<M, 9>::RB;
     }
+}
+
+template <int M>
+static int variant_tx_m(int v) {
+    return (v == 4 && HasVariants<M>::value) ? Geo<M, 9>::TX : Geo<M, 0>::TX;
 }
 
 int tile_variant_rb(int m, int variant) {
@@ -41,7 +47,7 @@ int tile_dims(int m, int variant, int* ty, int* tx) {
     switch (m) {
 #define X(MM)                      \
     case MM:                       \
-        *tx = Geo<MM, 0>::TX;      \
+        *tx = variant_tx_m<MM>(variant); \
         break;
         DIA_FOR_EACH_M(X)
 #undef X

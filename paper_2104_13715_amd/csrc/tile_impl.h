@@ -343,7 +343,8 @@ hipError_t TileOps<M>::launch(int mode, int grid, const TileArgs& a, hipStream_t
     if constexpr (HasVariants<M>::value) {
         if (v == 1) return launch_eval_v<M, 1>(grid, a, s);
         if (v == 2) return launch_eval_v<M, 2>(grid, a, s);
-        return launch_eval_v<M, 4>(grid, a, s);
+        if (v == 3) return launch_eval_v<M, 4>(grid, a, s);
+        return launch_eval_v<M, 9>(grid, a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -354,7 +355,8 @@ hipError_t TileOps<M>::launch_batched(int grid, const BatchedArgs& b, hipStream_
     if constexpr (HasVariants<M>::value) {
         if (v == 1) return launch_bv<M, 1>(grid, b, s);
         if (v == 2) return launch_bv<M, 2>(grid, b, s);
-        return launch_bv<M, 4>(grid, b, s);
+        if (v == 3) return launch_bv<M, 4>(grid, b, s);
+        return launch_bv<M, 9>(grid, b, s);
     }
     return hipErrorInvalidValue;
 }
@@ -365,7 +367,8 @@ int TileOps<M>::occupancy(int v, bool batched) {
     if constexpr (HasVariants<M>::value) {
         if (v == 1) return occupancy_for<M, 1>(batched);
         if (v == 2) return occupancy_for<M, 2>(batched);
-        return occupancy_for<M, 4>(batched);
+        if (v == 3) return occupancy_for<M, 4>(batched);
+        return occupancy_for<M, 9>(batched);
     }
     return 1;
 }

@@ -12,8 +12,9 @@ struct HasVariants {
     static constexpr bool value = (M == 9 || M == 17 || M == 19 || M == 25);
 };
 
-// Variant v -> forward rows per thread requested (0 = automatic); variant 3 asks for 4.
-constexpr int variant_rbv(int v) { return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : 0)); }
+// Variant v -> the Geo parameter: forward rows per thread requested (0 = automatic; variant 3 asks
+// for 4), and variant 4 the narrow shape with one row.
+constexpr int variant_rbv(int v) { return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : (v == 4 ? 9 : 0))); }
 
 template <int M>
 struct TileOps {
