@@ -112,6 +112,9 @@ def test_loss_grad_argument_errors_return_before_hip(dia):
     assert _call_loss_grad(dia, R, I, _obj(dia, rho=1, c=0.0)) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia, var=3, var_floor=0.0)) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia, sigma0=0.0, var_floor=0.0)) == dia.E_ARG
+    assert _call_loss_grad(dia, R, I, _obj(dia, lam=-1.0)) == dia.E_ARG
+    assert _call_loss_grad(dia, R, I, _obj(dia, lam=float("nan"))) == dia.E_ARG
+    assert _call_loss_grad(dia, R, I, _obj(dia, lam=float("inf"))) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia), theta=0) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia), ws=0) == dia.E_WORKSPACE
     assert _call_loss_grad(dia, R, I, _obj(dia), ws=0x500001) == dia.E_WORKSPACE
@@ -157,3 +160,25 @@ def test_default_options_follow_the_paper(dia):
     o = dia.fit_options()
     assert o.lr_K == 1e-3 and o.lr_B0 == 10.0 and o.tol_switch == 1e-6
     assert o.history == 10 and o.init == dia.INIT["flat"] and o.max_outer == 1
+
+
+def test_struct_layouts_match_the_header(dia, tmp_path):
+    # the ctypes mirrors of the ABI structs have the C compiler's sizes and field offsets
+    structs = {"dia_image": dia._Image, "dia_objective": dia._Objective, "dia_epoch": dia._Epoch,
+               "dia_fit_opts": dia._FitOpts, "dia_fit_result": dia._FitResult}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "dia.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            cf = "lambda" if (cname == "dia_objective" and fname == "lam") else fname
+            lines.append(f'printf("{cname}.{fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
