@@ -227,3 +227,24 @@ def test_covariance_flags_a_matrix_that_is_not_positive_definite(dia):
     out = dia.covariance(gpu(F, torch.float64), m)
     assert not out.valid
     assert torch.isnan(out.cov).all() and torch.isnan(out.sigma).all() and np.isnan(out.sigma_P)
+
+
+def test_newton_polish_with_a_numerically_singular_hessian(dia):
+    # a reference PSF so wide (sigma 1.82 px) that at m = 19 the Hessian is singular in FP64 (the
+    # oracle's Cholesky of it fails at the truth): the polish falls back from the exact form to the
+    # Gauss-Newton form to Levenberg-Marquardt damping, keeps stepping, and only lowers the loss
+    rng = np.random.default_rng(7)
+    m = 19
+    R = sf.star_field(rng, 256, 256, 600, 1e2, 1e5, "gauss", sf.FWHM_PER_SIGMA * 1.82, 200.0).astype(np.float32)
+    K = sf.kernel_gaussian(m, sf.FWHM_PER_SIGMA * 2.6, total=1.05)
+    I0 = sf.correlate_target(R.astype(np.float64), K, 7.0)
+    I = (I0 + np.sqrt(2.0 * np.clip(I0, 0.0, None)) * rng.standard_normal(I0.shape)).astype(np.float32)
+    o = dia.Objective(rho="huber", var="emccd_model", gain=1.0, excess=2.0)
+    r0 = dia.fit(gpu(R), gpu(I), m, o, max_newton=0)
+    r8 = dia.fit(gpu(R), gpu(I), m, o)
+    print(f"no polish: loss {r0.loss:.10e} stop {r0.stop}; polish: loss {r8.loss:.10e} newton {r8.n_newton} "
+          f"hessians {r8.n_hessian} stop {r8.stop}")
+    assert r0.status >= 0 and r8.status >= 0
+    assert r8.n_newton >= 1 and r8.n_hessian > r8.n_newton  # the first step needed a fallback form
+    assert r8.loss < r0.loss
+    assert np.all(np.isfinite(r8.theta.cpu().numpy()))
