@@ -98,3 +98,31 @@ def test_emccd_single_fit_matches_oracle(dia, case, init):
     for k, e in enumerate(b.epochs):
         r = dia.fit(R, gpu(e.I), m, o, init=init, init_phi=float(phi_K[k]))
         check(r, r.theta.cpu().numpy(), refs[k], losses[k], f"single {init} target {k}")
+
+
+@pytest.mark.parametrize("form", ["single_flat", "single_gauss", "batched_fp32", "batched_bf16x3"])
+def test_emccd_full_size_target_matches_oracle(dia, form):
+    # target 0 of the seeded workload at full size (482^2, m = 19) against the oracle's minimiser
+    # (tests/golden/make_emccd_target0.py), in every fit form
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("emccd_target0", os.path.join(here, "make_emccd_target0.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    b, e = mod.target()
+    m = mod.M
+    ref = np.loadtxt(os.path.join(here, "emccd_target0_oracle_theta.txt"))
+    with open(os.path.join(here, "emccd_target0_oracle_theta.txt")) as f:
+        L_ref = float(f.readline().rsplit("loss", 1)[1])
+    Fd = gpu(b.meta["flat"])
+    o = dia.Objective(rho="huber", var="emccd_model", gain=b.gain, excess=b.meta["excess"], flat=Fd)
+    R, I = gpu(b.R), gpu(e.I)
+    if form.startswith("single"):
+        phi = np.sqrt(b.meta["phi_I"][0] ** 2 - b.meta["phi_R"] ** 2) / sf.FWHM_PER_SIGMA
+        r = dia.fit(R, I, m, o, init=form.split("_")[1], init_phi=float(phi))
+        th = r.theta.cpu().numpy()
+    else:
+        theta, res, st = dia.fit_batched(R, [dia.Epoch(I=I, flat=Fd)], m, o, precision=form.split("_")[1])
+        r, th = res[0], theta[0].cpu().numpy()
+    check(r, th, ref, L_ref, form)
