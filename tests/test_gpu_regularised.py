@@ -166,3 +166,32 @@ def test_penalty_with_mask_and_one_tap_kernel(dia, c1):
     L1, g1 = dia.loss_grad(gpu(p.R), gpu(p.I), gpu(th1), 1, o1)
     L0, g0 = dia.loss_grad(gpu(p.R), gpu(p.I), gpu(th1), 1, o0)
     assert float(L1.item()) == float(L0.item()) and torch.equal(g1, g0)
+
+
+def test_regularised_fit_full_size_emccd_target(dia):
+    # the MAP fit (lambda = 1) of target 0 of the EMCCD workload at full size (482^2, m = 19)
+    # against the oracle's (tests/golden/make_emccd_target0.py)
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("emccd_target0", os.path.join(here, "make_emccd_target0.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    b, e = mod.target()
+    m = mod.M
+    path = os.path.join(here, "emccd_target0_lam1_oracle_theta.txt")
+    ref = np.loadtxt(path)
+    with open(path) as f:
+        L_ref = float(f.readline().rsplit("loss", 1)[1])
+    o = dia.Objective(rho="huber", var="emccd_model", gain=b.gain, excess=b.meta["excess"],
+                      flat=gpu(b.meta["flat"]), lam=1.0)
+    r = dia.fit(gpu(b.R), gpu(e.I), m, o)
+    th = r.theta.cpu().double().numpy()
+    K, Kr = th[:m * m], ref[:m * m]
+    eK = np.linalg.norm(K - Kr) / np.linalg.norm(Kr)
+    eP = abs(r.P - Kr.sum()) / abs(Kr.sum())
+    eB = abs(r.B0 - ref[-1]) / max(abs(ref[-1]), 1.0)
+    eL = abs(r.loss - L_ref) / abs(L_ref)
+    print(f"MAP 482^2: K {eK:.2e} P {eP:.2e} B0 {eB:.2e} loss {eL:.2e} evals {r.n_eval} stop {r.stop}")
+    assert r.status >= 0
+    assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4 and eL <= 1e-10
