@@ -19,7 +19,10 @@ loss/gradient launches on the launch stream), the FP64 CPU oracle timed on
 a bounded sample of the same pair, and ("batched") the split-precision bf16x3
 matrix-core form on 256 epochs of 2048^2 against one shared reference (m = 25)
 beside the plain form on the first 32 of them: fits/s, evaluations per fit and
-the fraction of the BF16 MFMA / FP64 vector peak.
+the fraction of the BF16 MFMA / FP64 vector peak; and ("many_small_pairs") 158
+EMCCD-like targets of one 482^2 field, m = 19, Huber loss with the EMCCD model
+variance: per-image solution times (median, 16th and 84th percentiles) from the
+box-car and Gaussian starts and the MAP fit, and the batched fits/s.
 """
 from __future__ import annotations
 
@@ -264,6 +267,8 @@ def main() -> int:
                          "from a shared 2048^2 reference (m = 17, plain form only); emccd: many small aligned "
                          "pairs, Huber loss with the EMCCD noise model (printed alone)")
     ap.add_argument("--emccd-epochs", type=int, default=158)
+    ap.add_argument("--small-pairs", type=int, default=1,
+                    help="1: add the many-small-pairs section (first of --emccd-sizes / --emccd-m) to the line")
     ap.add_argument("--emccd-sizes", default="482,242", help="central crop sides of the emccd workload")
     ap.add_argument("--emccd-m", default="19,25", help="kernel sizes of the emccd workload")
     ap.add_argument("--emccd-lambda", type=float, default=1.0,
@@ -286,6 +291,14 @@ def main() -> int:
 
     # the batch first: its worker processes start before this process loads the GPU runtime
     batch = make_batch(args, sf) if args.batch_epochs > 0 and not args.profile_kernel else None
+    # the many-small-pairs workload at its first crop and kernel size, as a section of the line
+    small = None
+    if args.small_pairs and args.batch_workload != "emccd" and not (args.only_batched or args.profile_batched
+                                                                      or args.profile_kernel):
+        t0 = time.time()
+        small = sf.config_emccd(n_epochs=args.emccd_epochs, size=int(args.emccd_sizes.split(",")[0]),
+                                m=int(args.emccd_m.split(",")[0]), workers=min(16, os.cpu_count() or 1))
+        print(f"# generated the many-small-pairs batch in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
 
     import torch
 
@@ -401,6 +414,11 @@ def main() -> int:
                          f"x {W - m + 1} columns of the same pair, m={m}"}
 
     batched = batched_section(args, batch, dia, torch, dev, np) if batch is not None else None
+    many_small = None
+    if small is not None:
+        sa = argparse.Namespace(**vars(args))
+        sa.emccd_sizes, sa.emccd_m = args.emccd_sizes.split(",")[0], args.emccd_m.split(",")[0]
+        many_small = emccd_section(sa, small, dia, torch, dev, np)
 
     gtaps = n_eval * taps_per_eval / t_fit / 1e9
     line = {
@@ -432,6 +450,7 @@ def main() -> int:
                      "traffic": traffic},
         "cpu_baseline": cpu,
         "batched": batched,
+        "many_small_pairs": many_small,
     }
     print(json.dumps(line))
     return 0
