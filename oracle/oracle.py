@@ -25,6 +25,7 @@ What it computes, with the passage each part follows:
 * ``fit_clipped``    the B08 outer loop: refit with sigma from the previous model and
                      cumulative |z| > kappa clipping (Sec. 2.1 / Sec. 2.4)
 * ``adam_step``      one bias-corrected Adam update (Sec. 2.3, Kingma & Ba defaults)
+* ``lbfgs_direction`` the L-BFGS search direction by the two-loop recursion (Sec. 2.3)
 * ``init_theta``     B0 = median(I), flat or Gaussian K (Sec. 2.9)
 * ``photometric_scale``  P = sum K (eq. photometric_scale_factor)
 * ``covariance``     Sec. 2.5: Sigma = F^-1 of the observed Fisher information F (eq. covmatrix),
@@ -588,6 +589,25 @@ def adam_step(theta, grad, m1, v1, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mhat = m1 / (1.0 - beta1 ** t)
     vhat = v1 / (1.0 - beta2 ** t)
     return np.asarray(theta, np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m1, v1
+
+
+def lbfgs_direction(g, pairs):
+    """The L-BFGS search direction d = -H g of Sec. 2.3 (eq. newtonupdate with H the quasi-Newton
+    inverse-Hessian estimate), by the two-loop recursion of Nocedal & Wright (Numerical Optimization,
+    Algorithm 7.4): pairs = [(s_i, y_i)] oldest first, each with s_i . y_i > 0; the initial estimate
+    is gamma I with gamma = s.y / y.y of the newest pair (1 when there is none).  Returns d."""
+    q = np.array(g, np.float64)
+    alphas = []
+    for s, y in reversed(pairs):
+        a = float(s @ q) / float(s @ y)
+        q = q - a * y
+        alphas.append(a)
+    gamma = float(pairs[-1][0] @ pairs[-1][1]) / float(pairs[-1][1] @ pairs[-1][1]) if pairs else 1.0
+    r = gamma * q
+    for (s, y), a in zip(pairs, reversed(alphas)):
+        b = float(y @ r) / float(s @ y)
+        r = r + (a - b) * s
+    return -r
 
 
 def init_theta(I, m, kind: str = "flat", phi_K: float = 1.0):

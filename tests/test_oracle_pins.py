@@ -456,6 +456,33 @@ def test_adam_first_step_is_lr_times_sign():
         t1 = t2
 
 
+def test_lbfgs_direction_is_the_bfgs_inverse_hessian_update():
+    # the two-loop recursion applies the inverse-Hessian estimate built by the BFGS update
+    #   H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T,  rho = 1 / s.y,
+    # from H_0 = gamma I, pair by pair (oldest first), written out here as dense matrices
+    rng = np.random.default_rng(12)
+    n = 7
+    A = rng.normal(size=(n, n))
+    A = A @ A.T + n * np.eye(n)  # a convex quadratic: y = A s gives s.y > 0
+    pairs = []
+    for _ in range(4):
+        s = rng.normal(size=n)
+        pairs.append((s, A @ s))
+    g = rng.normal(size=n)
+    s_n, y_n = pairs[-1]
+    H = (s_n @ y_n) / (y_n @ y_n) * np.eye(n)
+    for s, y in pairs:
+        rho = 1.0 / (s @ y)
+        E = np.eye(n) - rho * np.outer(s, y)
+        H = E @ H @ E.T + rho * np.outer(s, s)
+    np.testing.assert_allclose(oracle.lbfgs_direction(g, pairs), -H @ g, rtol=1e-12, atol=1e-12)
+    # no pairs: steepest descent; n A-conjugate pairs of a quadratic (the eigenvectors of A) give the
+    # exact Newton step (the BFGS update keeps the secant condition of every earlier conjugate pair)
+    np.testing.assert_allclose(oracle.lbfgs_direction(g, []), -g, rtol=0, atol=0)
+    full = [(e, A @ e) for e in np.linalg.eigh(A)[1].T]
+    np.testing.assert_allclose(oracle.lbfgs_direction(g, full), -np.linalg.solve(A, g), rtol=1e-10, atol=1e-12)
+
+
 def test_init_theta():
     I = np.arange(1.0, 101.0).reshape(10, 10)
     t = oracle.init_theta(I, 5, "flat")
