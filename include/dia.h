@@ -131,6 +131,16 @@ int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM,
 int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m,
                   double* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
 
+/* dia_loss_grad with FP64 parameters and gradient: theta is device double[m*m+1]
+ * (same layout), grad receives the FP64 reduction, device double[m*m+1].  The
+ * fused pass computes in FP64 from FP64 parameters in either form; this one
+ * skips the FP32 rounding of theta and of the gradient, for callers that
+ * iterate in FP64 (an FP64 autograd parameter, a line search at points closer
+ * than the FP32 spacing).  Same workspace (DIA_OP_LOSS_GRAD) and tile-shape
+ * choice as dia_loss_grad.  Asynchronous on stream. */
+int dia_loss_grad64(dia_image R, dia_image I, const dia_objective* obj, const double* theta, int32_t m,
+                    double* loss, double* grad, void* ws, size_t ws_bytes, void* stream);
+
 /* Observed Fisher information (Section 2.5): the Hessian of L at theta,
  *   H[i * n + j] = d2L / dtheta_i dtheta_j,   n = m*m + 1,
  * FP64, row-major, parameters in theta's order (kernel taps row by row, then
@@ -223,6 +233,10 @@ typedef struct {
     int32_t status;   /* same as the return value                       */
     int32_t n_newton; /* accepted Newton steps, all outer fits          */
     int32_t n_hessian; /* Hessians formed by the Newton polish          */
+    int32_t first_order_stop; /* why the last fit's Adam -> L-BFGS phase stopped (codes of stop
+                                 1 .. 4), before any Newton polish: 4 means that phase hit its
+                                 iteration cap even when the polish then converged          */
+    int32_t reserved;
 } dia_fit_result;
 
 /* Full fit from the chosen initialisation to the stopping rule; theta
@@ -262,7 +276,9 @@ typedef struct {
 } dia_epoch;
 
 /* Arithmetic of the batched contraction.
- *   FP32   : FP32 direct correlation on the vector ALUs (the plain form).
+ *   FP32   : the plain form: direct correlation on the vector ALUs, FP32 images and
+ *            parameters widened exactly to FP64, FP64 products and sums (an FP64 FMA
+ *            issues at the rate of an unpacked FP32 FMA on gfx950).
  *   BF16X3 : forward and dL/dK as implicit GEMMs over the epochs on BF16 matrix
  *            cores, each FP32 operand split x = hi + lo (both bf16) and the
  *            product taken as hi*hi + hi*lo + lo*hi with FP32 accumulation;

@@ -5,6 +5,7 @@ memory and the current stream.  The names follow the C ABI in include/dia.h:
 
 * ``model(R, theta, m)``                       eq. model_image_delta_basis on the valid region
 * ``loss_grad(R, I, theta, m, objective)``     fused forward + objective + backward
+* ``loss_grad64(R, I, theta, m, objective)``   the same at FP64 parameters, FP64 gradient
 * ``fit(R, I, m, objective, **opts)``           Adam then L-BFGS on the device
 * ``DIALoss.apply(theta, R, I, m, objective)``  autograd wrapper around ``loss_grad``
 * ``hessian(R, I, theta, m, objective)``         observed Fisher information (Section 2.5)
@@ -71,7 +72,8 @@ class _FitResult(ctypes.Structure):
     _fields_ = [("loss", ctypes.c_double), ("P", ctypes.c_double), ("B0", ctypes.c_double),
                 ("n_eval", ctypes.c_int32), ("n_adam", ctypes.c_int32), ("n_lbfgs", ctypes.c_int32),
                 ("n_outer", ctypes.c_int32), ("n_masked", ctypes.c_int64), ("stop", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("n_newton", ctypes.c_int32), ("n_hessian", ctypes.c_int32)]
+                ("status", ctypes.c_int32), ("n_newton", ctypes.c_int32), ("n_hessian", ctypes.c_int32),
+                ("first_order_stop", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -81,6 +83,7 @@ _lib.dia_status_string.restype = ctypes.c_char_p
 _lib.dia_workspace_size.argtypes = [_i32, _i32, _i32, _i64, _i32, ctypes.POINTER(_sz)]
 _lib.dia_model.argtypes = [_Image, _vp, _i32, _vp, _i64, _vp]
 _lib.dia_loss_grad.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.dia_loss_grad64.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_hessian.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.dia_covariance.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_opts_default.argtypes = [ctypes.POINTER(_FitOpts)]
@@ -93,13 +96,15 @@ _lib.dia_loss_grad_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i3
                                        _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, ctypes.POINTER(_Objective),
                                  ctypes.POINTER(_FitOpts), _i32, _vp, ctypes.POINTER(_FitResult), _vp, _sz, _vp]
-for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_hessian", "dia_covariance", "dia_fit",
+for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64", "dia_hessian", "dia_covariance", "dia_fit",
            "dia_batched_workspace_size", "dia_loss_grad_batched", "dia_fit_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-PREC = {"fp32": 0, "bf16x3": 1}
+# "fp32" (the C enum's name) and "plain" name the same form: FP32 data, FP64 arithmetic on the vector ALUs
+PREC = {"fp32": 0, "plain": 0, "bf16x3": 1}
 
-EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad", "dia_hessian",
+EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64",
+           "dia_hessian",
            "dia_covariance", "dia_fit_opts_default", "dia_fit", "dia_batched_workspace_size",
            "dia_loss_grad_batched", "dia_fit_batched")
 
@@ -233,6 +238,27 @@ def loss_grad(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, obj
     return loss, grad
 
 
+def loss_grad64(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
+                workspace: Optional[Workspace] = None, loss: Optional[torch.Tensor] = None,
+                grad: Optional[torch.Tensor] = None):
+    """(loss float64[1], grad float64[m*m+1]) at FP64 parameters theta, one fused pass (dia_loss_grad64)."""
+    Ri, Ii = _image(R, "R"), _image(I, "I")
+    if theta.dtype != torch.float64 or theta.numel() != m * m + 1 or not theta.is_contiguous():
+        raise ValueError("theta must be a contiguous float64 tensor of m*m + 1 values")
+    if theta.device != R.device:
+        raise ValueError("theta must live on the images' device")
+    obj = objective._c(I)
+    ws = workspace or Workspace(R.device)
+    p, nb = ws.get(workspace_size(OP_LOSS_GRAD, I.shape[0], I.shape[1], I.stride(0), m))
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=R.device)
+    if grad is None:
+        grad = torch.empty(m * m + 1, dtype=torch.float64, device=R.device)
+    _check(_lib.dia_loss_grad64(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(), grad.data_ptr(),
+                                p, nb, _stream(R.device)), "dia_loss_grad64")
+    return loss, grad
+
+
 def hessian(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
             workspace: Optional[Workspace] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Observed Fisher information: the exact FP64 Hessian d2L/dtheta2, (m*m+1) x (m*m+1)."""
@@ -303,6 +329,7 @@ class FitResult:
     status: int
     n_newton: int = 0
     n_hessian: int = 0
+    first_order_stop: str = "none"
     extra: dict = field(default_factory=dict)
 
     @property
@@ -344,19 +371,23 @@ def fit(R: torch.Tensor, I: torch.Tensor, m: int, objective: Objective, theta: O
     return FitResult(theta=theta, loss=res.loss, P=res.P, B0=res.B0, n_eval=res.n_eval, n_adam=res.n_adam,
                      n_lbfgs=res.n_lbfgs, n_outer=res.n_outer, n_masked=int(res.n_masked),
                      stop=STOP.get(res.stop, str(res.stop)), status=st, n_newton=res.n_newton,
-                     n_hessian=res.n_hessian)
+                     n_hessian=res.n_hessian, first_order_stop=STOP.get(res.first_order_stop, str(res.first_order_stop)))
 
 
 class DIALoss(torch.autograd.Function):
     """L(theta) as a 0-d float64 tensor whose backward is the fused hand-written gradient.
 
-    forward runs one ``dia_loss_grad`` pass and keeps the gradient; backward scales it by the
-    incoming gradient, so no second pass over the images is needed."""
+    forward runs one fused pass and keeps the gradient; backward scales it by the incoming
+    gradient, so no second pass over the images is needed.  A float64 theta goes through
+    ``dia_loss_grad64`` unrounded (FP64 gradient); any other dtype through ``dia_loss_grad``
+    at FP32."""
 
     @staticmethod
     def forward(ctx, theta, R, I, m, objective, workspace=None):
-        t = theta.detach().to(torch.float32).contiguous()
-        loss, grad = loss_grad(R, I, t, m, objective, workspace)
+        if theta.dtype == torch.float64:
+            loss, grad = loss_grad64(R, I, theta.detach().contiguous(), m, objective, workspace)
+        else:
+            loss, grad = loss_grad(R, I, theta.detach().to(torch.float32).contiguous(), m, objective, workspace)
         ctx.save_for_backward(grad)
         ctx.theta_dtype = theta.dtype
         return loss.reshape(())
@@ -443,5 +474,6 @@ def fit_batched(R: torch.Tensor, epochs, m: int, objective: Objective, theta: Op
     out = [FitResult(theta=theta[k], loss=r.loss, P=r.P, B0=r.B0, n_eval=r.n_eval, n_adam=r.n_adam,
                      n_lbfgs=r.n_lbfgs, n_outer=r.n_outer, n_masked=int(r.n_masked),
                      stop=STOP.get(r.stop, str(r.stop)), status=r.status, n_newton=r.n_newton,
-                     n_hessian=r.n_hessian) for k, r in enumerate(res)]
+                     n_hessian=r.n_hessian, first_order_stop=STOP.get(r.first_order_stop, str(r.first_order_stop)))
+           for k, r in enumerate(res)]
     return theta, out, st

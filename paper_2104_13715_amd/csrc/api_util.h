@@ -257,7 +257,10 @@ struct Autotuner {
 
     // time_fn(variant) returns the measured milliseconds (< 0 on failure).
     // Variants 0 .. n_variants - 1 are candidates (the batched kinds leave out the narrow shape).
-    int pick(int m, int sc, int kind, const std::function<float(int)>& time_fn, int n_variants = kNumVariants) {
+    // may_time = false (a call being captured into a graph): a cached choice or the default, nothing
+    // timed and nothing cached.  A choice is cached only when every candidate was timed.
+    int pick(int m, int sc, int kind, const std::function<float(int)>& time_fn, int n_variants = kNumVariants,
+             bool may_time = true) {
         if (const char* pin = std::getenv("DIA_TILE_VARIANT")) {
             const int v = std::atoi(pin);
             if (v >= 0 && v < n_variants && tile_variant_rb(m, v) != 0) return v;
@@ -271,6 +274,7 @@ struct Autotuner {
             auto it = cache.find({name, m, sc, kind});
             if (it != cache.end() && it->second < n_variants && tile_variant_rb(m, it->second) != 0) return it->second;
         }
+        if (!may_time) return 0;
         // distinct effective shapes (tile height and width) only
         std::vector<int> cand;
         std::vector<std::pair<int, int>> seen;
@@ -285,15 +289,18 @@ struct Autotuner {
         }
         int best = 0;
         float best_ms = 1e30f;
+        bool all_timed = true;
         if (cand.size() > 1) {
             for (int v : cand) {
                 const float ms = time_fn(v);
+                all_timed = all_timed && ms >= 0.0f;
                 if (ms >= 0.0f && ms < best_ms) {
                     best_ms = ms;
                     best = v;
                 }
             }
         }
+        if (!all_timed) return best;
         std::lock_guard<std::mutex> lk(mu);
         cache[{name, m, sc, kind}] = best;
         store_locked(name, m, sc, kind, best);
@@ -304,6 +311,13 @@ struct Autotuner {
 inline Autotuner& autotuner() {
     static Autotuner t;
     return t;
+}
+
+// Whether s is being captured into a graph (then nothing may be timed or waited for on it).
+inline bool stream_capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return true;
+    return st != hipStreamCaptureStatusNone;
 }
 
 // Fastest of a few timed runs of fn on stream s, in milliseconds (-1 on error).

@@ -492,6 +492,7 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
             for (int e = 0; e < n; ++e) {
                 int se = fs[e].done ? fs[e].status : DIA_W_NOT_CONVERGED;
                 int stop = fs[e].done ? fs[e].stop : STOP_CAP;
+                const int first_stop = stop;
                 if (se >= 0 && nw[e].converged) se = DIA_OK, stop = STOP_NEWTON;
                 if (se < worst_neg) worst_neg = se;
                 if (se > worst_pos) worst_pos = se;
@@ -508,6 +509,8 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
                     res[e].status = se;
                     res[e].n_newton = nw[e].steps;
                     res[e].n_hessian = nw[e].hessians;
+                    res[e].first_order_stop = first_stop;
+                    res[e].reserved = 0;
                 }
             }
             rc = worst_neg < 0 ? worst_neg : worst_pos;

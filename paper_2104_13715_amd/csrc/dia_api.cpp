@@ -56,12 +56,35 @@ Layout make_layout(int op, int rows, int cols, long long ld, int m) {
 
 // Tile-shape variant for a single-pair evaluation, timed on the caller's data once per
 // (kernel size, size class); the timing passes write only the workspace's partial rows.
+// s must be a stream this library owns (the timing waits on it).
 int choose_variant(const TileArgs& a, int m, hipStream_t s) {
     const int sc = size_class((double)(a.rows - m + 1) * (a.cols - m + 1));
     return autotuner().pick(m, sc, /*kind=*/0, [&](int v) -> float {
         const int grid = eval_grid(m, tile_grid_tiles(m, a.rows, a.cols, v), v);
         return time_launches(s, [&]() { return launch_tile(MODE_EVAL, m, grid, a, s, v) == hipSuccess; });
     });
+}
+
+// The same for a call on the caller's stream: the timing runs on a private stream that first waits
+// for the work already queued on the caller's stream (it writes the workspace); nothing is timed
+// while the caller's stream is being captured into a graph (then a cached choice or the default).
+int choose_variant_for_caller(const TileArgs& a, int m, hipStream_t user) {
+    const int sc = size_class((double)(a.rows - m + 1) * (a.cols - m + 1));
+    if (stream_capturing(user)) return autotuner().pick(m, sc, /*kind=*/0, nullptr, kNumVariants, false);
+    hipStream_t ps = nullptr;
+    hipEvent_t ev = nullptr;
+    int v = 0;
+    if (hipStreamCreateWithFlags(&ps, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess && hipEventRecord(ev, user) == hipSuccess &&
+        hipStreamWaitEvent(ps, ev, 0) == hipSuccess) {
+        v = choose_variant(a, m, ps);
+        (void)hipStreamSynchronize(ps);
+    } else {
+        v = autotuner().pick(m, sc, /*kind=*/0, nullptr, kNumVariants, false);
+    }
+    if (ev) (void)hipEventDestroy(ev);
+    if (ps) (void)hipStreamDestroy(ps);
+    return v;
 }
 
 // One fit (init already done on cs): capture poll_every iterations in a graph, replay until done.
@@ -148,7 +171,7 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
         const int variant = choose_variant(tune, m, cs);
         const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, variant), variant);
 
-        int n_eval = 0, n_adam = 0, n_lbfgs = 0, n_outer = 0, n_newton = 0, n_hess = 0;
+        int n_eval = 0, n_adam = 0, n_lbfgs = 0, n_outer = 0, n_newton = 0, n_hess = 0, first_stop = 0;
         FitState fs;
         std::memset(&fs, 0, sizeof(fs));
         for (int outer = 0; outer < o.max_outer; ++outer) {
@@ -199,6 +222,7 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
             n_adam += fs.n_adam;
             n_lbfgs += fs.n_lbfgs;
             n_outer = outer + 1;
+            first_stop = fs.stop;
             if (fs.status < 0) break;
             if (o.max_newton > 0) {
                 const bool quad = cur.rho == DIA_RHO_GAUSS && cur.var != DIA_VAR_CCD_MODEL &&
@@ -248,6 +272,8 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
             res->status = rc;
             res->n_newton = n_newton;
             res->n_hessian = n_hess;
+            res->first_order_stop = first_stop;
+            res->reserved = 0;
         }
     } while (false);
 #undef TRY
@@ -256,6 +282,54 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
     (void)hipStreamDestroy(cs);
     if (res != nullptr && rc < 0) res->status = rc;
     return rc;
+}
+
+// One fused pass and its reduction on the caller's stream.  Exactly one of theta32 / theta64 is given:
+// FP32 parameters are widened into the workspace first, FP64 ones are read where they are.
+int loss_grad_impl(const dia_image& R, const dia_image& I, const dia_objective* obj, const float* theta32,
+                   const double* theta64, int m, double* loss, float* grad32, double* grad64, void* ws,
+                   size_t ws_bytes, void* stream) {
+    int c = check_image(R);
+    if (c != DIA_OK) return c;
+    if ((c = check_image(I)) != DIA_OK) return c;
+    if (R.rows != I.rows || R.cols != I.cols) return DIA_E_SIZE;
+    if ((c = check_m(m, R.rows, R.cols)) != DIA_OK) return c;
+    if ((c = check_obj(obj)) != DIA_OK) return c;
+    if ((theta32 == nullptr && theta64 == nullptr) || loss == nullptr || (grad32 == nullptr && grad64 == nullptr))
+        return DIA_E_ARG;
+    const Layout L = make_layout(DIA_OP_LOSS_GRAD, R.rows, R.cols, I.ld, m);
+    if ((c = check_ws(ws, ws_bytes, L.total)) != DIA_OK) return c;
+    char* base = static_cast<char*>(ws);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TileArgs a = base_args(R, I, theta32);
+    const double* th64 = theta64;
+    if (th64 == nullptr) {
+        double* w = reinterpret_cast<double*>(base + L.th64);
+        if (launch_widen(theta32, w, L.n, s) != hipSuccess) return DIA_E_HIP;
+        th64 = w;
+    }
+    a.theta64 = th64;
+    a.obj = to_params(*obj);
+    a.partial = reinterpret_cast<double*>(base + L.partial);
+    // the tile shape the fits use for this kernel and image size (timed once per process on the first
+    // call for a size class, on a private stream; the timing passes write only the workspace's partial rows)
+    const int variant = choose_variant_for_caller(a, m, s);
+    const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, variant), variant);
+    if (launch_tile(MODE_EVAL, m, grid, a, s, variant) != hipSuccess) return DIA_E_HIP;
+    ReduceArgs ra;
+    std::memset(&ra, 0, sizeof(ra));
+    ra.partial = a.partial;
+    ra.nblk = grid;
+    ra.npp = L.npp;
+    ra.gt = reinterpret_cast<double*>(base + L.gt);
+    ra.out_loss = loss;
+    ra.out_grad = grad32;
+    ra.out_grad64 = grad64;
+    ra.n = L.n;
+    ra.m = m;
+    ra.reg = penalty_weight(*obj, I, m);
+    ra.th64 = th64;
+    return launch_reduce(ra, s) == hipSuccess ? DIA_OK : DIA_E_HIP;
 }
 
 }  // namespace
@@ -320,41 +394,12 @@ int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM,
 
 int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m, double* loss,
                   float* grad, void* ws, size_t ws_bytes, void* stream) {
-    int c = check_image(R);
-    if (c != DIA_OK) return c;
-    if ((c = check_image(I)) != DIA_OK) return c;
-    if (R.rows != I.rows || R.cols != I.cols) return DIA_E_SIZE;
-    if ((c = check_m(m, R.rows, R.cols)) != DIA_OK) return c;
-    if ((c = check_obj(obj)) != DIA_OK) return c;
-    if (theta == nullptr || loss == nullptr || grad == nullptr) return DIA_E_ARG;
-    const Layout L = make_layout(DIA_OP_LOSS_GRAD, R.rows, R.cols, I.ld, m);
-    if ((c = check_ws(ws, ws_bytes, L.total)) != DIA_OK) return c;
-    char* base = static_cast<char*>(ws);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    TileArgs a = base_args(R, I, theta);
-    double* th64 = reinterpret_cast<double*>(base + L.th64);
-    if (launch_widen(theta, th64, L.n, s) != hipSuccess) return DIA_E_HIP;
-    a.theta64 = th64;
-    a.obj = to_params(*obj);
-    a.partial = reinterpret_cast<double*>(base + L.partial);
-    // the tile shape the fits use for this kernel and image size (timed once per process on the first
-    // call for a size class; the timing passes write only the workspace's partial rows)
-    const int variant = choose_variant(a, m, s);
-    const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, variant), variant);
-    if (launch_tile(MODE_EVAL, m, grid, a, s, variant) != hipSuccess) return DIA_E_HIP;
-    ReduceArgs ra;
-    std::memset(&ra, 0, sizeof(ra));
-    ra.partial = a.partial;
-    ra.nblk = grid;
-    ra.npp = L.npp;
-    ra.gt = reinterpret_cast<double*>(base + L.gt);
-    ra.out_loss = loss;
-    ra.out_grad = grad;
-    ra.n = L.n;
-    ra.m = m;
-    ra.reg = penalty_weight(*obj, I, m);
-    ra.th64 = th64;
-    return launch_reduce(ra, s) == hipSuccess ? DIA_OK : DIA_E_HIP;
+    return loss_grad_impl(R, I, obj, theta, nullptr, m, loss, grad, nullptr, ws, ws_bytes, stream);
+}
+
+int dia_loss_grad64(dia_image R, dia_image I, const dia_objective* obj, const double* theta, int32_t m, double* loss,
+                    double* grad, void* ws, size_t ws_bytes, void* stream) {
+    return loss_grad_impl(R, I, obj, nullptr, theta, m, loss, nullptr, grad, ws, ws_bytes, stream);
 }
 
 int dia_hessian(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m, double* H,

@@ -429,6 +429,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
     if (tid < kReduceCols && col < ra.npp) {
         ra.gt[col] = tot;
         if (ra.out_grad != nullptr && col < ra.n) ra.out_grad[col] = (float)tot;
+        if (ra.out_grad64 != nullptr && col < ra.n) ra.out_grad64[col] = tot;
         if (ra.out_loss != nullptr && col == ra.n) ra.out_loss[0] = tot;
     }
     if (ra.st == nullptr) return;
@@ -491,6 +492,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchRed
     ra.gt = gt;
     ra.out_loss = nullptr;
     ra.out_grad = nullptr;
+    ra.out_grad64 = nullptr;
     ra.st = st;
     ra.v = offset_vecs(br.v, off);
     ra.o = br.o;

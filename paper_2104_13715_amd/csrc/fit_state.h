@@ -65,6 +65,7 @@ struct ReduceArgs {
     double* gt;             // reduced gradient and loss (FP64)
     double* out_loss;       // loss-grad mode: device double[1]
     float* out_grad;        // loss-grad mode: device float[n]
+    double* out_grad64;     // loss-grad mode: device double[n] (the FP64 entry point)
     FitState* st;           // fit mode when non-null
     FitVecs v;
     FitOptsDev o;

@@ -155,12 +155,15 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
         }
         if (hinfo[0] != 0.0) break;  // not positive definite: keep the current point
         const double dec = hinfo[1];
-        // negligible predicted decrease, or a step that moves every parameter by at most two FP32
-        // spacings (the fit is stored in FP32: nothing finer can be represented)
-        if (!(dec > 2e-12 * (std::fabs(L) + 1.0)) || hinfo[2] <= 3e-8 || hinfo[3] <= 2.0) {
+        // a negligible predicted decrease ends the polish at once
+        if (!(dec > 2e-12 * (std::fabs(L) + 1.0))) {
             out->converged = 1;
             break;
         }
+        // a step that moves every parameter by at most two FP32 spacings (the fit is stored in FP32:
+        // nothing finer can be represented), or by at most 3e-8 of the largest parameter, is still
+        // taken through the line search below; the polish ends after it
+        const bool last = hinfo[2] <= 3e-8 || hinfo[3] <= 2.0;
         bool accepted = false;
         double alpha = 1.0;
         for (int ls = 0; ls < 8; ++ls, alpha *= 0.5) {
@@ -184,11 +187,12 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
         if (!accepted) {
             // no trial point lowers the loss: at the resolution of FP32 parameters when the predicted
             // decrease is already tiny against the loss
-            if (dec <= 1e-10 * (std::fabs(L) + 1.0)) out->converged = 1;
+            if (last || dec <= 1e-10 * (std::fabs(L) + 1.0)) out->converged = 1;
             if (launch_newton_trial(th, d, 0.0, v.theta_eval, v.theta_eval64, n, s) != hipSuccess) return DIA_E_HIP;
             break;
         }
         ++out->steps;
+        if (last) out->converged = 1;
         if (out->converged) break;
     }
     if (launch_set_x(st, v, th, n, L, s) != hipSuccess) return DIA_E_HIP;

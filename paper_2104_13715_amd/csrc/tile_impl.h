@@ -11,8 +11,8 @@
 //   3. the per-pixel objective gives l and g = dl/dM in registers (FP64 running
 //      sums of l and g); g goes to an LDS tile — the residual never reaches HBM;
 //   4. backward: dL/dK_ab = sum g_ij R_(i+a)(j+b) — thread (a, strip) correlates the
-//      g tile with the same LDS reference tile into m FP32 accumulators, flushed
-//      into FP64 after every tile.
+//      g tile with the same LDS reference tile into m FP64 accumulators that persist
+//      across the workgroup's tiles.
 // A workgroup reduces its m*m + 2 sums in a fixed order and writes one row of
 // partials; a separate kernel adds the rows in FP64.
 #pragma once

@@ -13,6 +13,7 @@ import pytest
 import torch
 
 import oracle
+from parity import summation_scale
 from synthetic import starfield as sf
 
 pytestmark = [pytest.mark.gpu,
@@ -90,10 +91,8 @@ def test_dialoss_composes_with_torch_autograd(dia, crop):
 def test_dialoss_drives_torch_lbfgs(dia):
     # torch's own L-BFGS on the fused loss.  The reference is background subtracted first (as the
     # paper always does, Section 2.9) so that the raw parameters are not dominated by the
-    # K-B0 coupling.  DIALoss evaluates at the FP32 rounding of torch's FP64 parameters, so
-    # torch's optimiser stops on its own tolerance once neighbouring trial points round alike;
-    # this checks that it gets within 1% of the optimum loss (convergence to the optimum itself
-    # is what dia.fit is for).
+    # K-B0 coupling.  DIALoss evaluates an FP64 parameter unrounded (dia_loss_grad64) and returns
+    # the FP64 gradient, so torch's optimiser converges on the fused loss as on any smooth one.
     p = sf.config1()
     m = p.m
     Rb = (p.R - np.float32(np.mean(p.R, dtype=np.float64))).astype(np.float32)
@@ -117,7 +116,29 @@ def test_dialoss_drives_torch_lbfgs(dia):
     ref = oracle.solve(Rb, p.I, m, o_or)
     Lref, _ = oracle.loss_grad(Rb, p.I, ref, m, o_or)
     assert th.grad.dtype == torch.float64
-    assert L1 < L0 and abs(L1 - Lref) <= 1e-2 * abs(Lref), (L0, L1, Lref)
+    assert L1 < L0 and abs(L1 - Lref) <= 1e-4 * abs(Lref), (L0, L1, Lref)
+    t = th.detach().cpu().numpy()
+    eP = abs(t[:m * m].sum() - ref[:m * m].sum()) / abs(ref[:m * m].sum())
+    assert eP <= 1e-4, eP
+
+
+def test_loss_grad64_matches_oracle_elementwise(dia):
+    # the FP64 entry point at an FP64 point that FP32 cannot represent, against the oracle at the same
+    # point, element by element (loss and every gradient component)
+    p = sf.config1()
+    m = p.m
+    rng = np.random.default_rng(7)
+    t = np.r_[p.K_true.ravel(), p.B0_true] * (1.0 + 1e-9 * rng.standard_normal(m * m + 1)) + 1e-3 * rng.standard_normal(
+        m * m + 1)
+    obj = dia.Objective(rho="cauchy", var="ccd_model", sigma0=p.sigma0_adu, gain=p.gain, c=2.3849)
+    o_or = oracle.Objective(rho="cauchy", var="ccd_model", sigma0=p.sigma0_adu, gain=p.gain, c=2.3849)
+    loss, g = dia.loss_grad64(gpu(p.R), gpu(p.I), torch.tensor(t, dtype=torch.float64, device=DEV), m, obj)
+    L_ref, g_ref = oracle.loss_grad(p.R, p.I, t, m, o_or)
+    assert g.dtype == torch.float64
+    assert abs(loss.item() - L_ref) <= 1e-12 * abs(L_ref)
+    gg = g.cpu().numpy()
+    scale = summation_scale(p.R, p.I, t, m, o_or)
+    assert np.all(np.abs(gg - g_ref) <= 1e-10 * scale), np.max(np.abs(gg - g_ref) / scale)
 
 
 @pytest.fixture(scope="module")
