@@ -54,6 +54,8 @@ extern "C" {
 #define DIA_E_WORKSPACE (-3)    /* workspace NULL, misaligned or smaller than dia_workspace_size  */
 #define DIA_E_HIP (-4)          /* a HIP runtime call failed                                      */
 #define DIA_E_NONFINITE (-5)    /* the loss or gradient became NaN or infinite                    */
+#define DIA_E_SCRATCH (-6)      /* dia_loss_grad_noalloc: the call needs more workspace than the
+                                   library's static scratch, DIA_NOALLOC_SCRATCH_BYTES          */
 
 /* An image in device memory. */
 typedef struct {
@@ -140,6 +142,27 @@ int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const floa
  * choice as dia_loss_grad.  Asynchronous on stream. */
 int dia_loss_grad64(dia_image R, dia_image I, const dia_objective* obj, const double* theta, int32_t m,
                     double* loss, double* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* dia_loss_grad for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, results and kernels as dia_loss_grad, without the workspace:
+ * the partial rows and the reduced gradient live in a static device array of
+ * the library, DIA_NOALLOC_SCRATCH_BYTES on every GPU the library's kernels
+ * are loaded on, held until the process ends.  The call allocates nothing (no hipMalloc,
+ * hipFree, stream or event): the tile shape is one already chosen by an
+ * earlier call for this kernel size and image-size class, else the default
+ * shape; nothing is timed.  The first call on a GPU looks the array up there
+ * (hipGetSymbolAddress) under a lock.  Returns DIA_E_SCRATCH, before anything
+ * is enqueued, when dia_workspace_size(DIA_OP_LOSS_GRAD, ...) exceeds
+ * DIA_NOALLOC_SCRATCH_BYTES (every image fits for m <= 31).  Every call on
+ * one GPU uses that GPU's one array: calls that overlap in time on one GPU
+ * (two streams, two host threads) race and must be ordered by the caller; a
+ * call leaves the array holding its own partial sums, and each call writes
+ * every word it later reads, so nothing needs clearing.  Asynchronous on
+ * stream. */
+#define DIA_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int dia_loss_grad_noalloc(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m,
+                          double* loss, float* grad, void* stream);
 
 /* Observed Fisher information (Section 2.5): the Hessian of L at theta,
  *   H[i * n + j] = d2L / dtheta_i dtheta_j,   n = m*m + 1,

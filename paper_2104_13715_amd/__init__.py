@@ -6,6 +6,7 @@ memory and the current stream.  The names follow the C ABI in include/dia.h:
 * ``model(R, theta, m)``                       eq. model_image_delta_basis on the valid region
 * ``loss_grad(R, I, theta, m, objective)``     fused forward + objective + backward
 * ``loss_grad64(R, I, theta, m, objective)``   the same at FP64 parameters, FP64 gradient
+* ``loss_grad_noalloc(R, I, theta, m, objective)``  loss_grad on the library's static scratch
 * ``fit(R, I, m, objective, **opts)``           Adam then L-BFGS on the device
 * ``DIALoss.apply(theta, R, I, m, objective)``  autograd wrapper around ``loss_grad``
 * ``hessian(R, I, theta, m, objective)``         observed Fisher information (Section 2.5)
@@ -33,7 +34,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 # ----------------------------------------------------------------------------- constants (dia.h)
 MAX_M = 49
 OK, W_NOT_CONVERGED = 0, 1
-E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_NONFINITE = -1, -2, -3, -4, -5
+E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_NONFINITE, E_SCRATCH = -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 16 << 20
 RHO = {"gauss": 0, "huber": 1, "cauchy": 2}
 VAR = {"weights": 0, "ccd_data": 1, "ccd_model": 2, "emccd_data": 3, "emccd_model": 4}
 OP_MODEL, OP_LOSS_GRAD, OP_FIT, OP_FIT_CLIPPED, OP_HESSIAN, OP_COVARIANCE = 0, 1, 2, 3, 4, 5
@@ -84,6 +86,7 @@ _lib.dia_workspace_size.argtypes = [_i32, _i32, _i32, _i64, _i32, ctypes.POINTER
 _lib.dia_model.argtypes = [_Image, _vp, _i32, _vp, _i64, _vp]
 _lib.dia_loss_grad.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_loss_grad64.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
+_lib.dia_loss_grad_noalloc.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp]
 _lib.dia_hessian.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.dia_covariance.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_opts_default.argtypes = [ctypes.POINTER(_FitOpts)]
@@ -96,7 +99,8 @@ _lib.dia_loss_grad_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i3
                                        _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, ctypes.POINTER(_Objective),
                                  ctypes.POINTER(_FitOpts), _i32, _vp, ctypes.POINTER(_FitResult), _vp, _sz, _vp]
-for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64", "dia_hessian", "dia_covariance", "dia_fit",
+for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64", "dia_loss_grad_noalloc",
+           "dia_hessian", "dia_covariance", "dia_fit",
            "dia_batched_workspace_size", "dia_loss_grad_batched", "dia_fit_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -104,7 +108,7 @@ for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64"
 PREC = {"fp32": 0, "plain": 0, "bf16x3": 1}
 
 EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64",
-           "dia_hessian",
+           "dia_loss_grad_noalloc", "dia_hessian",
            "dia_covariance", "dia_fit_opts_default", "dia_fit", "dia_batched_workspace_size",
            "dia_loss_grad_batched", "dia_fit_batched")
 
@@ -256,6 +260,23 @@ def loss_grad64(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, o
         grad = torch.empty(m * m + 1, dtype=torch.float64, device=R.device)
     _check(_lib.dia_loss_grad64(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(), grad.data_ptr(),
                                 p, nb, _stream(R.device)), "dia_loss_grad64")
+    return loss, grad
+
+
+def loss_grad_noalloc(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
+                      loss: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None):
+    """loss_grad without a workspace (dia_loss_grad_noalloc): the library's static device scratch holds
+    the partial sums.  Pass preallocated loss (float64[1]) and grad (float32[m*m+1]) to allocate
+    nothing at all."""
+    Ri, Ii = _image(R, "R"), _image(I, "I")
+    theta = _theta(theta, m, R.device)
+    obj = objective._c(I)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float64, device=R.device)
+    if grad is None:
+        grad = torch.empty(m * m + 1, dtype=torch.float32, device=R.device)
+    _check(_lib.dia_loss_grad_noalloc(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(),
+                                      grad.data_ptr(), _stream(R.device)), "dia_loss_grad_noalloc")
     return loss, grad
 
 

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdia.so")
 SOURCES = ["tile_dispatch.cpp", "fit_kernels.hip", "newton_kernels.hip", "bf16x3_kernels.hip", "dia_api.cpp",
-           "batched_api.cpp", "newton_host.cpp"]
+           "batched_api.cpp", "newton_host.cpp", "noalloc_api.cpp"]
 KERNEL_SIZES = list(range(1, 50, 2))  # one translation unit of tiled kernels per odd kernel size
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

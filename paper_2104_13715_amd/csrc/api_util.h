@@ -338,4 +338,9 @@ inline float time_launches(hipStream_t s, const std::function<bool()>& fn, int r
     return ok ? best : -1.0f;
 }
 
+// One fused pass and its reduction on the caller's stream (dia_api.cpp); see dia_loss_grad.
+int loss_grad_impl(const dia_image& R, const dia_image& I, const dia_objective* obj, const float* theta32,
+                   const double* theta64, int m, double* loss, float* grad32, double* grad64, void* ws,
+                   size_t ws_bytes, void* stream, bool may_time);
+
 }  // namespace dia

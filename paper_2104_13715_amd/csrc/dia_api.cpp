@@ -68,9 +68,10 @@ int choose_variant(const TileArgs& a, int m, hipStream_t s) {
 // The same for a call on the caller's stream: the timing runs on a private stream that first waits
 // for the work already queued on the caller's stream (it writes the workspace); nothing is timed
 // while the caller's stream is being captured into a graph (then a cached choice or the default).
-int choose_variant_for_caller(const TileArgs& a, int m, hipStream_t user) {
+// may_time = false: never time (no stream or event is created), a cached choice or the default.
+int choose_variant_for_caller(const TileArgs& a, int m, hipStream_t user, bool may_time = true) {
     const int sc = size_class((double)(a.rows - m + 1) * (a.cols - m + 1));
-    if (stream_capturing(user)) return autotuner().pick(m, sc, /*kind=*/0, nullptr, kNumVariants, false);
+    if (!may_time || stream_capturing(user)) return autotuner().pick(m, sc, /*kind=*/0, nullptr, kNumVariants, false);
     hipStream_t ps = nullptr;
     hipEvent_t ev = nullptr;
     int v = 0;
@@ -284,11 +285,15 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
     return rc;
 }
 
+}  // namespace
+
 // One fused pass and its reduction on the caller's stream.  Exactly one of theta32 / theta64 is given:
 // FP32 parameters are widened into the workspace first, FP64 ones are read where they are.
+// may_time = false keeps the tile-shape choice to a cached one or the default (nothing is timed,
+// no stream or event is created).
 int loss_grad_impl(const dia_image& R, const dia_image& I, const dia_objective* obj, const float* theta32,
                    const double* theta64, int m, double* loss, float* grad32, double* grad64, void* ws,
-                   size_t ws_bytes, void* stream) {
+                   size_t ws_bytes, void* stream, bool may_time) {
     int c = check_image(R);
     if (c != DIA_OK) return c;
     if ((c = check_image(I)) != DIA_OK) return c;
@@ -313,7 +318,7 @@ int loss_grad_impl(const dia_image& R, const dia_image& I, const dia_objective* 
     a.partial = reinterpret_cast<double*>(base + L.partial);
     // the tile shape the fits use for this kernel and image size (timed once per process on the first
     // call for a size class, on a private stream; the timing passes write only the workspace's partial rows)
-    const int variant = choose_variant_for_caller(a, m, s);
+    const int variant = choose_variant_for_caller(a, m, s, may_time);
     const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, variant), variant);
     if (launch_tile(MODE_EVAL, m, grid, a, s, variant) != hipSuccess) return DIA_E_HIP;
     ReduceArgs ra;
@@ -332,7 +337,6 @@ int loss_grad_impl(const dia_image& R, const dia_image& I, const dia_objective* 
     return launch_reduce(ra, s) == hipSuccess ? DIA_OK : DIA_E_HIP;
 }
 
-}  // namespace
 }  // namespace dia
 
 using namespace dia;
@@ -350,6 +354,8 @@ const char* dia_status_string(int status) {
         case DIA_E_WORKSPACE: return "DIA_E_WORKSPACE: workspace missing, misaligned or too small";
         case DIA_E_HIP: return "DIA_E_HIP: HIP runtime error";
         case DIA_E_NONFINITE: return "DIA_E_NONFINITE: loss or gradient not finite";
+        case DIA_E_SCRATCH:
+            return "DIA_E_SCRATCH: the call needs more than the library's static scratch (DIA_NOALLOC_SCRATCH_BYTES)";
         default: return "unknown status";
     }
 }
@@ -394,12 +400,12 @@ int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM,
 
 int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m, double* loss,
                   float* grad, void* ws, size_t ws_bytes, void* stream) {
-    return loss_grad_impl(R, I, obj, theta, nullptr, m, loss, grad, nullptr, ws, ws_bytes, stream);
+    return loss_grad_impl(R, I, obj, theta, nullptr, m, loss, grad, nullptr, ws, ws_bytes, stream, true);
 }
 
 int dia_loss_grad64(dia_image R, dia_image I, const dia_objective* obj, const double* theta, int32_t m, double* loss,
                     double* grad, void* ws, size_t ws_bytes, void* stream) {
-    return loss_grad_impl(R, I, obj, nullptr, theta, m, loss, nullptr, grad, ws, ws_bytes, stream);
+    return loss_grad_impl(R, I, obj, nullptr, theta, m, loss, nullptr, grad, ws, ws_bytes, stream, true);
 }
 
 int dia_hessian(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m, double* H,

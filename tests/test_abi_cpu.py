@@ -50,7 +50,7 @@ def dia():
 
 def test_status_strings(dia):
     assert dia.status_string(0) == "DIA_OK"
-    for s in (1, -1, -2, -3, -4, -5):
+    for s in (1, -1, -2, -3, -4, -5, -6):
         assert dia.status_string(s).startswith("DIA_")
     assert dia.version() >= 10000
 
