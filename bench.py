@@ -8,9 +8,10 @@ sum 0.9) plus B0 = -12, read noise 8 e-, gain 1.5.  Objective: chi-squared with
 CCD variance from the data.  Inputs are synthetic and seeded; they are
 resident in HBM before timing starts.
 
-A step is one complete fit (flat kernel, B0 = median, Adam then L-BFGS to the
-stopping rule): every optimiser iteration is one fused forward + objective +
-backward pass plus the FP64 reduction and the optimiser update.
+A step is one complete fit (flat kernel, B0 = median; Adam, then L-BFGS on
+the paper's schedule, then the exact-Hessian Newton polish): every optimiser
+iteration is one fused forward + objective + backward pass plus the FP64
+reduction and the optimiser update.
 
 Printed (one JSON line): fwd+bwd Gtap/s sustained through the timed fits
 (value), fits/s, evaluations per fit, the fused kernel's roofline fraction
@@ -44,7 +45,7 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense
 
 def make_batch(args, sf):
     """The batched workload's synthetic inputs, made before anything touches the GPU (the epochs are
-    built in parallel worker processes; each has its own random stream, so the batch is the same)."""
+    built on threads of this process; each has its own random stream, so the batch is the same)."""
     t0 = time.time()
     workers = min(16, os.cpu_count() or 1)
     if args.batch_workload == "emccd":
@@ -54,15 +55,54 @@ def make_batch(args, sf):
         b = sf.config4(n_epochs=args.batch_epochs, workers=workers)
     else:
         b = sf.config5(n_epochs=args.batch_epochs, workers=workers)
-    print(f"# generated {len(b.epochs)}-epoch batch in {time.time() - t0:.1f}s ({workers} processes)",
+    print(f"# generated {len(b.epochs)}-epoch batch in {time.time() - t0:.1f}s ({workers} threads)",
           file=sys.stderr, flush=True)
     return b
+
+
+def oracle_golden(name, b, np):
+    """The oracle's minimisers for this batch's epochs (tests/golden/make_batched_oracle.py), as
+    {epoch: theta}, keeping only epochs whose target sums match the stored ones (the same seeded
+    inputs); empty when the file is missing."""
+    path = os.path.join(ROOT, "tests", "golden", "batched_oracle_thetas.npz")
+    if not os.path.exists(path):
+        return {}
+    z = np.load(path)
+    if f"{name}_epochs" not in z.files:
+        return {}
+    out = {}
+    for e, th, sm in zip(z[f"{name}_epochs"], z[f"{name}_theta"], z[f"{name}_target_sum"]):
+        e = int(e)
+        if e < len(b.epochs) and float(np.sum(b.epochs[e].I, dtype=np.float64)) == float(sm):
+            out[e] = th
+    return out
+
+
+def fit_errors(theta, res, gold, m, np):
+    """Per-fit error against the oracle's minimiser for the epochs in gold: ||dK||/||K||, |dP|/|P| (P of
+    the fit's FP64 iterate), |dB0|/max(|B0|, 1); max and median over those epochs."""
+    th = theta.detach().cpu().double().numpy()
+    eK, eP, eB = [], [], []
+    for e, ref in gold.items():
+        if e >= th.shape[0]:
+            continue
+        Kr = ref[:m * m]
+        eK.append(float(np.linalg.norm(th[e, :m * m] - Kr) / np.linalg.norm(Kr)))
+        eP.append(abs(res[e].P - Kr.sum()) / abs(Kr.sum()))
+        eB.append(abs(res[e].B0 - ref[-1]) / max(abs(ref[-1]), 1.0))
+    if not eK:
+        return None
+    f = lambda x, q: float(f"{np.percentile(x, q):.3g}")
+    return {"epochs_checked": len(eK), "K_rel_max": f(eK, 100), "K_rel_median": f(eK, 50), "P_rel_max": f(eP, 100),
+            "P_rel_median": f(eP, 50), "B0_rel_max": f(eB, 100), "B0_rel_median": f(eB, 50),
+            "within_1e-4": bool(max(eK) <= 1e-4 and max(eP) <= 1e-4 and max(eB) <= 1e-4)}
 
 
 def batched_section(args, b, dia, torch, dev, np):
     """The batched workload (epochs of 2048^2 against one shared 2048^2 reference, m = 25): one batched fit
     and a burst of batched loss/gradient evaluations in each precision.  The plain form runs on the first
-    --batch-fp32-epochs epochs of the same batch."""
+    --batch-plain-epochs epochs of the same batch.  Each fit's error against the oracle's minimiser is
+    reported for the epochs that tests/golden/make_batched_oracle.py solved."""
     uneven = args.batch_workload == "uneven"
     m = b.m
     R = torch.from_numpy(b.R).to(dev)
@@ -80,13 +120,14 @@ def batched_section(args, b, dia, torch, dev, np):
         wl = (f"{n_all} epochs x {side}x{side} against one shared {side}x{side} reference, m={m}, "
               f"chi2 with CCD data variance")
     out = {"workload": wl, "epochs": n_all, "valid_pixels": int(sum(Ps_all))}
+    gold = oracle_golden("c4" if uneven else "c5", b, np)
     if args.profile_batched:
         for _ in range(args.kernel_reps):
             dia.loss_grad_batched(R, eps_all, th_all, m, obj, precision=args.profile_batched, workspace=ws)
         torch.cuda.synchronize()
         return out
     for prec in [p for p in args.batch_precisions.split(",") if p]:
-        n = n_all if prec == "bf16x3" else min(n_all, args.batch_fp32_epochs)
+        n = n_all if prec == "bf16x3" else min(n_all, args.batch_plain_epochs)
         eps, th = eps_all[:n], th_all[:n].contiguous()
         flop = 4.0 * sum(Ps_all[:n]) * m * m  # forward + backward, one FMA (2 FLOP) per tap, every epoch
         for _ in range(2):
@@ -111,7 +152,13 @@ def batched_section(args, b, dia, torch, dev, np):
         rec = {"epochs": n, "fits_per_s": round(n / t_fit, 3), "fit_s": round(t_fit, 2),
                "evals_per_fit_max": int(max(ev)), "evals_per_fit_mean": round(float(np.mean(ev)), 1),
                "eval_ms": round(1e3 * t_eval, 3), "algorithmic_tflops": round(alg, 2), "status": st,
-               "stops": sorted({r.stop for r in res})}
+               "stops": sorted({r.stop for r in res}),
+               "first_order_stops": {k: sum(1 for r in res if r.first_order_stop == k)
+                                     for k in sorted({r.first_order_stop for r in res})},
+               "n_adam_mean": round(float(np.mean([r.n_adam for r in res])), 1),
+               "n_lbfgs_mean": round(float(np.mean([r.n_lbfgs for r in res])), 1),
+               "n_newton_mean": round(float(np.mean([r.n_newton for r in res])), 2),
+               "error_vs_oracle": fit_errors(theta, res, gold, m, np)}
         if prec == "bf16x3":
             rec["mfma_tflops"] = round(3 * alg, 2)
             rec["roofline"] = {"bound": "mfma", "achieved": round(3 * alg, 2), "peak": PEAK_BF16_MFMA_TFLOPS,
@@ -119,7 +166,7 @@ def batched_section(args, b, dia, torch, dev, np):
         else:
             rec["roofline"] = {"bound": "alu", "achieved": round(alg, 2), "peak": PEAK_FP64_VECTOR_TFLOPS,
                                "unit": "TFLOP/s", "frac": round(alg / PEAK_FP64_VECTOR_TFLOPS, 4)}
-        out[prec] = rec
+        out["plain" if prec in ("fp32", "plain") else prec] = rec
         print(f"# batched {prec}: {rec}", file=sys.stderr, flush=True)
     return out
 
@@ -205,7 +252,7 @@ def emccd_section(args, b, dia, torch, dev, np):
             kg /= kg.sum(axis=(1, 2), keepdims=True)
             th_g = torch.from_numpy(kg.reshape(n, -1).astype(np.float32)).to(dev)
             th_g = torch.cat([th_g, torch.stack([I.median() for I in Is])[:, None]], 1).contiguous()
-            for prec in ("fp32", "bf16x3"):
+            for prec in ("plain", "bf16x3"):
                 for init in ("flat", "gauss"):
                     th0 = th_g.clone() if init == "gauss" else None
                     torch.cuda.synchronize()
@@ -257,11 +304,14 @@ def main() -> int:
     ap.add_argument("--init", default="flat", choices=["flat", "gauss"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=1024, help="valid rows of the oracle's timed sample")
+    ap.add_argument("--cpu-b08-rows", type=int, default=96,
+                    help="valid rows of the band on which the oracle's normal matrix is timed")
     ap.add_argument("--batch-epochs", type=int, default=256,
                     help="epochs of the batched split-precision workload (2048^2 each, m = 25); 0 skips it")
-    ap.add_argument("--batch-fp32-epochs", type=int, default=32,
-                    help="the plain form of the batched workload runs on this many of its epochs")
-    ap.add_argument("--batch-precisions", default="bf16x3,fp32")
+    ap.add_argument("--batch-plain-epochs", type=int, default=32,
+                    help="the plain form (FP32 data, FP64 arithmetic on the vector ALUs) of the batched workload "
+                         "runs on this many of its epochs")
+    ap.add_argument("--batch-precisions", default="bf16x3,plain")
     ap.add_argument("--batch-workload", default="shared", choices=["shared", "uneven", "emccd"],
                     help="shared: epochs of 2048^2 on one shared window (m = 25); uneven: sides 512..2048 cut "
                          "from a shared 2048^2 reference (m = 17, plain form only); emccd: many small aligned "
@@ -362,11 +412,15 @@ def main() -> int:
     t_fit = start.elapsed_time(end) / 1e3
     print(f"# {args.steps} fits in {t_fit:.3f}s, evals {[r.n_eval for r in results]}", file=sys.stderr, flush=True)
 
-    # one more fit from the Gaussian initialisation the paper uses in its speed tests (Section 5): the
-    # shape parameter from the known PSF difference, here the second moment of the injected kernel
-    yy, xx = np.mgrid[:m, :m] - (m - 1) / 2.0
-    kt = pair.K_true / pair.K_true.sum()
-    phi_k = float(np.sqrt(0.5 * np.sum(kt * (xx ** 2 + yy ** 2))))
+    # one more fit from the Gaussian initialisation the paper uses in its speed tests (Section 5): standard
+    # deviation sqrt(phi_I^2 - phi_R^2) from the two images' PSF widths (equivalent-circle FWHM of the
+    # reference PSF, and of that PSF carried to the target, as a width measurement on the target's stars
+    # returns), each converted to a Gaussian standard deviation
+    from synthetic.starfield import FWHM_PER_SIGMA, equivalent_fwhm, gaussian_psf, moffat_psf
+    psf = moffat_psf(pair.meta["fwhm"]) if pair.meta["psf"] == "moffat" else gaussian_psf(pair.meta["fwhm"])
+    phi_R = equivalent_fwhm(psf) / FWHM_PER_SIGMA
+    phi_I = equivalent_fwhm(psf, pair.K_true) / FWHM_PER_SIGMA
+    phi_k = float(np.sqrt(max(phi_I ** 2 - phi_R ** 2, 0.25)))
     torch.cuda.synchronize()
     gi0 = time.time()
     rg = dia.fit(R, I, m, obj, workspace=ws, init="gauss", init_phi=phi_k)
@@ -408,10 +462,37 @@ def main() -> int:
             tc += time.time() - t1
             reps += 1
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        cpu = {"value": round(reps * 2 * ps * m * m / tc / 1e9, 4), "unit": "Gtap/s", "cores": cores,
+        gtaps_cpu = reps * 2 * ps * m * m / tc / 1e9
+        # the oracle's B08-style solve (the paper's comparator, Sections 5.1-5.2): the normal matrix
+        # X^T W X (linear in the pixel count) timed on a band of rows and scaled to the whole pair, plus
+        # its Cholesky factorisation and the three residual-refinement passes at the measured tap rate
+        import scipy.linalg
+        brows = min(args.cpu_b08_rows, H - m + 1)
+        w = oracle.fixed_weights(oobj, pair.I[:brows + m - 1], m)
+        t1 = time.time()
+        A, _ = oracle.normal_matrix(pair.R[:brows + m - 1], m, w)
+        t_nm = time.time() - t1
+        t1 = time.time()
+        scipy.linalg.cho_factor(A + np.eye(A.shape[0]) * 1e-300, lower=True)
+        t_chol = time.time() - t1
+        t_b08 = t_nm * P / (brows * (W - m + 1)) + t_chol + 3 * 2.0 * P * m * m / (gtaps_cpu * 1e9)
+        model = "unknown"
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        cpu = {"value": round(gtaps_cpu, 4), "unit": "Gtap/s", "cores": cores,
                "kind": "oracle",
                "sample": f"{reps} FP64 loss+gradient evaluations (direct loops) of the top {rows - m + 1} valid rows "
-                         f"x {W - m + 1} columns of the same pair, m={m}"}
+                         f"x {W - m + 1} columns of the same pair, m={m}",
+               "cpu_model": model,
+               "b08_solve": {"fits_per_s": round(1.0 / t_b08, 5), "seconds_per_fit": round(t_b08, 1),
+                             "sample": f"normal matrix of the top {brows} valid rows ({t_nm:.2f} s) scaled to "
+                                       f"{P} valid pixels, Cholesky ({t_chol * 1e3:.1f} ms), three refinement "
+                                       f"passes at the measured tap rate"}}
 
     batched = batched_section(args, batch, dia, torch, dev, np) if batch is not None else None
     many_small = None
@@ -435,7 +516,8 @@ def main() -> int:
         "dtype": "f64",
         "data": "synthetic (seeded star field, resident in HBM)",
         "config": {"workload": f"single pair {H}x{W}, m={m}, chi2 with CCD data variance, {args.init} init, "
-                               f"Adam->L-BFGS to the stopping rule", "H": H, "W": W, "m": m,
+                               f"Adam then L-BFGS on the paper's schedule, then exact-Hessian Newton polish",
+                   "H": H, "W": W, "m": m,
                    "valid_pixels": P, "objective": "gauss/ccd_data"},
         "fits_per_s": round(args.steps / t_fit, 3),
         "evals_per_fit": round(n_eval / args.steps, 1),
@@ -443,7 +525,12 @@ def main() -> int:
         "fused_pass_us": round(1e6 * t_launch, 2),
         "kernel_gtaps": round(taps_per_eval / t_launch / 1e9, 1),
         "fit_stop": results[-1].stop,
+        "fit_counts": {"n_adam": results[-1].n_adam, "n_lbfgs": results[-1].n_lbfgs,
+                       "n_newton": results[-1].n_newton, "n_hessian": results[-1].n_hessian,
+                       "first_order_stop": results[-1].first_order_stop},
         "gauss_init_fit": {"fits_per_s": round(1.0 / t_gauss, 3), "evals": rg.n_eval, "init_phi": round(phi_k, 4),
+                           "phi_R": round(phi_R, 4), "phi_I": round(phi_I, 4), "n_adam": rg.n_adam,
+                           "n_lbfgs": rg.n_lbfgs, "n_newton": rg.n_newton, "first_order_stop": rg.first_order_stop,
                            "stop": rg.stop},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP64_VECTOR_TFLOPS, 4),

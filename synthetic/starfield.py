@@ -125,6 +125,28 @@ def add_ccd_noise(I_nl: np.ndarray, gain: float, sigma0_e: float, rng: np.random
     return e / gain
 
 
+def equivalent_fwhm(psf, K: np.ndarray | None = None, half_extent: float = 12.0, oversample: int = 10) -> float:
+    """FWHM (pixels) of the circle whose area equals the area above half maximum of a PSF profile,
+    measured on a grid oversampled ``oversample`` times per pixel.  psf is a radial profile f(r^2)
+    (gaussian_psf / moffat_psf); with K the profile is that PSF correlated with the pixel kernel K
+    (the PSF of a target made from the reference by K), which is what a width measurement on the
+    target's stars returns."""
+    t = np.arange(-half_extent, half_extent + 1e-9, 1.0 / oversample)
+    yy, xx = np.meshgrid(t, t, indexing="ij")
+    if K is None:
+        img = psf(xx * xx + yy * yy)
+    else:
+        h = (K.shape[0] - 1) // 2
+        img = np.zeros_like(xx)
+        for a in range(K.shape[0]):
+            for b in range(K.shape[1]):
+                if K[a, b] != 0.0:
+                    dy, dx = a - h, b - h
+                    img += K[a, b] * psf((xx + dx) ** 2 + (yy + dy) ** 2)
+    area = np.count_nonzero(img >= 0.5 * img.max()) / (oversample * oversample)
+    return 2.0 * math.sqrt(area / math.pi)
+
+
 # ----------------------------------------------------------------------- workloads
 @dataclass
 class Pair:
@@ -232,16 +254,15 @@ def _batched_epoch(config: int, e: int, R64: np.ndarray, m: int, ref_size: int, 
     return Epoch(I=I.astype(np.float32), row0=r0, col0=c0, K_true=K, B0_true=B0)
 
 
-_POOL_R64 = None
-
-
-def _pool_init(R64):
-    global _POOL_R64
-    _POOL_R64 = R64
-
-
-def _pool_epoch(a):
-    return _batched_epoch(a[0], a[1], _POOL_R64, *a[2:])
+def _map_epochs(fn, n_epochs: int, workers: int):
+    """[fn(0), ..., fn(n_epochs - 1)], on that many threads of this process when workers > 1 (the FFTs and
+    the random draws release the GIL; no child process is started, so callers need no __main__ guard
+    and a profiler attached to this process sees no extra processes)."""
+    if workers > 1 and n_epochs > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(workers, n_epochs)) as ex:
+            return list(ex.map(fn, range(n_epochs)))
+    return [fn(e) for e in range(n_epochs)]
 
 
 def batched(config: int, n_epochs: int, m: int, ref_size: int, n_stars: int, side_range, *,
@@ -251,19 +272,13 @@ def batched(config: int, n_epochs: int, m: int, ref_size: int, n_stars: int, sid
     Each epoch e draws a square side in ``side_range`` (inclusive), a crop offset uniform in
     [0, ref_size - side], a Gaussian kernel with FWHM ~ U(1.2, 3.0), sum ~ U(0.7, 1.3) and
     subpixel offset ~ U(-0.5, 0.5)^2, and B0 ~ U(-50, 50).  With workers > 1 the epochs are made
-    in that many freshly started worker processes (identical result: each epoch has its own
-    random stream)."""
+    on that many threads (identical result: each epoch has its own random stream)."""
     rng = rng_for(config, 0)
     R = star_field(rng, ref_size, ref_size, n_stars, 1e2, 1e6, "moffat", fwhm, 500.0).astype(np.float32)
     R64 = R.astype(np.float64)
     gain, sigma0_e = 1.5, 8.0
     tail = (m, ref_size, side_range, noise, gain, sigma0_e)
-    if workers > 1 and n_epochs > 1:
-        import multiprocessing as mp
-        with mp.get_context("spawn").Pool(min(workers, n_epochs), initializer=_pool_init, initargs=(R64,)) as pool:
-            epochs = pool.map(_pool_epoch, [(config, e) + tail for e in range(n_epochs)], chunksize=1)
-    else:
-        epochs = [_batched_epoch(config, e, R64, *tail) for e in range(n_epochs)]
+    epochs = _map_epochs(lambda e: _batched_epoch(config, e, R64, *tail), n_epochs, workers)
     return Batch(R=R, epochs=epochs, m=m, sigma0_adu=sigma0_e / gain, gain=gain,
                  meta=dict(config=config, ref_size=ref_size, n_stars=n_stars, side_range=side_range))
 
@@ -303,10 +318,6 @@ def _emccd_epoch(e: int, R64: np.ndarray, F: np.ndarray, m: int, noise: bool):
     return Epoch(I=I.astype(np.float32), row0=0, col0=0, K_true=K, B0_true=B0), phi_I
 
 
-def _pool_emccd(a):
-    return _emccd_epoch(a[0], _POOL_R64[0], _POOL_R64[1], a[1], a[2])
-
-
 def config_emccd(n_epochs: int = 158, size: int = 482, m: int = 19, noise: bool = True, workers: int = 1) -> Batch:
     """Many small aligned pairs shaped like the EMCCD speed test (Section 5.1): a size^2 field of
     2,000 stars (fluxes log-uniform 1e2..1e5, Gaussian PSF of FWHM phi_R, sky 200) as the shared
@@ -316,12 +327,7 @@ def config_emccd(n_epochs: int = 158, size: int = 482, m: int = 19, noise: bool 
     R = star_field(rng_for(6, 0), size, size, n_stars, 1e2, 1e5, "gauss", EMCCD_PHI_R, 200.0).astype(np.float32)
     F = rng_for(6, 100000).uniform(0.95, 1.05, (size, size))
     R64 = R.astype(np.float64)
-    if workers > 1 and n_epochs > 1:
-        import multiprocessing as mp
-        with mp.get_context("spawn").Pool(min(workers, n_epochs), initializer=_pool_init, initargs=((R64, F),)) as pool:
-            out = pool.map(_pool_emccd, [(e, m, noise) for e in range(n_epochs)], chunksize=1)
-    else:
-        out = [_emccd_epoch(e, R64, F, m, noise) for e in range(n_epochs)]
+    out = _map_epochs(lambda e: _emccd_epoch(e, R64, F, m, noise), n_epochs, workers)
     return Batch(R=R, epochs=[o[0] for o in out], m=m, sigma0_adu=0.0, gain=EMCCD_GAIN,
                  meta=dict(config="emccd", size=size, n_stars=n_stars, phi_R=EMCCD_PHI_R,
                            phi_I=[o[1] for o in out], flat=F.astype(np.float32), excess=EMCCD_EXCESS))
