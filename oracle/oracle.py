@@ -31,7 +31,8 @@ What it computes, with the passage each part follows:
 * ``covariance``     Sec. 2.5: Sigma = F^-1 of the observed Fisher information F (eq. covmatrix),
                      standard errors sqrt(Sigma_pp) (eq. deltatheta), the error of P, and the
                      paper's validity tests of Sigma (determinant and eigenvalues positive)
-* ``poly_terms``, ``norm_coords``, ``model_poly``, ``loss_grad_poly``, ``solve_chi2_poly``
+* ``poly_terms``, ``norm_coords``, ``model_poly``, ``loss_grad_poly``, ``solve_chi2_poly``,
+  ``hessian_poly``, ``solve_poly``
                      Sec. 2.6: the background B(x, y) = sum b_ab eta^a xi^b of degree d
                      (eq. polybackground) in the normalised coordinates of eq. normcoords,
                      replacing the constant B0 (the coefficient b_00 sits where B0 did)
@@ -342,6 +343,67 @@ def solve_chi2_poly(R, I, m, w, d, refine: int = 3) -> np.ndarray:
         gv = w * (model_poly(R, theta, m, d) - Iv)
         g = np.concatenate([grad_kernel(R, gv, m), np.tensordot(gv, P, axes=([0, 1], [0, 1]))])
         theta = theta - scipy.linalg.cho_solve(cf, g)
+    return theta
+
+
+def _penalty_poly(theta, m, d, lam, N):
+    """The penalty of eq. regularised_loss with a polynomial background: it acts on the kernel only,
+    so (value, gradient, Hessian) are those of the kernel block with every coefficient free."""
+    nb = len(poly_terms(d))
+    p, pg, ph = penalty(np.concatenate([_f64(theta)[:m * m], [0.0]]), m, lam, N)
+    g = np.zeros(m * m + nb)
+    g[:m * m] = pg[:m * m]
+    H = np.zeros((m * m + nb, m * m + nb))
+    H[:m * m, :m * m] = ph[:m * m, :m * m]
+    return p, g, H
+
+
+def hessian_poly(R, I, theta, m, obj: Objective, d):
+    """X^T diag(l'') X for the design [R windows, background terms] (Sec. 2.5 with Sec. 2.6), plus the
+    penalty's Hessian on the kernel block when obj.lam > 0."""
+    Iv = _f64(valid(_f64(I), m))
+    M = model_poly(R, theta, m, d)
+    _, _, h = pixel_terms(obj, Iv, M, m)
+    A, _ = normal_matrix_poly(R, m, d, h)
+    if obj.lam > 0.0:
+        A = A + _penalty_poly(theta, m, d, obj.lam, n_data(*np.shape(I), m))[2]
+    return A
+
+
+def solve_poly(R, I, m, obj: Objective, d, max_iter: int = 100):
+    """Stationary point of L(theta) with the degree-d background: the steps of ``solve`` (damped Newton
+    on the exact Hessian, the IRLS surrogate where it is not positive definite, Armijo backtracking)
+    on the design [R windows, background terms].  Starts from the chi-squared solution with sigma from
+    the data (for rho = gauss with fixed sigma that solution is the answer, refined by Newton steps)."""
+    Iv = _f64(valid(_f64(I), m))
+    N = n_data(*np.shape(I), m)
+    start = Objective(rho="gauss", var=obj.var.replace("model", "data"), sigma0=obj.sigma0, gain=obj.gain,
+                      excess=obj.excess, var_floor=obj.var_floor, weights=obj.weights, flat=obj.flat, mask=obj.mask)
+    theta = solve_chi2_poly(R, I, m, fixed_weights(start, I, m), d)
+    L, g = loss_grad_poly(R, I, theta, m, obj, d)
+    for _ in range(max_iter):
+        M = model_poly(R, theta, m, d)
+        A = hessian_poly(R, I, theta, m, obj, d)
+        try:
+            step = -scipy.linalg.cho_solve(scipy.linalg.cho_factor(A, lower=True), g)
+        except np.linalg.LinAlgError:
+            A, _ = normal_matrix_poly(R, m, d, _irls_weights(obj, Iv, M, m))
+            if obj.lam > 0.0:
+                A = A + _penalty_poly(theta, m, d, obj.lam, N)[2]
+            step = -scipy.linalg.cho_solve(scipy.linalg.cho_factor(A, lower=True), g)
+        slope = float(g @ step)
+        t = 1.0
+        while True:
+            cand = theta + t * step
+            Lc, gc = loss_grad_poly(R, I, cand, m, obj, d)
+            if Lc <= L + 1e-4 * t * slope or t < 1e-10:
+                break
+            t *= 0.5
+        done = np.linalg.norm(t * step) <= 1e-13 * max(1.0, np.linalg.norm(theta)) or Lc >= L
+        if Lc <= L:
+            theta, L, g = cand, Lc, gc
+        if done:
+            break
     return theta
 
 

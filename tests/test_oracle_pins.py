@@ -825,3 +825,71 @@ def test_poly_background_gradient_is_the_derivative(c1_pair, rho, var):
         fd = (oracle.loss_grad_poly(p.R, p.I, th + e, m, obj, d)[0]
               - oracle.loss_grad_poly(p.R, p.I, th - e, m, obj, d)[0]) / 2e-3
         assert fd == pytest.approx(g[k], rel=1e-5, abs=1e-6 * np.abs(g).max())
+
+
+def test_poly_hessian_is_the_jacobian_of_the_gradient(c1_pair):
+    # every column of hessian_poly against central differences of loss_grad_poly's gradient (Cauchy loss,
+    # model variance, degree 2), and the kernel block's penalty term with lambda > 0
+    p = c1_pair
+    m, d = p.m, 2
+    th = np.concatenate([p.K_true.ravel() * 1.02, [5.0, 3.0, -2.0, 4.0, 1.0, -6.0]])
+    for lam in (0.0, 0.3):
+        obj = oracle.Objective(rho="cauchy", var="ccd_model", sigma0=p.sigma0_adu, gain=p.gain, c=2.3849, lam=lam)
+        H = oracle.hessian_poly(p.R, p.I, th, m, obj, d)
+        assert np.allclose(H, H.T, rtol=1e-12, atol=1e-13 * np.abs(H).max())
+        cols = list(range(0, m * m, 7)) + list(range(m * m, m * m + 6))
+        for k in cols:
+            hk = 1e-6 if k < m * m else 1e-4
+            e = np.zeros_like(th)
+            e[k] = hk
+            fd = (oracle.loss_grad_poly(p.R, p.I, th + e, m, obj, d)[1]
+                  - oracle.loss_grad_poly(p.R, p.I, th - e, m, obj, d)[1]) / (2 * hk)
+            assert np.allclose(fd, H[:, k], rtol=1e-5, atol=1e-6 * np.abs(H[:, k]).max()), k
+
+
+def test_poly_hessian_of_degree_zero_is_the_hessian(c1_pair):
+    p = c1_pair
+    th = np.r_[p.K_true.ravel(), p.B0_true]
+    obj = oracle.Objective(rho="huber", var="emccd_model", gain=p.gain, excess=2.0, lam=0.5)
+    assert np.allclose(oracle.hessian_poly(p.R, p.I, th, p.m, obj, 0), oracle.hessian(p.R, p.I, th, p.m, obj),
+                       rtol=1e-12, atol=0)
+
+
+def test_solve_poly_chi2_is_the_normal_equations_solution(c1_pair):
+    p = c1_pair
+    m, d = p.m, 2
+    obj = oracle.Objective(rho="gauss", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain)
+    I = _tilted_target(p, [40.0, 25.0, -60.0, -35.0, 80.0, 15.0], d) + sf.rng_for(0, 77).normal(0, 3.0, p.R.shape)
+    th = oracle.solve_poly(p.R, I, m, obj, d)
+    ref = oracle.solve_chi2_poly(p.R, I, m, oracle.fixed_weights(obj, I, m), d)
+    assert np.allclose(th, ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
+def test_solve_poly_robust_loss_recovers_a_noiseless_background(c1_pair):
+    # noiseless target with a degree-2 background: every residual vanishes at the truth, where the
+    # Cauchy loss with fixed sigma takes its minimum
+    p = c1_pair
+    m, d = p.m, 2
+    coeffs = [40.0, 25.0, -60.0, -35.0, 80.0, 15.0]
+    I = _tilted_target(p, coeffs, d)
+    obj = oracle.Objective(rho="cauchy", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain, c=2.3849)
+    th = oracle.solve_poly(p.R, I, m, obj, d)
+    assert np.allclose(th[:m * m], p.K_true.ravel(), rtol=0, atol=1e-8 * np.abs(p.K_true).max())
+    assert np.allclose(th[m * m:], coeffs, rtol=1e-7, atol=1e-7)
+
+
+def test_solve_poly_is_stationary_and_reduces_to_solve(c1_pair):
+    p = c1_pair
+    m = p.m
+    obj = oracle.Objective(rho="cauchy", var="ccd_model", sigma0=p.sigma0_adu, gain=p.gain, c=2.3849)
+    th0 = oracle.solve_poly(p.R, p.I, m, obj, 0)
+    assert np.allclose(th0, oracle.solve(p.R, p.I, m, obj), rtol=1e-9, atol=1e-9 * np.abs(th0).max())
+    I = _tilted_target(p, [10.0, 5.0, -8.0], 1) + (p.I - p.I_noiseless)
+    th = oracle.solve_poly(p.R, I, m, obj, 1)
+    _, g = oracle.loss_grad_poly(p.R, I, th, m, obj, 1)
+    Iv = oracle.valid(I.astype(np.float64), m)
+    _, gp, _ = oracle.pixel_terms(obj, Iv, oracle.model_poly(p.R, th, m, 1), m)
+    scale = np.concatenate([oracle.grad_kernel(np.abs(p.R.astype(np.float64)), np.abs(gp), m),
+                            np.abs(gp).reshape(-1) @ np.abs(oracle.poly_columns(*p.R.shape, m, 1)).reshape(-1, 3)])
+    assert np.all(np.abs(g) <= 1e-10 * scale)
+    np.linalg.cholesky(oracle.hessian_poly(p.R, I, th, m, obj, 1))
