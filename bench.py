@@ -303,6 +303,8 @@ def main() -> int:
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--init", default="flat", choices=["flat", "gauss"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--newton-schedule", type=int, default=1,
+                    help="1: also time the exact-Hessian schedule (Adam to 1e-4, then Newton) on the same pair")
     ap.add_argument("--cpu-rows", type=int, default=1024, help="valid rows of the oracle's timed sample")
     ap.add_argument("--cpu-b08-rows", type=int, default=96,
                     help="valid rows of the band on which the oracle's normal matrix is timed")
@@ -427,6 +429,35 @@ def main() -> int:
     torch.cuda.synchronize()
     t_gauss = time.time() - gi0
 
+    # the same pair fitted on the exact-Hessian schedule: Adam to a looser switch (1e-4), no L-BFGS phase,
+    # then Newton steps (eq. newtonupdate with the exact FP64 Hessian) to convergence, chi-squared and
+    # Cauchy, each against the oracle's minimiser (tests/golden/make_c3_fit.py)
+    newton_sched = None
+    if args.newton_schedule and args.size == 4096:
+        newton_sched = {"options": {"tol_switch": 1e-4, "max_lbfgs": 0, "max_newton": 30, "init": args.init}}
+        for rho, gname in (("gauss", "c3_chi2_oracle_theta.txt"), ("cauchy", "c3_cauchy_oracle_theta.txt")):
+            o_r = dia.Objective(rho=rho, var="ccd_data", sigma0=pair.sigma0_adu, gain=pair.gain, c=2.3849)
+            kw = dict(init=args.init, init_phi=1.0, tol_switch=1e-4, max_lbfgs=0, max_newton=30)
+            dia.fit(R, I, m, o_r, workspace=ws, **kw)
+            torch.cuda.synchronize()
+            reps = 5
+            t1 = time.time()
+            for _ in range(reps):
+                rn = dia.fit(R, I, m, o_r, workspace=ws, **kw)
+            torch.cuda.synchronize()
+            tn = (time.time() - t1) / reps
+            rec = {"fits_per_s": round(1.0 / tn, 3), "evals": rn.n_eval, "n_adam": rn.n_adam, "n_newton": rn.n_newton,
+                   "n_hessian": rn.n_hessian, "stop": rn.stop, "status": rn.status}
+            gpath = os.path.join(ROOT, "tests", "golden", gname)
+            if os.path.exists(gpath):
+                ref = np.loadtxt(gpath)
+                th = rn.theta.cpu().double().numpy()
+                rec["K_rel_err"] = float(f"{np.linalg.norm(th[:m * m] - ref[:m * m]) / np.linalg.norm(ref[:m * m]):.3g}")
+                rec["P_rel_err"] = float(f"{abs(rn.P - ref[:m * m].sum()) / abs(ref[:m * m].sum()):.3g}")
+                rec["B0_rel_err"] = float(f"{abs(rn.B0 - ref[-1]) / max(abs(ref[-1]), 1.0):.3g}")
+            newton_sched["chi2" if rho == "gauss" else "cauchy"] = rec
+            print(f"# newton schedule {rho}: {rec}", file=sys.stderr, flush=True)
+
     # ------------------------------------------------------------------ kernel duration: burst of fused passes
     theta = results[-1].theta.clone()
     loss = torch.empty(1, dtype=torch.float64, device=dev)
@@ -535,6 +566,7 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP64_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP64_VECTOR_TFLOPS, 4),
                      "traffic": traffic},
+        "newton_schedule": newton_sched,
         "cpu_baseline": cpu,
         "batched": batched,
         "many_small_pairs": many_small,

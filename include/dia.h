@@ -19,7 +19,11 @@
  *   excluded): valid output (i, j), 0 <= i <= rows-m, 0 <= j <= cols-m, is
  *   target pixel (i + h, j + h) with h = (m - 1) / 2.
  * - theta is m*m + 1 floats: K row-major (K[a*m + b], a = row offset,
- *   b = column offset, the kernel centre at a = b = h), then B0.
+ *   b = column offset, the kernel centre at a = b = h), then B0.  With a
+ *   polynomial background of degree d >= 1 (dia_objective.bg_degree) it is
+ *   m*m + (d+1)(d+2)/2 values: K, then the background coefficients, b_00
+ *   where B0 was; "n" below is that length and gradients, Hessians and fits
+ *   follow the same layout.
  * - m is odd, 1 <= m <= DIA_MAX_M.
  * - Array arguments are DEVICE pointers owned by the caller, except where a
  *   comment says "host".  Option and result structs are host memory.
@@ -45,6 +49,7 @@ extern "C" {
 #endif
 
 #define DIA_MAX_M 49
+#define DIA_MAX_BG_DEGREE 4     /* highest degree of the polynomial background (Section 2.6)         */
 
 /* status codes */
 #define DIA_OK 0
@@ -101,6 +106,17 @@ typedef struct {
      * (dia_loss_grad, dia_hessian, dia_fit) include it in the loss, gradient and
      * Hessian; the batched ones require lambda = 0 (DIA_E_ARG otherwise). */
     double lambda;
+    /* Differential background of Section 2.6 (eq. polybackground): 0 = the
+     * scalar B0; d = 1 .. DIA_MAX_BG_DEGREE = the polynomial
+     *     B(x, y) = sum over a + b <= d of b_ab eta^a xi^b,
+     * eta = (x - x_c) / N_x, xi = (y - y_c) / N_y (eq. normcoords), x the
+     * target column, y the target row, (x_c, y_c) = ((cols - 1)/2, (rows - 1)/2)
+     * and N_x = cols, N_y = rows.  theta then holds the m*m kernel taps and the
+     * (d+1)(d+2)/2 coefficients in the equation's summation order (a = 0..d
+     * outer, b = 0..d-a inner), b_00 in B0's place; the smoothness penalty
+     * leaves every coefficient free.  Single-pair entry points only (the
+     * batched ones require 0); dia_fit requires max_outer = 1 with d >= 1. */
+    int32_t bg_degree;
 } dia_objective;
 
 /* Operations for dia_workspace_size. */
@@ -119,6 +135,13 @@ int dia_workspace_size(int32_t op, int32_t rows, int32_t cols, int64_t ld, int32
  * Asynchronous on stream; needs no workspace. */
 int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM, void* stream);
 
+/* dia_model with the polynomial background of Section 2.6 (eq. model_image
+ * with eq. polybackground): theta holds m*m + (d+1)(d+2)/2 values for
+ * bg_degree = d (see dia_objective.bg_degree; the coordinates are those of
+ * R's grid, rows x cols).  bg_degree = 0 is dia_model. */
+int dia_model_bg(dia_image R, const float* theta, int32_t m, int32_t bg_degree, float* M, int64_t ldM,
+                 void* stream);
+
 /* One fused forward + objective + backward pass (the residual is never
  * written to memory).  The tile shape is the one the fits use for this kernel
  * size and image-size class: the first call for a new (m, size class) in a
@@ -128,7 +151,10 @@ int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM,
  * thread where the LDS budget allows, compiled for m = 9, 17, 19, 25):
  *   *loss   = L(theta)  summed over valid, unmasked pixels, FP64      (device double[1])
  *   grad[k] = dL/dK_k = sum_p g_p R_(p + k),  grad[m*m] = dL/dB0 = sum_p g_p,
- *             g_p = d l_p / d M_p                                      (device float[m*m+1])
+ *             g_p = d l_p / d M_p                                      (device float[n])
+ *   with a polynomial background grad[m*m + j] = sum_p g_p eta_p^a xi_p^b for
+ *   the j-th coefficient b_ab.  A polynomial background always uses the
+ *   default tile shape.
  * Asynchronous on stream. */
 int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m,
                   double* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
@@ -165,10 +191,13 @@ int dia_loss_grad_noalloc(dia_image R, dia_image I, const dia_objective* obj, co
                           double* loss, float* grad, void* stream);
 
 /* Observed Fisher information (Section 2.5): the Hessian of L at theta,
- *   H[i * n + j] = d2L / dtheta_i dtheta_j,   n = m*m + 1,
+ *   H[i * n + j] = d2L / dtheta_i dtheta_j,   n = m*m + 1 (m*m + (d+1)(d+2)/2
+ * with a polynomial background of degree d),
  * FP64, row-major, parameters in theta's order (kernel taps row by row, then
- * B0); device double[n * n].  Since M is affine in theta,
- *   H = sum_p (d2 l_p / dM_p^2) x_p x_p^T,  x_p = (R_(p + k) for every tap k, 1),
+ * B0 or the background coefficients); device double[n * n].  Since M is
+ * affine in theta,
+ *   H = sum_p (d2 l_p / dM_p^2) x_p x_p^T,  x_p = (R_(p + k) for every tap k, 1)
+ *   (with a polynomial background the 1 becomes eta_p^a xi_p^b for each term),
  * computed exactly (including the derivative of the variance when it
  * depends on the model).  When L is a negative log-likelihood, H^-1 is the
  * asymptotic covariance of the fitted parameters and sqrt(H^-1[m*m][m*m])
@@ -193,7 +222,9 @@ typedef struct {
     int32_t history;       /* L-BFGS memory, 1..32                                         */
     int32_t max_adam;      /* Adam steps before the switch is forced                       */
     int32_t max_lbfgs;     /* accepted L-BFGS steps (then DIA_W_NOT_CONVERGED unless the
-                              Newton polish below converges)                                */
+                              Newton polish below converges); 0 = no L-BFGS phase: the
+                              first-order part ends at the Adam switch and the Newton
+                              polish (max_newton > 0) takes the fit from there              */
     int32_t max_eval;      /* total objective evaluations before DIA_W_NOT_CONVERGED       */
     int32_t max_outer;     /* fits in the reweight/clip loop (1 = a single fit)            */
     double clip_kappa;     /* clip |z| > clip_kappa between fits; 0 = no clipping          */
@@ -203,7 +234,8 @@ typedef struct {
 
 /* Covariance of the fitted parameters from the observed Fisher information
  * (Section 2.5, eq. covmatrix): for F = dia_hessian's H at the fit (device
- * double[n*n], n = m*m + 1, symmetric; not modified),
+ * double[n*n], n = m*m + 1, symmetric; not modified; see dia_covariance_bg
+ * for a polynomial background),
  *   cov     = F^-1                           (device double[n*n], row-major)
  *   sigma   = sqrt(diag cov), the Cramer-Rao error of each parameter (eq. deltatheta)
  *                                            (device double[n])
@@ -218,6 +250,13 @@ typedef struct {
  * FP64 matrices).  Asynchronous on stream. */
 int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, double* sigma_P, double* info, void* ws,
                    size_t ws_bytes, void* stream);
+
+/* dia_covariance for a fit with the polynomial background of Section 2.6:
+ * F is n x n with n = m*m + (d+1)(d+2)/2 for bg_degree = d (dia_hessian's H
+ * with dia_objective.bg_degree = d); sigma_P still sums over the m*m kernel
+ * taps.  Same workspace (DIA_OP_COVARIANCE covers every degree). */
+int dia_covariance_bg(const double* F, int32_t m, int32_t bg_degree, double* cov, double* sigma, double* sigma_P,
+                      double* info, void* ws, size_t ws_bytes, void* stream);
 
 /* Fill opts with the paper's settings (Section 2.9): flat init, lr_K 1e-3,
  * lr_B0 10, tol_switch 1e-6, L-BFGS lr 1 with history 10, tol_change 1e-8,

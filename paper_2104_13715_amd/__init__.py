@@ -33,6 +33,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ----------------------------------------------------------------------------- constants (dia.h)
 MAX_M = 49
+MAX_BG_DEGREE = 4
 OK, W_NOT_CONVERGED = 0, 1
 E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_NONFINITE, E_SCRATCH = -1, -2, -3, -4, -5, -6
 NOALLOC_SCRATCH_BYTES = 16 << 20
@@ -52,7 +53,7 @@ class _Objective(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_int32), ("var", ctypes.c_int32), ("sigma0", ctypes.c_double),
                 ("gain", ctypes.c_double), ("excess", ctypes.c_double), ("var_floor", ctypes.c_double),
                 ("c", ctypes.c_double), ("weights", ctypes.c_void_p), ("flat", ctypes.c_void_p),
-                ("mask", ctypes.c_void_p), ("lam", ctypes.c_double)]
+                ("mask", ctypes.c_void_p), ("lam", ctypes.c_double), ("bg_degree", ctypes.c_int32)]
 
 
 class _Epoch(ctypes.Structure):
@@ -84,11 +85,13 @@ _lib.dia_status_string.argtypes = [ctypes.c_int]
 _lib.dia_status_string.restype = ctypes.c_char_p
 _lib.dia_workspace_size.argtypes = [_i32, _i32, _i32, _i64, _i32, ctypes.POINTER(_sz)]
 _lib.dia_model.argtypes = [_Image, _vp, _i32, _vp, _i64, _vp]
+_lib.dia_model_bg.argtypes = [_Image, _vp, _i32, _i32, _vp, _i64, _vp]
 _lib.dia_loss_grad.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_loss_grad64.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_loss_grad_noalloc.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp]
 _lib.dia_hessian.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.dia_covariance.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+_lib.dia_covariance_bg.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_opts_default.argtypes = [ctypes.POINTER(_FitOpts)]
 _lib.dia_fit_opts_default.restype = None
 _lib.dia_fit.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _i32, ctypes.POINTER(_FitOpts), _vp,
@@ -99,16 +102,16 @@ _lib.dia_loss_grad_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i3
                                        _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_fit_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, ctypes.POINTER(_Objective),
                                  ctypes.POINTER(_FitOpts), _i32, _vp, ctypes.POINTER(_FitResult), _vp, _sz, _vp]
-for _f in ("dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64", "dia_loss_grad_noalloc",
-           "dia_hessian", "dia_covariance", "dia_fit",
+for _f in ("dia_workspace_size", "dia_model", "dia_model_bg", "dia_loss_grad", "dia_loss_grad64",
+           "dia_loss_grad_noalloc", "dia_hessian", "dia_covariance_bg", "dia_covariance", "dia_fit",
            "dia_batched_workspace_size", "dia_loss_grad_batched", "dia_fit_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 # "fp32" (the C enum's name) and "plain" name the same form: FP32 data, FP64 arithmetic on the vector ALUs
 PREC = {"fp32": 0, "plain": 0, "bf16x3": 1}
 
-EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_loss_grad", "dia_loss_grad64",
-           "dia_loss_grad_noalloc", "dia_hessian",
+EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_model_bg", "dia_loss_grad",
+           "dia_loss_grad64", "dia_loss_grad_noalloc", "dia_hessian", "dia_covariance_bg",
            "dia_covariance", "dia_fit_opts_default", "dia_fit", "dia_batched_workspace_size",
            "dia_loss_grad_batched", "dia_fit_batched")
 
@@ -158,7 +161,9 @@ def _stream(device) -> int:
 class Objective:
     """rho in {'gauss', 'huber', 'cauchy'}; var in {'weights', 'ccd_data', 'ccd_model', 'emccd_data',
     'emccd_model'} (see include/dia.h).  weights / flat / mask are tensors laid out like the target.
-    lam: lambda of the kernel-smoothness penalty (single-pair calls only; 0 = none)."""
+    lam: lambda of the kernel-smoothness penalty (single-pair calls only; 0 = none).
+    bg_degree: degree d of the polynomial background of Section 2.6 (0 = the scalar B0); theta then has
+    m*m + (d+1)(d+2)/2 entries (single-pair calls only)."""
     rho: str = "gauss"
     var: str = "ccd_data"
     sigma0: float = 0.0
@@ -170,13 +175,18 @@ class Objective:
     flat: Optional[torch.Tensor] = None
     mask: Optional[torch.Tensor] = None
     lam: float = 0.0
+    bg_degree: int = 0
+
+    def n_params(self, m: int) -> int:
+        d = int(self.bg_degree)
+        return m * m + (d + 1) * (d + 2) // 2
 
     def _c(self, I: torch.Tensor) -> _Objective:
         return _Objective(RHO[self.rho], VAR[self.var], float(self.sigma0), float(self.gain), float(self.excess),
                           float(self.var_floor), float(self.c),
                           _like_target(self.weights, I, torch.float32, "weights"),
                           _like_target(self.flat, I, torch.float32, "flat"),
-                          _like_target(self.mask, I, torch.uint8, "mask"), float(self.lam))
+                          _like_target(self.mask, I, torch.uint8, "mask"), float(self.lam), int(self.bg_degree))
 
 
 def workspace_size(op: int, rows: int, cols: int, ld: int, m: int) -> int:
@@ -203,32 +213,37 @@ class Workspace:
         return p + (-p) % 256, nbytes
 
 
-def _theta(theta: torch.Tensor, m: int, device) -> torch.Tensor:
-    if theta.dtype != torch.float32 or theta.numel() != m * m + 1 or not theta.is_contiguous():
-        raise ValueError("theta must be a contiguous float32 tensor of m*m + 1 values")
+def _theta(theta: torch.Tensor, m: int, device, n: Optional[int] = None) -> torch.Tensor:
+    n = m * m + 1 if n is None else n
+    if theta.dtype != torch.float32 or theta.numel() != n or not theta.is_contiguous():
+        raise ValueError(f"theta must be a contiguous float32 tensor of {n} values (the kernel, then the background)")
     if theta.device != device:
         raise ValueError("theta must live on the images' device")
     return theta
 
 
 # ----------------------------------------------------------------------------- entry points
-def model(R: torch.Tensor, theta: torch.Tensor, m: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Valid model image (rows-m+1, cols-m+1), eq. model_image_delta_basis."""
+def model(R: torch.Tensor, theta: torch.Tensor, m: int, out: Optional[torch.Tensor] = None,
+          bg_degree: int = 0) -> torch.Tensor:
+    """Valid model image (rows-m+1, cols-m+1), eq. model_image_delta_basis (with the polynomial background
+    of eq. polybackground when bg_degree > 0)."""
     Ri = _image(R, "R")
-    theta = _theta(theta, m, R.device)
+    theta = _theta(theta, m, R.device, Objective(bg_degree=bg_degree).n_params(m))
     if out is None:
         out = torch.empty((max(R.shape[0] - m + 1, 1), max(R.shape[1] - m + 1, 1)), dtype=torch.float32,
                           device=R.device)
-    _check(_lib.dia_model(Ri, theta.data_ptr(), m, out.data_ptr(), out.stride(0), _stream(R.device)), "dia_model")
+    _check(_lib.dia_model_bg(Ri, theta.data_ptr(), m, int(bg_degree), out.data_ptr(), out.stride(0),
+                             _stream(R.device)), "dia_model_bg")
     return out
 
 
 def loss_grad(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
               workspace: Optional[Workspace] = None, loss: Optional[torch.Tensor] = None,
               grad: Optional[torch.Tensor] = None):
-    """(loss float64[1], grad float32[m*m+1]) of the objective at theta, one fused pass."""
+    """(loss float64[1], grad float32[n]) of the objective at theta, one fused pass (n = objective.n_params(m))."""
     Ri, Ii = _image(R, "R"), _image(I, "I")
-    theta = _theta(theta, m, R.device)
+    n = objective.n_params(m)
+    theta = _theta(theta, m, R.device, n)
     obj = objective._c(I)
     ws = workspace or Workspace(R.device)
     nbytes = workspace_size(OP_LOSS_GRAD, I.shape[0], I.shape[1], I.stride(0), m)
@@ -236,7 +251,7 @@ def loss_grad(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, obj
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device=R.device)
     if grad is None:
-        grad = torch.empty(m * m + 1, dtype=torch.float32, device=R.device)
+        grad = torch.empty(n, dtype=torch.float32, device=R.device)
     _check(_lib.dia_loss_grad(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(), grad.data_ptr(),
                               p, nb, _stream(R.device)), "dia_loss_grad")
     return loss, grad
@@ -245,10 +260,11 @@ def loss_grad(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, obj
 def loss_grad64(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
                 workspace: Optional[Workspace] = None, loss: Optional[torch.Tensor] = None,
                 grad: Optional[torch.Tensor] = None):
-    """(loss float64[1], grad float64[m*m+1]) at FP64 parameters theta, one fused pass (dia_loss_grad64)."""
+    """(loss float64[1], grad float64[n]) at FP64 parameters theta, one fused pass (dia_loss_grad64)."""
     Ri, Ii = _image(R, "R"), _image(I, "I")
-    if theta.dtype != torch.float64 or theta.numel() != m * m + 1 or not theta.is_contiguous():
-        raise ValueError("theta must be a contiguous float64 tensor of m*m + 1 values")
+    n = objective.n_params(m)
+    if theta.dtype != torch.float64 or theta.numel() != n or not theta.is_contiguous():
+        raise ValueError(f"theta must be a contiguous float64 tensor of {n} values")
     if theta.device != R.device:
         raise ValueError("theta must live on the images' device")
     obj = objective._c(I)
@@ -257,7 +273,7 @@ def loss_grad64(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, o
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device=R.device)
     if grad is None:
-        grad = torch.empty(m * m + 1, dtype=torch.float64, device=R.device)
+        grad = torch.empty(n, dtype=torch.float64, device=R.device)
     _check(_lib.dia_loss_grad64(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(), grad.data_ptr(),
                                 p, nb, _stream(R.device)), "dia_loss_grad64")
     return loss, grad
@@ -269,12 +285,13 @@ def loss_grad_noalloc(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: 
     the partial sums.  Pass preallocated loss (float64[1]) and grad (float32[m*m+1]) to allocate
     nothing at all."""
     Ri, Ii = _image(R, "R"), _image(I, "I")
-    theta = _theta(theta, m, R.device)
+    n = objective.n_params(m)
+    theta = _theta(theta, m, R.device, n)
     obj = objective._c(I)
     if loss is None:
         loss = torch.empty(1, dtype=torch.float64, device=R.device)
     if grad is None:
-        grad = torch.empty(m * m + 1, dtype=torch.float32, device=R.device)
+        grad = torch.empty(n, dtype=torch.float32, device=R.device)
     _check(_lib.dia_loss_grad_noalloc(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(),
                                       grad.data_ptr(), _stream(R.device)), "dia_loss_grad_noalloc")
     return loss, grad
@@ -282,15 +299,15 @@ def loss_grad_noalloc(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: 
 
 def hessian(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
             workspace: Optional[Workspace] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Observed Fisher information: the exact FP64 Hessian d2L/dtheta2, (m*m+1) x (m*m+1)."""
+    """Observed Fisher information: the exact FP64 Hessian d2L/dtheta2, n x n (n = objective.n_params(m))."""
     Ri, Ii = _image(R, "R"), _image(I, "I")
-    theta = _theta(theta, m, R.device)
+    n = objective.n_params(m)
+    theta = _theta(theta, m, R.device, n)
     obj = objective._c(I)
-    n = m * m + 1
     if out is None:
         out = torch.empty((n, n), dtype=torch.float64, device=R.device)
     if out.dtype != torch.float64 or tuple(out.shape) != (n, n) or not out.is_contiguous():
-        raise ValueError("out must be a contiguous float64 tensor of shape (m*m+1, m*m+1)")
+        raise ValueError("out must be a contiguous float64 tensor of shape (n, n)")
     ws = workspace or Workspace(R.device)
     p, nb = ws.get(workspace_size(OP_HESSIAN, I.shape[0], I.shape[1], I.stride(0), m))
     _check(_lib.dia_hessian(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, out.data_ptr(), p, nb,
@@ -311,19 +328,20 @@ class Covariance:
     min_pivot: float
 
 
-def covariance(F: torch.Tensor, m: int, workspace: Optional[Workspace] = None) -> Covariance:
-    """Covariance estimate and validity test from an observed Fisher information F (float64, n x n)."""
-    n = m * m + 1
+def covariance(F: torch.Tensor, m: int, workspace: Optional[Workspace] = None, bg_degree: int = 0) -> Covariance:
+    """Covariance estimate and validity test from an observed Fisher information F (float64, n x n,
+    n = m*m + (d+1)(d+2)/2 for a background of degree d)."""
+    n = Objective(bg_degree=bg_degree).n_params(m)
     if F.dtype != torch.float64 or tuple(F.shape) != (n, n) or not F.is_contiguous() or F.device.type != "cuda":
-        raise ValueError("F must be a contiguous float64 device tensor of shape (m*m+1, m*m+1)")
+        raise ValueError(f"F must be a contiguous float64 device tensor of shape ({n}, {n})")
     cov = torch.empty((n, n), dtype=torch.float64, device=F.device)
     sigma = torch.empty(n, dtype=torch.float64, device=F.device)
     sP = torch.empty(1, dtype=torch.float64, device=F.device)
     info = torch.empty(3, dtype=torch.float64, device=F.device)
     ws = workspace or Workspace(F.device)
     p, nb = ws.get(workspace_size(OP_COVARIANCE, 1, 1, 1, m))
-    _check(_lib.dia_covariance(F.data_ptr(), m, cov.data_ptr(), sigma.data_ptr(), sP.data_ptr(), info.data_ptr(),
-                               p, nb, _stream(F.device)), "dia_covariance")
+    _check(_lib.dia_covariance_bg(F.data_ptr(), m, int(bg_degree), cov.data_ptr(), sigma.data_ptr(), sP.data_ptr(),
+                                  info.data_ptr(), p, nb, _stream(F.device)), "dia_covariance_bg")
     h = info.cpu().tolist()
     return Covariance(cov=cov, sigma=sigma, sigma_P=float(sP.item()), valid=h[0] == 1.0, logdet=h[1],
                       min_pivot=h[2])
@@ -332,7 +350,7 @@ def covariance(F: torch.Tensor, m: int, workspace: Optional[Workspace] = None) -
 def uncertainty(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,
                 workspace: Optional[Workspace] = None) -> Covariance:
     """Section 2.5 at theta: the covariance of the observed Fisher information (the exact Hessian)."""
-    return covariance(hessian(R, I, theta, m, objective, workspace), m, workspace)
+    return covariance(hessian(R, I, theta, m, objective, workspace), m, workspace, objective.bg_degree)
 
 
 @dataclass
@@ -353,10 +371,11 @@ class FitResult:
     first_order_stop: str = "none"
     extra: dict = field(default_factory=dict)
 
+    m: int = 0
+
     @property
     def K(self) -> torch.Tensor:
-        m = int(round((self.theta.numel() - 1) ** 0.5))
-        return self.theta[:m * m].view(m, m)
+        return self.theta[:self.m * self.m].view(self.m, self.m)
 
 
 def fit_options(**kw) -> _FitOpts:
@@ -373,13 +392,15 @@ def fit_options(**kw) -> _FitOpts:
 
 def fit(R: torch.Tensor, I: torch.Tensor, m: int, objective: Objective, theta: Optional[torch.Tensor] = None,
         workspace: Optional[Workspace] = None, **opts) -> FitResult:
-    """Fit K and B0 (Adam then L-BFGS on the device); returns after the fit has finished."""
+    """Fit K and the background (Adam then L-BFGS on the device, then the Newton polish); returns after the
+    fit has finished."""
     Ri, Ii = _image(R, "R"), _image(I, "I")
+    n = objective.n_params(m)
     if theta is not None:
         opts.setdefault("init", "user")
-        theta = _theta(theta, m, R.device)
+        theta = _theta(theta, m, R.device, n)
     else:
-        theta = torch.empty(m * m + 1, dtype=torch.float32, device=R.device)
+        theta = torch.empty(n, dtype=torch.float32, device=R.device)
     o = fit_options(**opts)
     obj = objective._c(I)
     ws = workspace or Workspace(R.device)
@@ -392,7 +413,8 @@ def fit(R: torch.Tensor, I: torch.Tensor, m: int, objective: Objective, theta: O
     return FitResult(theta=theta, loss=res.loss, P=res.P, B0=res.B0, n_eval=res.n_eval, n_adam=res.n_adam,
                      n_lbfgs=res.n_lbfgs, n_outer=res.n_outer, n_masked=int(res.n_masked),
                      stop=STOP.get(res.stop, str(res.stop)), status=st, n_newton=res.n_newton,
-                     n_hessian=res.n_hessian, first_order_stop=STOP.get(res.first_order_stop, str(res.first_order_stop)))
+                     n_hessian=res.n_hessian, first_order_stop=STOP.get(res.first_order_stop, str(res.first_order_stop)),
+                     m=m)
 
 
 class DIALoss(torch.autograd.Function):
@@ -495,6 +517,7 @@ def fit_batched(R: torch.Tensor, epochs, m: int, objective: Objective, theta: Op
     out = [FitResult(theta=theta[k], loss=r.loss, P=r.P, B0=r.B0, n_eval=r.n_eval, n_adam=r.n_adam,
                      n_lbfgs=r.n_lbfgs, n_outer=r.n_outer, n_masked=int(r.n_masked),
                      stop=STOP.get(r.stop, str(r.stop)), status=r.status, n_newton=r.n_newton,
-                     n_hessian=r.n_hessian, first_order_stop=STOP.get(r.first_order_stop, str(r.first_order_stop)))
+                     n_hessian=r.n_hessian, first_order_stop=STOP.get(r.first_order_stop, str(r.first_order_stop)),
+                     m=m)
            for k, r in enumerate(res)]
     return theta, out, st

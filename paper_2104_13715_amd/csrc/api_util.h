@@ -44,6 +44,7 @@ inline int check_obj(const dia_objective* o, bool need_weights_ptr = true) {
     if (o->var < DIA_VAR_WEIGHTS || o->var > DIA_VAR_EMCCD_MODEL) return DIA_E_ARG;
     if (o->rho != DIA_RHO_GAUSS && !(o->c > 0.0 && is_fin(o->c))) return DIA_E_ARG;
     if (!(o->lambda >= 0.0) || !is_fin(o->lambda)) return DIA_E_ARG;
+    if (o->bg_degree < 0 || o->bg_degree > DIA_MAX_BG_DEGREE) return DIA_E_ARG;
     if (o->var == DIA_VAR_WEIGHTS) {
         if (need_weights_ptr && o->weights == nullptr) return DIA_E_ARG;
     } else {
@@ -79,7 +80,7 @@ inline int check_opts(const dia_fit_opts* opts) {
     if (!(o.beta1 >= 0.0 && o.beta1 < 1.0) || !(o.beta2 >= 0.0 && o.beta2 < 1.0) || !(o.eps >= 0.0)) return DIA_E_ARG;
     if (!(o.tol_switch >= 0.0) || !(o.tol_change >= 0.0) || !(o.tol_grad >= 0.0)) return DIA_E_ARG;
     if (o.history < 1 || o.history > kMaxHistory) return DIA_E_ARG;
-    if (o.max_adam < 1 || o.max_lbfgs < 1 || o.max_eval < 1 || o.max_outer < 1 || o.poll_every < 1) return DIA_E_ARG;
+    if (o.max_adam < 1 || o.max_lbfgs < 0 || o.max_eval < 1 || o.max_outer < 1 || o.poll_every < 1) return DIA_E_ARG;
     if (o.poll_every > 1024) return DIA_E_ARG;
     if (o.max_newton < 0 || o.max_newton > 1000) return DIA_E_ARG;
     if (!(o.clip_kappa >= 0.0) || !is_fin(o.clip_kappa)) return DIA_E_ARG;
@@ -131,8 +132,25 @@ inline TileArgs base_args(const dia_image& R, const dia_image& I, const float* t
     a.rows = R.rows;
     a.cols = R.cols;
     a.theta = theta;
+    a.nb = 1;
     return a;
 }
+
+// The background of a call: degree d (0 = the scalar B0) and, for d >= 1, the normalised coordinates
+// of eq. normcoords at the valid pixels: eta = (x - x_c) / N_x with x = ox + h the target column,
+// x_c = (N_x - 1) / 2 the centre and N_x = cols the target's width; xi the same along the rows.
+inline void set_background(TileArgs& a, int d, int m) {
+    const int h = (m - 1) / 2;
+    a.bg_deg = d;
+    a.nb = bg_terms(d);
+    a.deta = 1.0 / (double)a.cols;
+    a.eta0 = ((double)h - 0.5 * (double)(a.cols - 1)) / (double)a.cols;
+    a.dxi = 1.0 / (double)a.rows;
+    a.xi0 = ((double)h - 0.5 * (double)(a.rows - 1)) / (double)a.rows;
+}
+
+// Parameters of a single-pair call: m*m kernel taps and the background coefficients.
+inline int n_params(int m, const dia_objective& o) { return m * m + bg_terms(o.bg_degree); }
 
 // Optimiser vectors of one fit: 8 vectors, the L-BFGS history (S, Y, rho, alpha) and theta_eval.
 inline size_t vec_bytes(int nld) {

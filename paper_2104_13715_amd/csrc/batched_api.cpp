@@ -234,7 +234,7 @@ int dia_loss_grad_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32
     int c = check_image(R);
     if (c != DIA_OK) return c;
     if ((c = check_obj(obj, false)) != DIA_OK) return c;
-    if (obj->lambda != 0.0) return DIA_E_ARG;  // the smoothness penalty is a single-pair option
+    if (obj->lambda != 0.0 || obj->bg_degree != 0) return DIA_E_ARG;  // penalty and polynomial background: single pair
     if ((c = check_epochs(R, epochs, n, m, obj, precision)) != DIA_OK) return c;
     if (theta == nullptr || loss == nullptr || grad == nullptr) return DIA_E_ARG;
     const BLayout L = make_blayout(epochs, n, m, precision, false);
@@ -294,7 +294,7 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
     int c = check_image(R);
     if (c != DIA_OK) return c;
     if ((c = check_obj(obj, false)) != DIA_OK) return c;
-    if (obj->lambda != 0.0) return DIA_E_ARG;  // the smoothness penalty is a single-pair option
+    if (obj->lambda != 0.0 || obj->bg_degree != 0) return DIA_E_ARG;  // penalty and polynomial background: single pair
     if ((c = check_epochs(R, epochs, n, m, obj, precision)) != DIA_OK) return c;
     if ((c = check_opts(opts)) != DIA_OK) return c;
     if (opts->max_outer != 1 || theta == nullptr) return DIA_E_ARG;
@@ -330,7 +330,8 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
                 TRY(launch_ref_stats(Re, epochs[e].rows, epochs[e].cols, R.ld, sel, cs) == hipSuccess);
             }
             if (rc != DIA_OK) break;
-            TRY(launch_init_fit(st0, v0, m, o.init, o.init_phi, theta, sel0, cs, n, (long long)L.stride) == hipSuccess);
+            TRY(launch_init_fit(st0, v0, m, 1, o.init, o.init_phi, theta, sel0, cs, n, (long long)L.stride) ==
+                hipSuccess);
             TRY(launch_zero_ints(ints, 16, cs) == hipSuccess);
 
             const int* done0 = &st0->done;
@@ -457,7 +458,7 @@ int dia_fit_batched(dia_image R, const dia_epoch* epochs, int32_t n, int32_t m, 
                         oe.mask = epochs[e].mask;
                         const NewtonLayout NL = newton_layout(m, Ie.rows, Ie.cols, true, true);
                         const int ge = eval_grid(m, tile_grid_tiles(m, Ie.rows, Ie.cols, 0), 0);
-                        const int pr = newton_polish(Re, Ie, to_params(oe), 0.0, m, ge, 0, st,
+                        const int pr = newton_polish(Re, Ie, to_params(oe), 0.0, m, 0, ge, 0, st,
                                                      offset_vecs(v0, (long long)e * L.stride),
                                                      reinterpret_cast<double*>(nb + NL.part), nb, NL, o.max_newton,
                                                      quad, ls, &nw[e]);

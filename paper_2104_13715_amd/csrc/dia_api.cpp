@@ -17,7 +17,7 @@ struct Layout {
 
 Layout make_layout(int op, int rows, int cols, long long ld, int m) {
     Layout L;
-    L.n = m * m + 1;
+    L.n = m * m + kMaxBgTerms;  // room for the largest background; a call uses m*m + bg_terms(bg_degree)
     L.npp = L.n + 1;
     L.nld = (L.n + 63) / 64 * 64;
     const int nt = max_tiles(m, rows, cols);
@@ -150,7 +150,7 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
         TRY(hipStreamWaitEvent(cs, ev, 0));
         if (o.init != DIA_INIT_USER) TRY(launch_median(I.data, I.rows, I.cols, I.ld, sel, cs));
         TRY(launch_ref_stats(R.data, R.rows, R.cols, R.ld, sel, cs));
-        TRY(launch_init_fit(st, v, m, o.init, o.init_phi, theta, sel, cs));
+        TRY(launch_init_fit(st, v, m, bg_terms(obj.bg_degree), o.init, o.init_phi, theta, sel, cs));
         TRY(launch_zero_ints(ints, 16, cs));
 
         FitOptsDev od = opts_dev(o);
@@ -164,12 +164,13 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
             cur.mask = wmask;
         }
 
-        // tile shape: timed on this pair at the start point
+        // tile shape: timed on this pair at the start point (the default shape with a polynomial background)
         TileArgs tune = base_args(R, I, v.theta_eval);
         tune.theta64 = v.theta_eval64;
         tune.obj = to_params(cur);
         tune.partial = reinterpret_cast<double*>(base + L.partial);
-        const int variant = choose_variant(tune, m, cs);
+        const int variant = obj.bg_degree > 0 ? 0 : choose_variant(tune, m, cs);
+        const int n = n_params(m, obj);
         const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, variant), variant);
 
         int n_eval = 0, n_adam = 0, n_lbfgs = 0, n_outer = 0, n_newton = 0, n_hess = 0, first_stop = 0;
@@ -192,24 +193,25 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
                 cur.weights = wts;
                 cur.flat = nullptr;
                 cur.mask = wmask;
-                TRY(launch_restart_fit(st, v, L.n, cs));
+                TRY(launch_restart_fit(st, v, n, cs));
             }
             TileArgs ta = base_args(R, I, v.theta_eval);
             ta.theta64 = v.theta_eval64;
             ta.obj = to_params(cur);
             ta.partial = reinterpret_cast<double*>(base + L.partial);
             ta.done = &st->done;
+            set_background(ta, obj.bg_degree, m);
             ReduceArgs ra;
             std::memset(&ra, 0, sizeof(ra));
             ra.partial = ta.partial;
             ra.nblk = grid;
-            ra.npp = L.npp;
+            ra.npp = n + 1;
             ra.gt = reinterpret_cast<double*>(base + L.gt);
             ra.st = st;
             ra.v = v;
             ra.o = od;
             ra.o.skip_adam = outer > 0 ? 1 : 0;
-            ra.n = L.n;
+            ra.n = n;
             ra.m = m;
             ra.done = &st->done;
             ra.reg = penalty_weight(obj, I, m);
@@ -229,7 +231,8 @@ int fit_impl(const dia_image& R, const dia_image& I, const dia_objective& obj, i
                 const bool quad = cur.rho == DIA_RHO_GAUSS && cur.var != DIA_VAR_CCD_MODEL &&
                                   cur.var != DIA_VAR_EMCCD_MODEL;
                 NewtonOutcome no;
-                const int pr = newton_polish(R, I, to_params(cur), penalty_weight(obj, I, m), m, grid, variant, st, v,
+                const int pr = newton_polish(R, I, to_params(cur), penalty_weight(obj, I, m), m, obj.bg_degree, grid,
+                                             variant, st, v,
                                              ta.partial, base + L.newton, L.NL, o.max_newton, quad, cs, &no);
                 if (pr != DIA_OK) {
                     rc = pr;
@@ -306,31 +309,33 @@ int loss_grad_impl(const dia_image& R, const dia_image& I, const dia_objective* 
     if ((c = check_ws(ws, ws_bytes, L.total)) != DIA_OK) return c;
     char* base = static_cast<char*>(ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = n_params(m, *obj);
     TileArgs a = base_args(R, I, theta32);
     const double* th64 = theta64;
     if (th64 == nullptr) {
         double* w = reinterpret_cast<double*>(base + L.th64);
-        if (launch_widen(theta32, w, L.n, s) != hipSuccess) return DIA_E_HIP;
+        if (launch_widen(theta32, w, n, s) != hipSuccess) return DIA_E_HIP;
         th64 = w;
     }
     a.theta64 = th64;
     a.obj = to_params(*obj);
     a.partial = reinterpret_cast<double*>(base + L.partial);
+    set_background(a, obj->bg_degree, m);
     // the tile shape the fits use for this kernel and image size (timed once per process on the first
     // call for a size class, on a private stream; the timing passes write only the workspace's partial rows)
-    const int variant = choose_variant_for_caller(a, m, s, may_time);
+    const int variant = obj->bg_degree > 0 ? 0 : choose_variant_for_caller(a, m, s, may_time);
     const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, variant), variant);
     if (launch_tile(MODE_EVAL, m, grid, a, s, variant) != hipSuccess) return DIA_E_HIP;
     ReduceArgs ra;
     std::memset(&ra, 0, sizeof(ra));
     ra.partial = a.partial;
     ra.nblk = grid;
-    ra.npp = L.npp;
+    ra.npp = n + 1;
     ra.gt = reinterpret_cast<double*>(base + L.gt);
     ra.out_loss = loss;
     ra.out_grad = grad32;
     ra.out_grad64 = grad64;
-    ra.n = L.n;
+    ra.n = n;
     ra.m = m;
     ra.reg = penalty_weight(*obj, I, m);
     ra.th64 = th64;
@@ -362,7 +367,7 @@ const char* dia_status_string(int status) {
 
 // the covariance region: F factored in place, then W = L^-1
 static size_t covariance_bytes(int m) {
-    const size_t n = (size_t)m * m + 1;
+    const size_t n = (size_t)m * m + kMaxBgTerms;
     return 2 * align_up(sizeof(double) * n * n);
 }
 
@@ -385,17 +390,23 @@ int dia_workspace_size(int32_t op, int32_t rows, int32_t cols, int64_t ld, int32
     return DIA_OK;
 }
 
-int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM, void* stream) {
+int dia_model_bg(dia_image R, const float* theta, int32_t m, int32_t bg_degree, float* M, int64_t ldM, void* stream) {
     int c = check_image(R);
     if (c != DIA_OK) return c;
     if ((c = check_m(m, R.rows, R.cols)) != DIA_OK) return c;
     if (theta == nullptr || M == nullptr) return DIA_E_ARG;
+    if (bg_degree < 0 || bg_degree > DIA_MAX_BG_DEGREE) return DIA_E_ARG;
     if (ldM < R.cols - m + 1) return DIA_E_SIZE;
     TileArgs a = base_args(R, R, theta);
     a.out = M;
     a.ld_out = ldM;
+    set_background(a, bg_degree, m);
     const int grid = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols));
     return launch_tile(MODE_MODEL, m, grid, a, static_cast<hipStream_t>(stream)) == hipSuccess ? DIA_OK : DIA_E_HIP;
+}
+
+int dia_model(dia_image R, const float* theta, int32_t m, float* M, int64_t ldM, void* stream) {
+    return dia_model_bg(R, theta, m, 0, M, ldM, stream);
 }
 
 int dia_loss_grad(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m, double* loss,
@@ -422,28 +433,35 @@ int dia_hessian(dia_image R, dia_image I, const dia_objective* obj, const float*
     char* base = static_cast<char*>(ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* th64 = reinterpret_cast<double*>(base + L.th64);
-    if (launch_widen(theta, th64, L.n, s) != hipSuccess) return DIA_E_HIP;
+    if (launch_widen(theta, th64, n_params(m, *obj), s) != hipSuccess) return DIA_E_HIP;
     try {
-        return hessian_into(R, I, to_params(*obj), penalty_weight(*obj, I, m), m, theta, th64, /*exact=*/1,
+        return hessian_into(R, I, to_params(*obj), penalty_weight(*obj, I, m), m, obj->bg_degree, theta, th64,
+                            /*exact=*/1,
                             reinterpret_cast<double*>(base + L.partial), base + L.newton, L.NL, H, s);
     } catch (...) {
         return DIA_E_HIP;
     }
 }
 
-int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, double* sigma_P, double* info, void* ws,
-                   size_t ws_bytes, void* stream) {
+int dia_covariance_bg(const double* F, int32_t m, int32_t bg_degree, double* cov, double* sigma, double* sigma_P,
+                      double* info, void* ws, size_t ws_bytes, void* stream) {
     if (m < 1 || m > DIA_MAX_M || m % 2 == 0) return DIA_E_SIZE;
+    if (bg_degree < 0 || bg_degree > DIA_MAX_BG_DEGREE) return DIA_E_ARG;
     if (F == nullptr || cov == nullptr || sigma == nullptr || sigma_P == nullptr || info == nullptr) return DIA_E_ARG;
     const int c = check_ws(ws, ws_bytes, covariance_bytes(m));
     if (c != DIA_OK) return c;
-    const int n = m * m + 1;
+    const int n = m * m + bg_terms(bg_degree);
     hipStream_t s = static_cast<hipStream_t>(stream);
     double* A = static_cast<double*>(ws);
     double* W = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up(sizeof(double) * (size_t)n * n));
     if (hipMemcpyAsync(A, F, sizeof(double) * (size_t)n * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return DIA_E_HIP;
-    return launch_covariance(A, n, W, cov, sigma, sigma_P, info, s) == hipSuccess ? DIA_OK : DIA_E_HIP;
+    return launch_covariance(A, n, m * m, W, cov, sigma, sigma_P, info, s) == hipSuccess ? DIA_OK : DIA_E_HIP;
+}
+
+int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, double* sigma_P, double* info, void* ws,
+                   size_t ws_bytes, void* stream) {
+    return dia_covariance_bg(F, m, 0, cov, sigma, sigma_P, info, ws, ws_bytes, stream);
 }
 
 void dia_fit_opts_default(dia_fit_opts* o) {
@@ -480,6 +498,7 @@ int dia_fit(dia_image R, dia_image I, const dia_objective* obj, int32_t m, const
     if ((c = check_opts(opts)) != DIA_OK) return c;
     if (theta == nullptr) return DIA_E_ARG;
     if (opts->max_outer > 1 && obj->var == DIA_VAR_WEIGHTS) return DIA_E_ARG;
+    if (opts->max_outer > 1 && obj->bg_degree > 0) return DIA_E_ARG;  // the clip pass has the scalar background
     const int op = opts->max_outer > 1 ? DIA_OP_FIT_CLIPPED : DIA_OP_FIT;
     const Layout L = make_layout(op, R.rows, R.cols, I.ld, m);
     if ((c = check_ws(ws, ws_bytes, L.total)) != DIA_OK) return c;

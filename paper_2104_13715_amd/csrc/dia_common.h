@@ -23,6 +23,16 @@ struct ObjParams {
     const uint8_t* mask;
 };
 
+// Spatially varying background (Section 2.6, eq. polybackground): B(x, y) = sum b_ab eta^a xi^b over
+// a + b <= d, in the normalised coordinates of eq. normcoords.  theta holds the kernel (m*m values),
+// then the coefficients in the equation's summation order (a = 0..d outer, b = 0..d-a inner), so b_00
+// sits where the scalar B0 does and d = 0 is the scalar background.
+constexpr int kMaxBgDegree = DIA_MAX_BG_DEGREE;
+constexpr int kMaxBgTerms = (kMaxBgDegree + 1) * (kMaxBgDegree + 2) / 2;
+__host__ __device__ constexpr int bg_terms(int d) { return (d + 1) * (d + 2) / 2; }
+// position of eta^a xi^b among the coefficients of a degree-d background
+__host__ __device__ constexpr int bg_index(int a, int b, int d) { return a * (d + 1) - a * (a - 1) / 2 + b; }
+
 // What one launch of the tiled kernel does with the forward result.
 enum TileMode { MODE_EVAL = 0, MODE_MODEL = 1, MODE_CLIP = 2, MODE_CURV = 3 };
 
@@ -32,10 +42,10 @@ struct TileArgs {
     const float* I;
     long long ldI;     // also the leading dimension of weights, flat, mask, w_out, mask_out
     int rows, cols;
-    const float* theta;    // K (m*m, row-major) then B0
-    const double* theta64; // MODE_EVAL: the same values widened to FP64 (exactly)
+    const float* theta;    // K (m*m, row-major) then the nb background coefficients
+    const double* theta64; // MODE_EVAL / MODE_CURV: the same values in FP64
     ObjParams obj;
-    double* partial;     // MODE_EVAL: [gridDim.x][m*m + 2]: dL/dK, dL/dB0, loss
+    double* partial;     // MODE_EVAL / MODE_CURV: [gridDim.x][m*m + nb + 1]: dL/dK, dL/db, loss
     float* out;          // MODE_MODEL: valid model
     long long ld_out;
     float* w_out;        // MODE_CLIP: 1/v(M) on the target grid
@@ -45,6 +55,14 @@ struct TileArgs {
     const int* done;     // if non-null and *done != 0 the launch does nothing
     double* h_out;       // MODE_CURV: per-pixel curvature d2l/dM2 on the valid region, row stride Wv
     int curv_exact;      // MODE_CURV: 1 = exact d2l/dM2, 0 = the positive Gauss-Newton / IRLS form
+    // background: nb coefficients after the kernel (1 = the scalar B0); degree bg_deg >= 1 selects the
+    // polynomial form, with eta = eta0 + ox * deta at valid column ox and xi = xi0 + oy * dxi at valid row oy
+    int nb, bg_deg;
+    double eta0, deta, xi0, dxi;
+    // MODE_CURV with a polynomial background: the pass weights each pixel's curvature by the monomial
+    // eta^curv_a xi^curv_b (its partial row is then that background term's row of the Hessian); h_out is
+    // written by the unweighted pass (curv_a = curv_b = 0) only
+    int curv_a, curv_b;
 };
 
 // Geometry of the tiled kernel for an m x m kernel (all compile-time).

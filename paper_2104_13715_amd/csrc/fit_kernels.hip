@@ -168,6 +168,7 @@ __device__ void new_direction(FitState* st, const FitVecs& v, const FitOptsDev& 
 
 __device__ void adam_update(FitState* st, const FitVecs& v, const FitOptsDev& o, int n, double* sh) {
     const int t = st->adam_t + 1;
+    const int nk = st->nk;
     const double bc1 = 1.0 - pow(o.beta1, (double)t);
     const double bc2 = 1.0 - pow(o.beta2, (double)t);
     for (int i = threadIdx.x; i < n; i += kReduceThreads) {
@@ -178,8 +179,8 @@ __device__ void adam_update(FitState* st, const FitVecs& v, const FitOptsDev& o,
         v.v1[i] = v1;
         v.xp[i] = v.x[i];
         v.gp[i] = gi;
-        // kernel steps of lr_K in K are steps of lr_K * c in u
-        const double lr = (i == n - 1) ? o.lr_B0 : o.lr_K * st->ref_scale;
+        // kernel steps of lr_K in K are steps of lr_K * c in u; every background coefficient takes lr_B0
+        const double lr = (i >= nk) ? o.lr_B0 : o.lr_K * st->ref_scale;
         v.x[i] = v.x[i] - lr * (m1 / bc1) / (sqrt(v1 / bc2) + o.eps);
     }
     __syncthreads();
@@ -194,23 +195,31 @@ __device__ void adam_update(FitState* st, const FitVecs& v, const FitOptsDev& o,
 // The optimiser works in coordinates u = (c K, B0 + s sum K), s and c the mean and RMS spread
 // of the reference.  M = sum K R + B0 = sum (u_K / c)(R - s) + u_B: the constant part of R no
 // longer couples every kernel pixel to B0, and kernel pixels and background have comparable
-// curvature.  The optimum is the same point (the reference-offset invariance of the model).
+// curvature.  The optimum is the same point (the reference-offset invariance of the model).  With a
+// polynomial background B0 is its constant term b_00; the other coefficients are not coupled to
+// the reference's offset and are used as they are.
 __device__ void write_theta(const FitState* st, const double* u, float* theta, int n, double* sh,
                             double* theta64 = nullptr) {
     const double c = st->ref_scale, s = st->ref_shift;
+    const int nk = st->nk;
     double ks = 0.0;
-    for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) {
+    for (int i = threadIdx.x; i < nk; i += kReduceThreads) {
         const double k = u[i] / c;
         const float kf = (float)k;
         theta[i] = kf;
         if (theta64) theta64[i] = (double)kf;
         ks += k;
     }
+    for (int i = nk + 1 + threadIdx.x; i < n; i += kReduceThreads) {
+        const float bf = (float)u[i];
+        theta[i] = bf;
+        if (theta64) theta64[i] = (double)bf;
+    }
     ks = block_sum(ks, sh);
     if (threadIdx.x == 0) {
-        const float bf = (float)(u[n - 1] - s * ks);
-        theta[n - 1] = bf;
-        if (theta64) theta64[n - 1] = (double)bf;
+        const float bf = (float)(u[nk] - s * ks);
+        theta[nk] = bf;
+        if (theta64) theta64[nk] = (double)bf;
     }
     __syncthreads();
 }
@@ -233,9 +242,10 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
     }
     // gradient in u: dL/du_K = (dL/dK - s dL/dB0) / c, dL/du_B = dL/dB0 (in place)
     {
-        const double gB = gt[n - 1], sft = st->ref_shift, inv_c = 1.0 / st->ref_scale;
+        const int nk = st->nk;
+        const double gB = gt[nk], sft = st->ref_shift, inv_c = 1.0 / st->ref_scale;
         __syncthreads();
-        for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) gt[i] = (gt[i] - sft * gB) * inv_c;
+        for (int i = threadIdx.x; i < nk; i += kReduceThreads) gt[i] = (gt[i] - sft * gB) * inv_c;
         __syncthreads();
     }
     if (threadIdx.x == 0) st->n_eval += 1;
@@ -272,6 +282,13 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
             const double gm = max_abs(v.g, n, sh);
             if (gm <= o.tol_grad * st->gmax0) {
                 finish(st, ra.n_done, STOP_GRAD, DIA_OK);
+                return;
+            }
+            if (o.max_lbfgs == 0) {
+                // no quasi-Newton phase: the first-order part ends at the switch (the exact-Hessian Newton
+                // polish, when enabled, continues from here)
+                const bool capped = phase == PH_ADAM && !(rel < o.tol_switch);
+                finish(st, ra.n_done, capped ? STOP_CAP : STOP_CHANGE, capped ? DIA_W_NOT_CONVERGED : DIA_OK);
                 return;
             }
             new_direction(st, v, o, n, sh);
@@ -621,11 +638,12 @@ hipError_t launch_ref_stats(const float* R, int rows, int cols, long long ld, Se
 }
 
 // ---------------------------------------------------------------------------- fit init / finalize
-__global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st0, FitVecs v0, int m, int init_kind,
-                                                                  double phi, const float* theta_user0,
+__global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st0, FitVecs v0, int m, int nb,
+                                                                  int init_kind, double phi,
+                                                                  const float* theta_user0,
                                                                   const SelectState* sel0, long long stride) {
     __shared__ double sh[16];
-    const int n = m * m + 1;
+    const int nk = m * m, n = nk + nb;
     const long long off = (long long)blockIdx.x * stride;
     FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + off);
     const FitVecs v = offset_vecs(v0, off);
@@ -666,8 +684,10 @@ __global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st0,
         if (i < n) {
             if (init_kind == DIA_INIT_USER) {
                 x = (double)theta_user[i];
-            } else if (i == n - 1) {
+            } else if (i == nk) {
                 x = B0;
+            } else if (i > nk) {
+                x = 0.0;  // higher background terms start flat
             } else if (init_kind == DIA_INIT_FLAT) {
                 x = 1.0 / (double)(m * m);
             } else {
@@ -676,9 +696,9 @@ __global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st0,
             }
             v.theta_eval[i] = (float)x;
             v.theta_eval64[i] = (double)(float)x;
-            if (i < n - 1) kt += x;
+            if (i < nk) kt += x;
         }
-        const double u = (i < n - 1) ? scl * x : x;
+        const double u = (i < nk) ? scl * x : x;
         v.x[i] = u;
         v.xt[i] = u;
         v.g[i] = 0.0;
@@ -690,21 +710,23 @@ __global__ __launch_bounds__(kReduceThreads) void init_fit_kernel(FitState* st0,
     }
     kt = block_sum(kt, sh);
     if (threadIdx.x == 0) {
-        v.x[n - 1] += sft * kt;
-        v.xt[n - 1] = v.x[n - 1];
-        v.xp[n - 1] = v.x[n - 1];
+        v.x[nk] += sft * kt;
+        v.xt[nk] = v.x[nk];
+        v.xp[nk] = v.x[nk];
         FitState z = {};
         z.phase = PH_INIT;
         z.alpha = 1.0;
         z.ref_shift = sft;
         z.ref_scale = scl;
+        z.nk = nk;
+        z.n = n;
         *st = z;
     }
 }
 
-hipError_t launch_init_fit(FitState* st, FitVecs v, int m, int init_kind, double phi, const float* theta_user,
+hipError_t launch_init_fit(FitState* st, FitVecs v, int m, int nb, int init_kind, double phi, const float* theta_user,
                            const SelectState* sel, hipStream_t s, int n_epochs, long long stride) {
-    hipLaunchKernelGGL(init_fit_kernel, dim3(n_epochs), dim3(kReduceThreads), 0, s, st, v, m, init_kind, phi,
+    hipLaunchKernelGGL(init_fit_kernel, dim3(n_epochs), dim3(kReduceThreads), 0, s, st, v, m, nb, init_kind, phi,
                        theta_user, sel, stride);
     return hipGetLastError();
 }
@@ -717,7 +739,7 @@ __global__ __launch_bounds__(kReduceThreads) void restart_fit_kernel(FitState* s
     const long long off = (long long)blockIdx.x * stride;
     FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + off);
     const FitVecs v = offset_vecs(v0, off);
-    const int hist_n = st->hist_n, hist_head = st->hist_head;
+    const int hist_n = st->hist_n, hist_head = st->hist_head, nk = st->nk, np = st->n;
     const double sft = st->ref_shift, scl = st->ref_scale;
     write_theta(st, v.x, v.theta_eval, n, sh, v.theta_eval64);
     for (int i = threadIdx.x; i < v.ld; i += kReduceThreads) {
@@ -739,6 +761,8 @@ __global__ __launch_bounds__(kReduceThreads) void restart_fit_kernel(FitState* s
         z.hist_head = hist_head;
         z.ref_shift = sft;
         z.ref_scale = scl;
+        z.nk = nk;
+        z.n = np;
         *st = z;
     }
 }
@@ -751,21 +775,21 @@ hipError_t launch_restart_fit(FitState* st, FitVecs v, int n, hipStream_t s, int
 __global__ __launch_bounds__(kReduceThreads) void finalize_kernel(FitState* st0, FitVecs v0, int m, float* theta_out0,
                                                                   long long stride) {
     __shared__ double sh[16];
-    const int n = m * m + 1;
     const long long off = (long long)blockIdx.x * stride;
     FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(st0) + off);
     const FitVecs v = offset_vecs(v0, off);
+    const int n = st->n, nk = st->nk;
     float* theta_out = theta_out0 + (long long)blockIdx.x * n;
     write_theta(st, v.x, theta_out, n, sh, nullptr);
     // P and B0 of the FP64 iterate (the point whose loss is reported), not of its FP32 rounding:
     // when sum |K| is large against P (an unregularised kernel whose poorly constrained modes are
     // big), rounding every pixel to FP32 moves sum K by up to 2^-24 sum |K|
     double s = 0.0;
-    for (int i = threadIdx.x; i < n - 1; i += kReduceThreads) s += v.x[i];
+    for (int i = threadIdx.x; i < nk; i += kReduceThreads) s += v.x[i];
     const double P = block_sum(s, sh) / st->ref_scale;
     if (threadIdx.x == 0) {
         st->out_P = P;
-        st->out_B0 = v.x[n - 1] - st->ref_shift * P;
+        st->out_B0 = v.x[nk] - st->ref_shift * P;
         st->out_loss = st->L;
     }
 }

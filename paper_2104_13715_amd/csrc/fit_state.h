@@ -27,7 +27,7 @@ struct FitState {
     int n_eval, n_adam, n_lbfgs, ls_iter;
     int hist_n, hist_head, counter, adam_t;
     int small_steps;  // consecutive accepted L-BFGS steps with relative change below tol_change
-    int pad_i;
+    int nk, n;        // kernel taps (m*m; the scalar background or b_00 sits at index nk) and parameters
     double L;        // loss at the current point (Adam) or the accepted point (L-BFGS)
     double alpha;    // line-search step
     double gtd;      // g . d at the accepted point
@@ -38,7 +38,7 @@ struct FitState {
     double pad[3];
 };
 
-// Pointers into the workspace for one fit (n = m*m + 1 parameters).
+// Pointers into the workspace for one fit (n = m*m + nb parameters: the kernel, then the background).
 struct FitVecs {
     double *x, *g, *d, *xt, *m1, *v1, *xp, *gp;
     double *S, *Y, *rh, *al;  // L-BFGS history: S[kMaxHistory][ld], Y[kMaxHistory][ld]
@@ -122,7 +122,7 @@ hipError_t launch_median(const float* img, int rows, int cols, long long ld, Sel
 hipError_t launch_ref_stats(const float* R, int rows, int cols, long long ld, SelectState* sel, hipStream_t s);
 // The init / restart / finalize launchers run one workgroup per epoch (n_epochs >= 1, epoch e at
 // byte offset e * stride; theta_user / theta_out hold n_epochs consecutive parameter vectors).
-hipError_t launch_init_fit(FitState* st, FitVecs v, int m, int init_kind, double phi, const float* theta_user,
+hipError_t launch_init_fit(FitState* st, FitVecs v, int m, int nb, int init_kind, double phi, const float* theta_user,
                            const SelectState* sel, hipStream_t s, int n_epochs = 1, long long stride = 0);
 hipError_t launch_restart_fit(FitState* st, FitVecs v, int n, hipStream_t s, int n_epochs = 1, long long stride = 0);
 hipError_t launch_finalize(FitState* st, FitVecs v, int m, float* theta_out, hipStream_t s, int n_epochs = 1,

@@ -6,7 +6,7 @@ namespace dia {
 
 NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own_H) {
     NewtonLayout L;
-    const int n = m * m + 1;
+    const int n = m * m + kMaxBgTerms;
     const long long hv_px = (long long)(rows - m + 1) * (cols - m + 1);
     L.npb = hess_pair_blocks(m);
     L.splits = hess_splits(m, rows, cols);
@@ -22,7 +22,7 @@ NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own
         off = align_up(off + sizeof(double) * (size_t)n * n);
     }
     L.hv = off;
-    off = align_up(off + sizeof(double) * (size_t)(n + 1));
+    off = align_up(off + sizeof(double) * (size_t)kMaxBgTerms * (n + 1));
     L.d = off;
     off = align_up(off + sizeof(double) * (size_t)n);
     L.th = off;
@@ -43,20 +43,22 @@ NewtonLayout newton_layout(int m, int rows, int cols, bool own_partial, bool own
 namespace {
 
 // One fused pass at (theta, theta64) reduced into gt (gradient, then the loss at gt[n]).
-bool eval_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int grid,
+bool eval_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int bg_deg, int grid,
                int variant, const float* theta, const double* theta64, double* partial, double* gt, hipStream_t s) {
     TileArgs a = base_args(R, I, theta);
     a.theta64 = theta64;
     a.obj = obj;
     a.partial = partial;
+    set_background(a, bg_deg, m);
     if (launch_tile(MODE_EVAL, m, grid, a, s, variant) != hipSuccess) return false;
+    const int n = m * m + a.nb;
     ReduceArgs ra;
     std::memset(&ra, 0, sizeof(ra));
     ra.partial = partial;
     ra.nblk = grid;
-    ra.npp = m * m + 2;
+    ra.npp = n + 1;
     ra.gt = gt;
-    ra.n = m * m + 1;
+    ra.n = n;
     ra.m = m;
     ra.reg = reg;
     ra.th64 = theta64;
@@ -70,9 +72,9 @@ bool read_back(void* dst, const void* src, size_t bytes, hipStream_t s) {
 
 }  // namespace
 
-int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, const float* theta,
-                 const double* theta64, int exact, double* partial, char* nbase, const NewtonLayout& NL, double* H,
-                 hipStream_t s, double damp) {
+int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int bg_deg,
+                 const float* theta, const double* theta64, int exact, double* partial, char* nbase,
+                 const NewtonLayout& NL, double* H, hipStream_t s, double damp) {
     const int grid0 = eval_grid(m, tile_grid_tiles(m, R.rows, R.cols, 0), 0);
     TileArgs c = base_args(R, I, theta);
     c.theta64 = theta64;
@@ -80,16 +82,25 @@ int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, d
     c.partial = partial;
     c.h_out = reinterpret_cast<double*>(nbase + NL.h);
     c.curv_exact = exact;
-    if (launch_tile(MODE_CURV, m, grid0, c, s) != hipSuccess) return DIA_E_HIP;
-    ReduceArgs ra;
-    std::memset(&ra, 0, sizeof(ra));
-    ra.partial = partial;
-    ra.nblk = grid0;
-    ra.npp = m * m + 2;
-    ra.gt = reinterpret_cast<double*>(nbase + NL.hv);
-    ra.n = m * m + 1;
-    ra.m = m;
-    if (launch_reduce(ra, s) != hipSuccess) return DIA_E_HIP;
+    set_background(c, bg_deg, m);
+    const int nb = c.nb, n = m * m + nb;
+    // one curvature pass per background term: term (a, b) weights the per-pixel curvature by
+    // eta^a xi^b, so its partial row is that term's row of H (the first pass also writes h)
+    for (int pa = 0; pa <= bg_deg; ++pa)
+        for (int pb = 0; pb <= bg_deg - pa; ++pb) {
+            c.curv_a = pa;
+            c.curv_b = pb;
+            if (launch_tile(MODE_CURV, m, grid0, c, s) != hipSuccess) return DIA_E_HIP;
+            ReduceArgs ra;
+            std::memset(&ra, 0, sizeof(ra));
+            ra.partial = partial;
+            ra.nblk = grid0;
+            ra.npp = n + 1;
+            ra.gt = reinterpret_cast<double*>(nbase + NL.hv) + (size_t)bg_index(pa, pb, bg_deg) * (n + 1);
+            ra.n = n;
+            ra.m = m;
+            if (launch_reduce(ra, s) != hipSuccess) return DIA_E_HIP;
+        }
     HessArgs ha;
     std::memset(&ha, 0, sizeof(ha));
     ha.R = R.data;
@@ -99,18 +110,17 @@ int hessian_into(const dia_image& R, const dia_image& I, const ObjParams& obj, d
     ha.cols = R.cols;
     ha.partial = reinterpret_cast<double*>(nbase + NL.hpart);
     if (launch_hess(m, ha, s) != hipSuccess) return DIA_E_HIP;
-    if (launch_hess_assemble(ha.partial, NL.splits, NL.npb, m, reinterpret_cast<const double*>(nbase + NL.hv), H, reg,
-                             damp, s) !=
-        hipSuccess)
+    if (launch_hess_assemble(ha.partial, NL.splits, NL.npb, m, nb, reinterpret_cast<const double*>(nbase + NL.hv), H,
+                             reg, damp, s) != hipSuccess)
         return DIA_E_HIP;
     return DIA_OK;
 }
 
-int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int grid,
-                  int variant,
+int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, double reg, int m, int bg_deg,
+                  int grid, int variant,
                   FitState* st, const FitVecs& v, double* partial, char* nbase, const NewtonLayout& NL,
                   int max_steps, bool quadratic, hipStream_t s, NewtonOutcome* out) {
-    const int n = m * m + 1;
+    const int n = m * m + bg_terms(bg_deg);
     double* th = reinterpret_cast<double*>(nbase + NL.th);
     double* d = reinterpret_cast<double*>(nbase + NL.d);
     double* H = reinterpret_cast<double*>(nbase + NL.H);
@@ -121,7 +131,7 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
     if (launch_theta_from_x(st, v, n, s) != hipSuccess) return DIA_E_HIP;
     if (hipMemcpyAsync(th, v.theta_eval64, sizeof(double) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return DIA_E_HIP;
-    if (!eval_into(R, I, obj, reg, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s)) return DIA_E_HIP;
+    if (!eval_into(R, I, obj, reg, m, bg_deg, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s)) return DIA_E_HIP;
     ++out->evals;
     double L = 0.0;
     if (!read_back(&L, gt + n, sizeof(double), s)) return DIA_E_HIP;
@@ -140,7 +150,7 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
         static const double kDamp[] = {0.0, 1e-12, 1e-9, 1e-6};
         for (int form = form0; form < 5; ++form) {
             if (factor) {
-                const int rc = hessian_into(R, I, obj, reg, m, v.theta_eval, v.theta_eval64, form == 0 ? 1 : 0,
+                const int rc = hessian_into(R, I, obj, reg, m, bg_deg, v.theta_eval, v.theta_eval64, form == 0 ? 1 : 0,
                                             partial, nbase, NL, H, s, form == 0 ? 0.0 : kDamp[form - 1]);
                 if (rc != DIA_OK) return rc;
                 ++out->evals;
@@ -168,7 +178,7 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
         double alpha = 1.0;
         for (int ls = 0; ls < 8; ++ls, alpha *= 0.5) {
             if (launch_newton_trial(th, d, alpha, v.theta_eval, v.theta_eval64, n, s) != hipSuccess) return DIA_E_HIP;
-            if (!eval_into(R, I, obj, reg, m, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s))
+            if (!eval_into(R, I, obj, reg, m, bg_deg, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s))
                 return DIA_E_HIP;
             ++out->evals;
             double Lt = 0.0;

@@ -13,8 +13,10 @@ namespace dia {
 constexpr int kCholThreads = 1024;
 
 // H[t1][t2] for the kernel taps from the split partials (fixed order; element (min, max) of the
-// region-pair blocks of 64 x 64, so H is exactly symmetric), the background row from
-// hv = [sum h R_(p+t) (t < m*m), sum h].
+// region-pair blocks of 64 x 64, so H is exactly symmetric), the background rows from hv: row k
+// (stride n + 1) holds [sum h P_k R_(p+t) (t < m*m), sum h P_k P_l (l < nb)], P_k the k-th
+// background term at the pixel (1 for the scalar B0); the background block takes element
+// (min(k, l), max(k, l)), so it is exactly symmetric too.
 // Entry (u, v) of L L, L the kernel-pixel Laplacian (Section 2.7, eq. laplacian; pixels sharing a
 // side are adjacent): sum over w of L_uw L_wv.  On the grid: deg^2 + deg on the diagonal, -(deg u +
 // deg v) for neighbours (they share no neighbour), the number of common neighbours at distance two.
@@ -32,10 +34,10 @@ __device__ __forceinline__ double lap2_entry(int u, int v, int m) {
 }
 
 __global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partial, int splits, int npb, int m,
-                                                            const double* hv, double* H, double reg,
+                                                            int nb, const double* hv, double* H, double reg,
                                                             double damp) {
     constexpr int RG = 64;
-    const int n = m * m + 1, T = m * m;
+    const int T = m * m, n = T + nb;
     const int nr = (T + RG - 1) / RG;
     const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid < (long long)T * T) {
@@ -50,11 +52,19 @@ __global__ __launch_bounds__(256) void hess_assemble_kernel(const double* partia
         if (t1 == t2) s *= 1.0 + damp;
         H[(long long)t1 * n + t2] = s;
     }
-    if (gid < n) {
-        const int t = (int)gid;
-        const double b = (t == n - 1) ? hv[t] * (1.0 + damp) : hv[t];
-        H[(long long)t * n + (n - 1)] = b;
-        H[(long long)(n - 1) * n + t] = b;
+    if (gid < (long long)nb * n) {
+        const int k = (int)(gid / n), t = (int)(gid % n);
+        if (t < T) {
+            const double b = hv[(long long)k * (n + 1) + t];
+            H[(long long)t * n + (T + k)] = b;
+            H[(long long)(T + k) * n + t] = b;
+        } else {
+            const int l = t - T;
+            const int lo = k < l ? k : l, hi = k < l ? l : k;
+            double b = hv[(long long)lo * (n + 1) + T + hi];
+            if (k == l) b *= 1.0 + damp;
+            H[(long long)(T + k) * n + t] = b;
+        }
     }
 }
 
@@ -350,10 +360,10 @@ __global__ __launch_bounds__(256) void cov_syrk_kernel(const double* W, int n, d
     }
 }
 
-// sigma_p = sqrt(Sigma_pp); sigma_P^2 = 1^T Sigma_KK 1 = sum_k (sum_{i < n-1} W[k][i])^2 (the kernel
-// block of Sigma = W^T W), summed in a fixed order.
-__global__ __launch_bounds__(256) void cov_finish_kernel(const double* S, const double* W, int n, double* sigma,
-                                                         double* sigma_P, const double* info) {
+// sigma_p = sqrt(Sigma_pp); sigma_P^2 = 1^T Sigma_KK 1 = sum_k (sum_{i < nk} W[k][i])^2 (the kernel
+// block of Sigma = W^T W, the first nk parameters), summed in a fixed order.
+__global__ __launch_bounds__(256) void cov_finish_kernel(const double* S, const double* W, int n, int nk,
+                                                         double* sigma, double* sigma_P, const double* info) {
     __shared__ double sh[4];
     const int tid = threadIdx.x;
     const bool ok = info[0] == 1.0;
@@ -362,7 +372,7 @@ __global__ __launch_bounds__(256) void cov_finish_kernel(const double* S, const 
     if (ok)
         for (int k = tid; k < n; k += 256) {
             double v = 0.0;
-            for (int i = 0; i < n - 1 && i <= k; ++i) v += W[(long long)k * n + i];
+            for (int i = 0; i < nk && i <= k; ++i) v += W[(long long)k * n + i];
             part += v * v;
         }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -388,17 +398,19 @@ __global__ void newton_trial_kernel(const double* th, const double* d, double al
 __global__ __launch_bounds__(256) void set_x_kernel(FitState* st, FitVecs v, const double* th, int n, double L) {
     __shared__ double sh[8];
     const double c = st->ref_scale, s = st->ref_shift;
+    const int nk = st->nk;
     double ks = 0.0;
-    for (int i = threadIdx.x; i < n - 1; i += 256) {
+    for (int i = threadIdx.x; i < nk; i += 256) {
         v.x[i] = c * th[i];
         ks += th[i];
     }
+    for (int i = nk + 1 + threadIdx.x; i < n; i += 256) v.x[i] = th[i];
     for (int off = 32; off > 0; off >>= 1) ks += __shfl_xor(ks, off);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ks;
     __syncthreads();
     if (threadIdx.x == 0) {
         const double tot = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-        v.x[n - 1] = th[n - 1] + s * tot;
+        v.x[nk] = th[nk] + s * tot;
         st->L = L;
     }
 }
@@ -407,30 +419,36 @@ __global__ __launch_bounds__(256) void set_x_kernel(FitState* st, FitVecs v, con
 __global__ __launch_bounds__(256) void theta_from_x_kernel(const FitState* st, FitVecs v, int n) {
     __shared__ double sh[8];
     const double c = st->ref_scale, s = st->ref_shift;
+    const int nk = st->nk;
     double ks = 0.0;
-    for (int i = threadIdx.x; i < n - 1; i += 256) {
+    for (int i = threadIdx.x; i < nk; i += 256) {
         const double k = v.x[i] / c;
         const float kf = (float)k;
         v.theta_eval[i] = kf;
         v.theta_eval64[i] = (double)kf;
         ks += k;
     }
+    for (int i = nk + 1 + threadIdx.x; i < n; i += 256) {
+        const float bf = (float)v.x[i];
+        v.theta_eval[i] = bf;
+        v.theta_eval64[i] = (double)bf;
+    }
     for (int off = 32; off > 0; off >>= 1) ks += __shfl_xor(ks, off);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = ks;
     __syncthreads();
     if (threadIdx.x == 0) {
         const double tot = ((sh[0] + sh[1]) + sh[2]) + sh[3];
-        const float bf = (float)(v.x[n - 1] - s * tot);
-        v.theta_eval[n - 1] = bf;
-        v.theta_eval64[n - 1] = (double)bf;
+        const float bf = (float)(v.x[nk] - s * tot);
+        v.theta_eval[nk] = bf;
+        v.theta_eval64[nk] = (double)bf;
     }
 }
 
-hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, const double* hv, double* H,
-                                double reg, double damp, hipStream_t s) {
-    const long long work = std::max<long long>((long long)m * m * m * m, m * m + 1);
+hipError_t launch_hess_assemble(const double* partial, int splits, int npb, int m, int nb, const double* hv,
+                                double* H, double reg, double damp, hipStream_t s) {
+    const long long work = std::max<long long>((long long)m * m * m * m, (long long)nb * (m * m + nb));
     const int blocks = (int)((work + 255) / 256);
-    hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, hv, H, reg,
+    hipLaunchKernelGGL(hess_assemble_kernel, dim3(blocks), dim3(256), 0, s, partial, splits, npb, m, nb, hv, H, reg,
                        damp);
     return hipGetLastError();
 }
@@ -442,8 +460,8 @@ hipError_t launch_chol_solve(double* A, int n, int factor, const double* g, cons
     return hipGetLastError();
 }
 
-hipError_t launch_covariance(double* A, int n, double* W, double* S, double* sigma, double* sigma_P, double* info,
-                             hipStream_t s) {
+hipError_t launch_covariance(double* A, int n, int nk, double* W, double* S, double* sigma, double* sigma_P,
+                             double* info, hipStream_t s) {
     // W's first element holds the factorisation's flag until chol_info_kernel has read it
     if (launch_chol_factor(A, n, W, s) != hipSuccess) return hipGetLastError();
     hipLaunchKernelGGL(chol_info_kernel, dim3(1), dim3(kCholThreads), 0, s, (const double*)A, n, (const double*)W,
@@ -451,7 +469,7 @@ hipError_t launch_covariance(double* A, int n, double* W, double* S, double* sig
     hipLaunchKernelGGL(tri_inverse_kernel, dim3(n), dim3(256), 0, s, (const double*)A, n, W, (const double*)info);
     const int nt = (n + kCovTile - 1) / kCovTile;
     hipLaunchKernelGGL(cov_syrk_kernel, dim3(nt, nt), dim3(256), 0, s, (const double*)W, n, S);
-    hipLaunchKernelGGL(cov_finish_kernel, dim3(1), dim3(256), 0, s, (const double*)S, (const double*)W, n, sigma,
+    hipLaunchKernelGGL(cov_finish_kernel, dim3(1), dim3(256), 0, s, (const double*)S, (const double*)W, n, nk, sigma,
                        sigma_P, (const double*)info);
     return hipGetLastError();
 }

@@ -13,8 +13,10 @@
 //   4. backward: dL/dK_ab = sum g_ij R_(i+a)(j+b) — thread (a, strip) correlates the
 //      g tile with the same LDS reference tile into m FP64 accumulators that persist
 //      across the workgroup's tiles.
-// A workgroup reduces its m*m + 2 sums in a fixed order and writes one row of
-// partials; a separate kernel adds the rows in FP64.
+// A workgroup reduces its m*m + nb + 1 sums in a fixed order and writes one row of
+// partials; a separate kernel adds the rows in FP64.  With a polynomial background
+// (POLY, Section 2.6) the forward starts each pixel at B(eta, xi) and the objective step
+// adds g eta^a xi^b into one FP64 sum per background term.
 #pragma once
 
 #include "tile_ops.h"
@@ -35,6 +37,43 @@ __device__ __forceinline__ double ktap(const TileArgs& a, int idx) {
     return (double)a.theta[idx];
 }
 
+// Polynomial background at normalised coordinates (eta, xi): sum over a of eta^a c_a(xi), each
+// c_a(xi) = sum_b b_ab xi^b by Horner's rule (coefficients read from theta after the m*m taps).
+template <int M, int MODE>
+__device__ __forceinline__ double bg_value(const TileArgs& a, double eta, double xi) {
+    const int d = a.bg_deg;
+    double B = 0.0, ep = 1.0;
+    for (int p = 0; p <= d; ++p) {
+        double c = 0.0;
+        for (int b = d - p; b >= 0; --b) c = fma(c, xi, ktap<MODE>(a, M * M + bg_index(p, b, d)));
+        B = fma(c, ep, B);
+        ep *= eta;
+    }
+    return B;
+}
+
+// bg[slot of (a, b)] += g eta^a xi^b for every term of the degree-d background.  The slots follow
+// the highest degree's order, so every register index is a compile-time constant.
+__device__ __forceinline__ void bg_accumulate(double (&bg)[kMaxBgTerms], double g, double eta, double xi, int d) {
+    double ep = g;
+#pragma unroll
+    for (int p = 0; p <= kMaxBgDegree; ++p) {
+        double t = ep;
+#pragma unroll
+        for (int b = 0; b <= kMaxBgDegree - p; ++b) {
+            if (p + b <= d) bg[bg_index(p, b, kMaxBgDegree)] += t;
+            t *= xi;
+        }
+        ep *= eta;
+    }
+}
+
+__device__ __forceinline__ double ipow(double x, int e) {
+    double r = 1.0;
+    for (int k = 0; k < e; ++k) r *= x;
+    return r;
+}
+
 // Reference tile (with its m-1 halo) straight from global memory into LDS (zero outside the image).
 template <int M, int RBV>
 __device__ __forceinline__ void stage_tile(const TileArgs& a, int ty0, int tx0, float* Rs) {
@@ -50,9 +89,10 @@ __device__ __forceinline__ void stage_tile(const TileArgs& a, int ty0, int tx0, 
 // (MODE_EVAL / MODE_CURV) backward into dk64.
 // FP32 data (exactly widened), FP64 products and sums: on gfx950 an FP64 FMA issues at the
 // rate of a non-packed FP32 FMA.
-template <int M, int RBV, int MODE>
+template <int M, int RBV, int MODE, bool POLY = false>
 __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0, int tx0, float* Rs, double* gs,
-                                          double (&dk64)[M], double& loss64, double& db064) {
+                                          double (&dk64)[M], double& loss64, double& db064,
+                                          double (&bg)[kMaxBgTerms]) {
     using G = Geo<M, RBV>;
     constexpr int S = G::S, NS = G::NS, RB = G::RB;
     constexpr int TY = G::TY, RS = G::RS, SP = G::SP, GP = G::GP;
@@ -71,7 +111,15 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
 #pragma unroll
         for (int i = 0; i < RB; ++i)
 #pragma unroll
-            for (int j = 0; j < S; ++j) acc[i][j] = B0;
+            for (int j = 0; j < S; ++j) {
+                if constexpr (POLY) {
+                    const double xi = a.xi0 + (double)(ty0 + q * RB + i) * a.dxi;
+                    const double eta = a.eta0 + (double)(tx0 + cs * S + j) * a.deta;
+                    acc[i][j] = bg_value<M, MODE>(a, eta, xi);
+                } else {
+                    acc[i][j] = B0;
+                }
+            }
         const float* rbase = Rs + (q * RB) * RS + cs * SP;
         for (int r = 0; r < RB + M - 1; ++r) {
             double seg[SEG];
@@ -114,7 +162,11 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                             double l;
                             pixel_objective_d(a.obj, (double)a.I[pix], acc[i][j], w, F, l, g);
                             loss64 += l;
-                            db064 += g;
+                            if constexpr (POLY)
+                                bg_accumulate(bg, g, a.eta0 + (double)ox * a.deta, a.xi0 + (double)oy * a.dxi,
+                                              a.bg_deg);
+                            else
+                                db064 += g;
                         }
                     }
                     gs[ly * GS + cs * GP + j] = g;
@@ -127,8 +179,15 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                             const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
                             hh = pixel_curvature_d(a.obj, (double)a.I[pix], acc[i][j], w, F, a.curv_exact != 0);
                         }
-                        a.h_out[(long long)oy * Wv + ox] = hh;
-                        db064 += hh;
+                        if constexpr (POLY) {
+                            if (a.curv_a == 0 && a.curv_b == 0) a.h_out[(long long)oy * Wv + ox] = hh;
+                            const double eta = a.eta0 + (double)ox * a.deta, xi = a.xi0 + (double)oy * a.dxi;
+                            hh *= ipow(eta, a.curv_a) * ipow(xi, a.curv_b);
+                            bg_accumulate(bg, hh, eta, xi, a.bg_deg);
+                        } else {
+                            a.h_out[(long long)oy * Wv + ox] = hh;
+                            db064 += hh;
+                        }
                     }
                     gs[ly * GS + cs * GP + j] = hh;
                 } else {  // MODE_CLIP
@@ -172,10 +231,11 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
 }
 
 // Fixed-order workgroup reduction of the per-thread sums into one partial row:
-// prow[a*m + b] = dL/dK_ab, prow[m*m] = dL/dB0, prow[m*m + 1] = loss.
-template <int M, int RBV>
-__device__ __forceinline__ void write_partials(const double (&dk64)[M], double loss64, double db064, float* Rs,
-                                               double* prow) {
+// prow[a*m + b] = dL/dK_ab, prow[m*m] = dL/dB0, prow[m*m + 1] = loss; with a polynomial background
+// (POLY, degree d, nb terms) prow[m*m + k] = dL/db_k for k < nb and prow[m*m + nb] = loss.
+template <int M, int RBV, bool POLY = false>
+__device__ __forceinline__ void write_partials(const double (&dk64)[M], double loss64, double db064,
+                                               double (&bg)[kMaxBgTerms], int d, float* Rs, double* prow) {
     using G = Geo<M, RBV>;
     constexpr int NS = G::NS, NT = G::NT;
     const int tid = threadIdx.x;
@@ -197,30 +257,56 @@ __device__ __forceinline__ void write_partials(const double (&dk64)[M], double l
         }
         __syncthreads();
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        loss64 += __shfl_xor(loss64, off);
-        db064 += __shfl_xor(db064, off);
-    }
     const int lane = tid & 63, wave = tid >> 6;
-    if (lane == 0) {
-        red[2 * wave] = db064;
-        red[2 * wave + 1] = loss64;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double sb = 0.0, sl = 0.0;
-        for (int w = 0; w < NT / 64; ++w) {
-            sb += red[2 * w];
-            sl += red[2 * w + 1];
+    if constexpr (POLY) {
+        // one slot per background term of the highest degree, then the loss
+        constexpr int NSL = kMaxBgTerms + 1;
+#pragma unroll
+        for (int k = 0; k < kMaxBgTerms; ++k)
+            for (int off = 32; off > 0; off >>= 1) bg[k] += __shfl_xor(bg[k], off);
+        for (int off = 32; off > 0; off >>= 1) loss64 += __shfl_xor(loss64, off);
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < kMaxBgTerms; ++k) red[NSL * wave + k] = bg[k];
+            red[NSL * wave + kMaxBgTerms] = loss64;
         }
-        prow[M * M] = sb;
-        prow[M * M + 1] = sl;
+        __syncthreads();
+        if (tid == 0) {
+            for (int p = 0; p <= d; ++p)
+                for (int b = 0; b <= d - p; ++b) {
+                    double sb = 0.0;
+                    for (int w = 0; w < NT / 64; ++w) sb += red[NSL * w + bg_index(p, b, kMaxBgDegree)];
+                    prow[M * M + bg_index(p, b, d)] = sb;
+                }
+            double sl = 0.0;
+            for (int w = 0; w < NT / 64; ++w) sl += red[NSL * w + kMaxBgTerms];
+            prow[M * M + bg_terms(d)] = sl;
+        }
+    } else {
+        for (int off = 32; off > 0; off >>= 1) {
+            loss64 += __shfl_xor(loss64, off);
+            db064 += __shfl_xor(db064, off);
+        }
+        if (lane == 0) {
+            red[2 * wave] = db064;
+            red[2 * wave + 1] = loss64;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double sb = 0.0, sl = 0.0;
+            for (int w = 0; w < NT / 64; ++w) {
+                sb += red[2 * w];
+                sl += red[2 * w + 1];
+            }
+            prow[M * M] = sb;
+            prow[M * M + 1] = sl;
+        }
     }
     __syncthreads();
 }
 
 // Single pair: a persistent grid walks a static, XCD-aware list of tiles.
-template <int M, int MODE, int RBV>
+template <int M, int MODE, int RBV, bool POLY = false>
 __global__ __launch_bounds__((Geo<M, RBV>::NT)) void tile_kernel(TileArgs a) {
     using G = Geo<M, RBV>;
     __shared__ Smem<M, RBV> sm;
@@ -241,21 +327,26 @@ __global__ __launch_bounds__((Geo<M, RBV>::NT)) void tile_kernel(TileArgs a) {
     const int t_begin = (int)((long long)ntiles * grp / ngrp);
     const int t_end = (int)((long long)ntiles * (grp + 1) / ngrp);
 
-    const double B0 = ktap<MODE>(a, M * M);
+    const double B0 = POLY ? 0.0 : ktap<MODE>(a, M * M);
     double dk64[M];
 #pragma unroll
     for (int b = 0; b < M; ++b) dk64[b] = 0.0;
     double loss64 = 0.0, db064 = 0.0;
+    double bg[kMaxBgTerms];
+#pragma unroll
+    for (int k = 0; k < kMaxBgTerms; ++k) bg[k] = 0.0;
 
     for (int t = t_begin + mem; t < t_end; t += nmem) {
         const int ty0 = (t / ntx) * G::TY, tx0 = (t % ntx) * G::TX;
         stage_tile<M, RBV>(a, ty0, tx0, sm.Rs);
         __syncthreads();
-        tile_body<M, RBV, MODE>(a, B0, ty0, tx0, sm.Rs, sm.gs, dk64, loss64, db064);
+        tile_body<M, RBV, MODE, POLY>(a, B0, ty0, tx0, sm.Rs, sm.gs, dk64, loss64, db064, bg);
     }
 
-    if (MODE == MODE_EVAL || MODE == MODE_CURV)
-        write_partials<M, RBV>(dk64, loss64, db064, sm.Rs, a.partial + (long long)blockIdx.x * (M * M + 2));
+    if (MODE == MODE_EVAL || MODE == MODE_CURV) {
+        const long long npp = POLY ? (M * M + bg_terms(a.bg_deg) + 1) : (M * M + 2);
+        write_partials<M, RBV, POLY>(dk64, loss64, db064, bg, a.bg_deg, sm.Rs, a.partial + (long long)blockIdx.x * npp);
+    }
 }
 
 // Batched fused pass: a persistent grid pops chunks (runs of tiles of one epoch)
@@ -293,13 +384,14 @@ __global__ __launch_bounds__((Geo<M, RBV>::NT)) void batched_eval_kernel(Batched
 #pragma unroll
         for (int k = 0; k < M; ++k) dk64[k] = 0.0;
         double loss64 = 0.0, db064 = 0.0;
+        double bg[kMaxBgTerms];  // unused: the batched fits have the scalar background
         for (int t = ch.t_begin; t < ch.t_end; ++t) {
             stage_tile<M, RBV>(a, (t / e.ntx) * G::TY, (t % e.ntx) * G::TX, sm.Rs);
             __syncthreads();
             tile_body<M, RBV, MODE_EVAL>(a, B0, (t / e.ntx) * G::TY, (t % e.ntx) * G::TX, sm.Rs, sm.gs, dk64, loss64,
-                                         db064);
+                                         db064, bg);
         }
-        write_partials<M, RBV>(dk64, loss64, db064, sm.Rs, b.partial + (long long)c * (M * M + 2));
+        write_partials<M, RBV>(dk64, loss64, db064, bg, 0, sm.Rs, b.partial + (long long)c * (M * M + 2));
     }
 }
 
@@ -329,6 +421,19 @@ static hipError_t launch_bv(int grid, const BatchedArgs& b, hipStream_t s) {
 template <int M>
 hipError_t TileOps<M>::launch(int mode, int grid, const TileArgs& a, hipStream_t s, int v) {
     dim3 blk(Geo<M, 0>::NT), grd(grid);
+    if (a.bg_deg > 0) {
+        // polynomial background: the default tile shape; no reweight/clip pass
+        if (v != 0 || a.bg_deg > kMaxBgDegree || a.nb != bg_terms(a.bg_deg)) return hipErrorInvalidValue;
+        if (mode == MODE_EVAL)
+            hipLaunchKernelGGL((tile_kernel<M, MODE_EVAL, 0, true>), grd, blk, 0, s, a);
+        else if (mode == MODE_CURV)
+            hipLaunchKernelGGL((tile_kernel<M, MODE_CURV, 0, true>), grd, blk, 0, s, a);
+        else if (mode == MODE_MODEL)
+            hipLaunchKernelGGL((tile_kernel<M, MODE_MODEL, 0, true>), grd, blk, 0, s, a);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (v == 0 || mode != MODE_EVAL) {
         if (mode == MODE_EVAL)
             hipLaunchKernelGGL((tile_kernel<M, MODE_EVAL, 0>), grd, blk, 0, s, a);

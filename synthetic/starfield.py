@@ -190,12 +190,25 @@ def star_field(rng, H, W, n_stars, flux_min, flux_max, psf_kind, fwhm, sky, beta
     return render_stars((H, W), x, y, flux, psf, radius, sky)
 
 
+def smooth_background(H: int, W: int, tilt_x: float, tilt_y: float, bump: float) -> np.ndarray:
+    """A smooth differential-background field on an H x W grid: a plane of the given end-to-end
+    tilts (ADU across the image) plus a wide Gaussian bump of the given height off the centre."""
+    r, c = np.mgrid[0:H, 0:W].astype(np.float64)
+    s = 0.4 * max(H, W)
+    return (tilt_x * (c / W - 0.5) + tilt_y * (r / H - 0.5)
+            + bump * np.exp(-((r - 0.3 * H) ** 2 + (c - 0.6 * W) ** 2) / (2.0 * s * s)))
+
+
 def make_pair(H, W, m, *, n_stars, flux_min, flux_max, psf_kind, fwhm, sky, K_true, B0,
-              sigma0_e, gain, noise=True, config=0, epoch=0) -> Pair:
+              sigma0_e, gain, noise=True, config=0, epoch=0, background=None) -> Pair:
+    """A reference star field and its target R (x) K_true + B0 (+ the field ``background`` when given),
+    with CCD noise."""
     rng = rng_for(config, epoch)
     R = star_field(rng, H, W, n_stars, flux_min, flux_max, psf_kind, fwhm, sky)
     R32 = R.astype(np.float32)
     I_nl = correlate_target(R32.astype(np.float64), K_true, B0)
+    if background is not None:
+        I_nl = I_nl + background
     I = add_ccd_noise(I_nl, gain, sigma0_e, rng) if noise else I_nl
     return Pair(R=R32, I=I.astype(np.float32), m=m, K_true=K_true, B0_true=B0,
                 sigma0_adu=sigma0_e / gain, gain=gain, I_noiseless=I_nl,
@@ -208,6 +221,17 @@ def config1(noise=True) -> Pair:
     K = kernel_gaussian(9, 1.5, dx=0.3, dy=0.3, total=1.1)
     return make_pair(128, 128, 9, n_stars=150, flux_min=1e2, flux_max=1e5, psf_kind="gauss", fwhm=2.0,
                      sky=100.0, K_true=K, B0=5.0, sigma0_e=5.0, gain=1.0, noise=noise, config=1)
+
+
+def config_varying_background(size: int = 128, m: int = 9, noise: bool = True) -> Pair:
+    """A pair whose differential background varies over the field (Section 2.6's case): config 1's
+    star field, PSF and kernel shape (m x m) at size^2 (150 stars per 128^2), with a tilt of 12 and
+    -7 ADU across the image and a bump of 9 ADU added to the target before the noise."""
+    K = kernel_gaussian(m, 1.5, dx=0.3, dy=0.3, total=1.1)
+    n = int(round(150 * (size / 128) ** 2))
+    return make_pair(size, size, m, n_stars=n, flux_min=1e2, flux_max=1e5, psf_kind="gauss", fwhm=2.0,
+                     sky=100.0, K_true=K, B0=5.0, sigma0_e=5.0, gain=1.0, noise=noise, config=7,
+                     background=smooth_background(size, size, 12.0, -7.0, 9.0))
 
 
 def config2(noise=True, size=1024) -> Pair:

@@ -115,6 +115,8 @@ def test_loss_grad_argument_errors_return_before_hip(dia):
     assert _call_loss_grad(dia, R, I, _obj(dia, lam=-1.0)) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia, lam=float("nan"))) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia, lam=float("inf"))) == dia.E_ARG
+    assert _call_loss_grad(dia, R, I, _obj(dia, bg_degree=-1)) == dia.E_ARG
+    assert _call_loss_grad(dia, R, I, _obj(dia, bg_degree=dia.MAX_BG_DEGREE + 1)) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia), theta=0) == dia.E_ARG
     assert _call_loss_grad(dia, R, I, _obj(dia), ws=0) == dia.E_WORKSPACE
     assert _call_loss_grad(dia, R, I, _obj(dia), ws=0x500001) == dia.E_WORKSPACE
@@ -138,6 +140,10 @@ def test_fit_option_errors_return_before_hip(dia):
     assert call(max_eval=0) == dia.E_ARG
     assert call(init=1, init_phi=0.0) == dia.E_ARG
     assert call(clip_kappa=-1.0) == dia.E_ARG
+    assert call(max_lbfgs=-1) == dia.E_ARG
+    obj.bg_degree = 1  # the reweight/clip loop keeps the scalar background
+    assert call(max_outer=3, clip_kappa=3.0) == dia.E_ARG
+    obj.bg_degree = 0
     assert call(poll_every=0) == dia.E_ARG
     o = dia.fit_options(max_outer=3)
     wobj = _obj(dia, var=0, weights=0x700000)

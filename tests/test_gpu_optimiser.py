@@ -169,3 +169,24 @@ def test_first_order_cap_is_reported_beside_a_converged_polish(dia, setup):
     res = dia.fit(R, I, m, o_gpu, max_adam=2, max_lbfgs=2)
     assert res.status == dia.OK and res.stop == "newton"
     assert res.first_order_stop == "cap" and res.n_lbfgs == 2
+
+
+@pytest.mark.parametrize("rho,var", [("gauss", "ccd_data"), ("cauchy", "ccd_model")])
+def test_no_lbfgs_phase_hands_over_to_newton(dia, rho, var):
+    # max_lbfgs = 0: the first-order part ends at the Adam switch and the exact-Hessian Newton steps take
+    # the fit to the oracle's minimiser (the eq. newtonupdate form with the exact Hessian)
+    p = sf.config1()
+    m = p.m
+    o_or = oracle.Objective(rho=rho, var=var, sigma0=p.sigma0_adu, gain=p.gain, c=2.3849)
+    o_gpu = dia.Objective(rho=rho, var=var, sigma0=p.sigma0_adu, gain=p.gain, c=2.3849)
+    res = dia.fit(gpu(p.R), gpu(p.I), m, o_gpu, tol_switch=1e-4, max_lbfgs=0, max_newton=30)
+    ref = oracle.solve(p.R, p.I, m, o_or)
+    th = res.theta.cpu().double().numpy()
+    eK = np.linalg.norm(th[:m * m] - ref[:m * m]) / np.linalg.norm(ref[:m * m])
+    eP = abs(res.P - ref[:m * m].sum()) / abs(ref[:m * m].sum())
+    eB = abs(res.B0 - ref[-1]) / max(abs(ref[-1]), 1.0)
+    assert res.n_lbfgs == 0 and res.n_newton >= 1 and res.stop == "newton", res
+    assert res.first_order_stop in ("rel_change", "cap"), res.first_order_stop
+    assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4, (eK, eP, eB)
+    # the Adam phase ended on the switch rule, not on its cap
+    assert res.n_adam < 5000
