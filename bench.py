@@ -15,8 +15,9 @@ reduction and the optimiser update.
 
 Printed (one JSON line): fwd+bwd Gtap/s sustained through the timed fits
 (value), fits/s, evaluations per fit, the fused kernel's roofline fraction
-(its duration measured with HIP events around a burst of back-to-back
-loss/gradient launches on the launch stream), the FP64 CPU oracle timed on
+(its duration measured with HIP events around a captured graph of back-to-back
+loss/gradient calls on the launch stream, each call the widening of theta, the
+fused pass and the reduction), the FP64 CPU oracle timed on
 a bounded sample of the same pair, and ("batched") the split-precision bf16x3
 matrix-core form on 256 epochs of 2048^2 against one shared reference (m = 25)
 beside the plain form on the first 32 of them: fits/s, evaluations per fit and
@@ -458,20 +459,35 @@ def main() -> int:
             newton_sched["chi2" if rho == "gauss" else "cauchy"] = rec
             print(f"# newton schedule {rho}: {rec}", file=sys.stderr, flush=True)
 
-    # ------------------------------------------------------------------ kernel duration: burst of fused passes
+    # ------------------------------------------------------------------ kernel duration: back-to-back fused passes
+    # kernel_reps dia_loss_grad calls (each: the FP64 widening of theta, the fused pass, the reduction) captured
+    # in one graph on this stream and replayed, so that no host gap separates the launches (an eager burst is
+    # bound by the Python call, and the clock drops in the gaps); every replay is checked against the eager loss
     theta = results[-1].theta.clone()
     loss = torch.empty(1, dtype=torch.float64, device=dev)
     grad = torch.empty(m * m + 1, dtype=torch.float32, device=dev)
     for _ in range(3):
         dia.loss_grad(R, I, theta, m, obj, ws, loss, grad)
     torch.cuda.synchronize()
+    L_eager = loss.item()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(args.kernel_reps):
+            dia.loss_grad(R, I, theta, m, obj, ws, loss, grad)
+    for _ in range(2):
+        loss.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        if loss.item() != L_eager:
+            raise RuntimeError(f"graph replay of the fused pass gave {loss.item()} instead of {L_eager}")
     kb, ke = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     kb.record()
-    for _ in range(args.kernel_reps):
-        dia.loss_grad(R, I, theta, m, obj, ws, loss, grad)
+    graph.replay()
     ke.record()
     torch.cuda.synchronize()
     t_launch = kb.elapsed_time(ke) / 1e3 / args.kernel_reps
+    if loss.item() != L_eager:
+        raise RuntimeError("timed graph replay of the fused pass disagrees with the eager loss")
     flop_per_launch = 2.0 * taps_per_eval
     achieved_tflops = flop_per_launch / t_launch / 1e12
     traffic = traffic_from_profile(kernel_source_sig())
