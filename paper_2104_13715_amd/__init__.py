@@ -25,7 +25,8 @@ from typing import Optional
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdia.so")
+# DIA_LIBRARY names another build of the same library (the host-sanitizer build of the CPU checks)
+LIB_PATH = os.environ.get("DIA_LIBRARY") or os.path.join(_HERE, "libdia.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libdia.so not found at {LIB_PATH}; build it with `python -m paper_2104_13715_amd.build`")
