@@ -142,3 +142,62 @@ def test_loss_grad_batched_uneven_full_size_sampled(dia):
         print(f"epoch {k} side {sides[k]}: grad rel err dK {eK:.2e} dB0 {eB:.2e}")
         assert eK <= 1e-5 and eB <= 1e-5
         assert abs(loss[k].item() - L_ref) <= 2e-6 * abs(L_ref)
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batched_oracle_thetas.npz")
+    if not os.path.exists(path):
+        pytest.skip("batched_oracle_thetas.npz not written (tests/golden/make_batched_oracle.py)")
+    z = np.load(path)
+    if f"{name}_epochs" not in z.files:
+        pytest.skip(f"no {name} epochs in batched_oracle_thetas.npz yet")
+    return {int(e): (th, s) for e, th, s in zip(z[f"{name}_epochs"], z[f"{name}_theta"], z[f"{name}_target_sum"])}
+
+
+def test_fit_batched_full_uneven_recipe_matches_oracle(dia):
+    # the full uneven-batch recipe: 64 epochs of side 512..2048 cut from the shared 2048^2 reference
+    # (30,000 stars), 17x17 kernels, one batched fit; every epoch the oracle solved
+    # (tests/golden/make_batched_oracle.py: every eighth) against its minimiser at the 1e-4 bar
+    gold = _golden("c4")
+    b = sf.config4(workers=16)
+    m = b.m
+    for e, (_, s) in gold.items():
+        assert float(np.sum(b.epochs[e].I, dtype=np.float64)) == s, "the seeded inputs differ from the solved ones"
+    o, _ = objs(dia, b)
+    theta, res, st = dia.fit_batched(gpu(b.R), epochs_gpu(dia, b), m, o)
+    th = theta.cpu().double().numpy()
+    assert st >= 0 and all(r.status >= 0 for r in res)
+    worst = 0.0
+    for e, (ref, _) in gold.items():
+        K, Kr = th[e, :m * m], ref[:m * m]
+        eK = np.linalg.norm(K - Kr) / np.linalg.norm(Kr)
+        eP = abs(res[e].P - Kr.sum()) / abs(Kr.sum())
+        eB = abs(res[e].B0 - ref[-1]) / max(abs(ref[-1]), 1.0)
+        worst = max(worst, eK, eP, eB)
+        assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4, (e, b.epochs[e].I.shape, eK, eP, eB)
+    print(f"uneven batch: {len(gold)} epochs checked, worst relative error {worst:.2e}")
+
+
+def test_fit_batched_full_shared_recipe_sample_matches_oracle(dia):
+    # eight epochs of the 256 x 2048^2, m = 25 recipe (the first eight the oracle solved), both precisions
+    gold = _golden("c5")
+    pick = sorted(gold)[:8]
+    b = sf.config5(n_epochs=max(pick) + 1, workers=16)
+    m = b.m
+    eps = [b.epochs[e] for e in pick]
+    for e in pick:
+        assert float(np.sum(b.epochs[e].I, dtype=np.float64)) == gold[e][1]
+    o, _ = objs(dia, b)
+    E = [dia.Epoch(I=gpu(ep.I), ref_row0=ep.row0, ref_col0=ep.col0) for ep in eps]
+    for prec in ("plain", "bf16x3"):
+        theta, res, st = dia.fit_batched(gpu(b.R), E, m, o, precision=prec)
+        th = theta.cpu().double().numpy()
+        assert st >= 0
+        for k, e in enumerate(pick):
+            ref = gold[e][0]
+            K, Kr = th[k, :m * m], ref[:m * m]
+            eK = np.linalg.norm(K - Kr) / np.linalg.norm(Kr)
+            eP = abs(res[k].P - Kr.sum()) / abs(Kr.sum())
+            eB = abs(res[k].B0 - ref[-1]) / max(abs(ref[-1]), 1.0)
+            assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4, (prec, e, eK, eP, eB)
