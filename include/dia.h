@@ -148,7 +148,9 @@ int dia_model_bg(dia_image R, const float* theta, int32_t m, int32_t bg_degree, 
  * process times the compiled shapes on this data, synchronising the stream
  * once (DIA_TILE_VARIANT=k pins shape k, DIA_AUTOTUNE=0 keeps the default;
  * shapes: 0 the default rows per thread, 1 / 2 / 3 one / two / four rows per
- * thread where the LDS budget allows, compiled for m = 9, 17, 19, 25):
+ * thread where the LDS budget allows, 4 two sets of threads with one row each
+ * (eight waves per workgroup), 5 a narrow tile for small images; 1-5 are
+ * compiled for m = 9, 17, 19, 25):
  *   *loss   = L(theta)  summed over valid, unmasked pixels, FP64      (device double[1])
  *   grad[k] = dL/dK_k = sum_p g_p R_(p + k),  grad[m*m] = dL/dB0 = sum_p g_p,
  *             g_p = d l_p / d M_p                                      (device float[n])

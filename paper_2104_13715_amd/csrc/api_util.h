@@ -242,12 +242,20 @@ struct Autotuner {
     std::map<std::tuple<std::string, int, int, int>, int> cache;
     bool loaded = false;
 
+    // the architecture name of the current device (looked up once per device)
     static std::string device_name() {
+        static std::mutex nmu;
+        static std::map<int, std::string> names;
+        const int dev = device_id();
+        std::lock_guard<std::mutex> lk(nmu);
+        auto it = names.find(dev);
+        if (it != names.end()) return it->second;
         hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, device_id()) != hipSuccess) return "unknown";
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
         std::string s = p.gcnArchName;
         for (auto& ch : s)
             if (ch == ' ') ch = '_';
+        names[dev] = s;
         return s;
     }
 
@@ -274,6 +282,24 @@ struct Autotuner {
     }
 
     // time_fn(variant) returns the measured milliseconds (< 0 on failure).
+    // The choice that needs no timing, if there is one: a pinned variant, the default when tuning is
+    // off, or a cached choice.
+    bool settled(int m, int sc, int kind, int n_variants, int* v) {
+        if (const char* pin = std::getenv("DIA_TILE_VARIANT")) {
+            const int p = std::atoi(pin);
+            if (p >= 0 && p < n_variants && tile_variant_rb(m, p) != 0) return *v = p, true;
+        }
+        if (const char* at = std::getenv("DIA_AUTOTUNE"))
+            if (std::atoi(at) == 0) return *v = 0, true;
+        const std::string name = device_name();
+        std::lock_guard<std::mutex> lk(mu);
+        load_locked();
+        auto it = cache.find({name, m, sc, kind});
+        if (it != cache.end() && it->second < n_variants && tile_variant_rb(m, it->second) != 0)
+            return *v = it->second, true;
+        return false;
+    }
+
     // Variants 0 .. n_variants - 1 are candidates (the batched kinds leave out the narrow shape).
     // may_time = false (a call being captured into a graph): a cached choice or the default, nothing
     // timed and nothing cached.  A choice is cached only when every candidate was timed.

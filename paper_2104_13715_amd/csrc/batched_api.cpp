@@ -43,9 +43,9 @@ Plan make_plan(int m, const dia_epoch* ep, int n, int variant) {
 }
 
 // The batched forms use the wide tile shapes only: every epoch descriptor carries the tiles across
-// for the default tile width, which the narrow shape (variant 4) does not share; many epochs fill
+// for the default tile width, which the narrow shape (variant 5) does not share; many epochs fill
 // the chip without it.
-constexpr int kBatchedVariants = 4;
+constexpr int kBatchedVariants = 5;
 
 int max_chunks(int m, const dia_epoch* ep, int n) {
     int mx = 0;

@@ -72,6 +72,9 @@ int choose_variant(const TileArgs& a, int m, hipStream_t s) {
 int choose_variant_for_caller(const TileArgs& a, int m, hipStream_t user, bool may_time = true) {
     const int sc = size_class((double)(a.rows - m + 1) * (a.cols - m + 1));
     if (!may_time || stream_capturing(user)) return autotuner().pick(m, sc, /*kind=*/0, nullptr, kNumVariants, false);
+    // a settled choice needs no private stream (and no wait on the caller's work)
+    int settled = 0;
+    if (autotuner().settled(m, sc, /*kind=*/0, kNumVariants, &settled)) return settled;
     hipStream_t ps = nullptr;
     hipEvent_t ev = nullptr;
     int v = 0;

@@ -76,7 +76,10 @@ struct TileArgs {
 // with this skew the lanes of a wave read distinct banks (backward, g tile) or at most two-way
 // shared ones (forward).
 // RBV selects the rows per forward thread (0 = the largest of 4, 2, 1 whose LDS fits the budget);
-// the autotuner chooses among the variants that are compiled.
+// the autotuner chooses among the variants that are compiled.  RBV >= 16 asks for two thread sets
+// (TS = 2) of RBV - 16 forward rows per thread: twice the threads and tile rows of the same
+// per-thread work, each set correlating its own half of the g tile in the backward pass, so a
+// workgroup is 8 waves and two workgroups per CU give 4 waves per SIMD.
 template <int M, int RBV = 0>
 struct Geo {
     static constexpr int kLdsBudget = 80 * 1024;         // two workgroups per CU
@@ -85,10 +88,11 @@ struct Geo {
     static constexpr int GP = 9;                         // g strip pitch (doubles per 8 columns)
     // RBV >= 8 asks for the narrow shape (RBV - 8 forward rows per thread): about one wave of column
     // strips per workgroup, so that images too small to fill the chip with wide tiles still do
-    static constexpr bool NARROW = RBV >= 8;
-    static constexpr int RBR = NARROW ? RBV - 8 : RBV;
+    static constexpr bool NARROW = RBV >= 8 && RBV < 16;
+    static constexpr int TS = RBV >= 16 ? 2 : 1;         // thread sets
+    static constexpr int RBR = NARROW ? RBV - 8 : (TS == 2 ? RBV - 16 : RBV);
     static constexpr int NS = NARROW ? ((64 / M) > 1 ? (64 / M) : 1) : ((256 / M) < 32 ? (256 / M) : 32);
-    static constexpr int NA = M * NS;                    // active threads
+    static constexpr int NA = TS * M * NS;               // active threads
     static constexpr int NT = ((NA + 63) / 64) * 64;     // launched threads (whole waves)
     static constexpr int TX = NS * S;
     static constexpr int RW = TX + M - 1;                // reference tile width (columns)
@@ -96,11 +100,15 @@ struct Geo {
     static constexpr int RS = RS0 + ((2 - RS0) % 64 + 64) % 64;  // row stride, = 2 (mod 64)
     static constexpr int GS = NS * GP;                   // g tile row stride (doubles)
     // FP32 reference tile + FP64 g tile
-    static constexpr int lds_bytes(int rb) { return 4 * (M * rb + M - 1) * RS + 8 * M * rb * GS; }
+    static constexpr int lds_bytes(int rb) { return 4 * (TS * M * rb + M - 1) * RS + 8 * TS * M * rb * GS; }
     static constexpr int RB_AUTO = lds_bytes(4) <= kLdsBudget ? 4 : (lds_bytes(2) <= kLdsBudget ? 2 : 1);
     static constexpr int RB = (RBR > 0 && lds_bytes(RBR) <= kLdsBudget) ? RBR : RB_AUTO;
-    static constexpr int TY = M * RB;
+    static constexpr int TY = TS * M * RB;
+    static constexpr int TYS = M * RB;                   // g rows of one thread set
     static constexpr int RH = TY + M - 1;                // reference tile height
+    // waves per SIMD that the LDS allows (160 KB per CU); the kernels are compiled for it
+    static constexpr int WAVES_PER_EU0 = ((160 * 1024) / lds_bytes(RB)) * (NT / 64) / 4;
+    static constexpr int WAVES_PER_EU = WAVES_PER_EU0 < 1 ? 1 : (WAVES_PER_EU0 > 8 ? 8 : WAVES_PER_EU0);
     // word offset of column c within a reference row / double offset within a g row
     static __host__ __device__ constexpr int rcol(int c) { return (c >> 3) * SP + (c & 7); }
     static __host__ __device__ constexpr int gcol(int c) { return (c >> 3) * GP + (c & 7); }
@@ -307,7 +315,7 @@ __device__ __forceinline__ float model_variance(const ObjParams& o, float M, flo
 }
 
 // Launchers for the tiled kernels (tile_kernels.hip).  Return hipError_t.
-constexpr int kNumVariants = 5;  // tile-shape variants: RB = auto, 1, 2, 4; narrow with RB = 1
+constexpr int kNumVariants = 6;  // tile-shape variants: RB = auto, 1, 2, 4; two thread sets of RB = 1; narrow RB = 1
 int tile_variant_rb(int m, int variant);               // effective RB of a variant (0 = not compiled)
 int tile_dims(int m, int variant, int* ty, int* tx);   // tile height / width of a variant
 int tile_grid_tiles(int m, int rows, int cols, int variant = 0);  // tiles of the valid region

@@ -20,13 +20,22 @@ static int variant_rb_m(int v) {
         case 1: return Geo<M, 1>::RB;
         case 2: return Geo<M, 2>::RB;
         case 3: return Geo<M, 4>::RB;
+        case 4: return Geo<M, 17>::RB;
         default: return Geo<M, 9>::RB;
     }
 }
 
+// tile height and width of a compiled variant
 template <int M>
-static int variant_tx_m(int v) {
-    return (v == 4 && HasVariants<M>::value) ? Geo<M, 9>::TX : Geo<M, 0>::TX;
+static void variant_dims_m(int v, int* ty, int* tx) {
+    switch (v) {
+        case 0: *ty = Geo<M, 0>::TY, *tx = Geo<M, 0>::TX; break;
+        case 1: *ty = Geo<M, 1>::TY, *tx = Geo<M, 1>::TX; break;
+        case 2: *ty = Geo<M, 2>::TY, *tx = Geo<M, 2>::TX; break;
+        case 3: *ty = Geo<M, 4>::TY, *tx = Geo<M, 4>::TX; break;
+        case 4: *ty = Geo<M, 17>::TY, *tx = Geo<M, 17>::TX; break;
+        default: *ty = Geo<M, 9>::TY, *tx = Geo<M, 9>::TX; break;
+    }
 }
 
 int tile_variant_rb(int m, int variant) {
@@ -45,16 +54,15 @@ int tile_dims(int m, int variant, int* ty, int* tx) {
     const int rb = tile_variant_rb(m, variant);
     if (rb == 0) return -1;
     switch (m) {
-#define X(MM)                      \
-    case MM:                       \
-        *tx = variant_tx_m<MM>(variant); \
+#define X(MM)                                   \
+    case MM:                                    \
+        variant_dims_m<MM>(variant, ty, tx);    \
         break;
         DIA_FOR_EACH_M(X)
 #undef X
         default:
             return -1;
     }
-    *ty = m * rb;
     return 0;
 }
 

@@ -210,10 +210,13 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
     if (MODE == MODE_EVAL || MODE == MODE_CURV) {
         __syncthreads();
         if (active) {
-            // 4. backward: dk[b] += sum_i sum_j g[i][j] * R[i + q][j + b] over this strip
+            // 4. backward: dk[b] += sum_i sum_j g[i][j] * R[i + a][j + b] over this strip, thread q = (set, a)
+            // taking the g rows of its set
+            constexpr int TYS = G::TYS;
+            const int set = q / M, ka = q - set * M;
             const double* gb = gs + cs * GP;
-            const float* rbase = Rs + q * RS + cs * SP;
-            for (int i = 0; i < TY; ++i) {
+            const float* rbase = Rs + ka * RS + cs * SP;
+            for (int i = set * TYS; i < (set + 1) * TYS; ++i) {
                 double gv[S];
 #pragma unroll
                 for (int j = 0; j < S; ++j) gv[j] = gb[i * GS + j];
@@ -252,7 +255,8 @@ __device__ __forceinline__ void write_partials(const double (&dk64)[M], double l
         for (int o = tid; o < M * nbr; o += NT) {
             const int ka = o / nbr, kb = o - ka * nbr;
             double s = 0.0;
-            for (int c = 0; c < NS; ++c) s += red[kb * NT + ka * NS + c];
+            for (int set = 0; set < G::TS; ++set)
+                for (int c = 0; c < NS; ++c) s += red[kb * NT + (set * M + ka) * NS + c];
             prow[ka * M + b0 + kb] = s;
         }
         __syncthreads();
@@ -307,7 +311,8 @@ __device__ __forceinline__ void write_partials(const double (&dk64)[M], double l
 
 // Single pair: a persistent grid walks a static, XCD-aware list of tiles.
 template <int M, int MODE, int RBV, bool POLY = false>
-__global__ __launch_bounds__((Geo<M, RBV>::NT)) void tile_kernel(TileArgs a) {
+__global__ __launch_bounds__((Geo<M, RBV>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, RBV>::WAVES_PER_EU)))
+void tile_kernel(TileArgs a) {
     using G = Geo<M, RBV>;
     __shared__ Smem<M, RBV> sm;
     if (a.done != nullptr && *a.done != 0) return;
@@ -353,7 +358,8 @@ __global__ __launch_bounds__((Geo<M, RBV>::NT)) void tile_kernel(TileArgs a) {
 // from a work queue.  Each chunk has its own partial row, so the result does not
 // depend on which workgroup ran it.  Chunks of converged epochs are skipped.
 template <int M, int RBV>
-__global__ __launch_bounds__((Geo<M, RBV>::NT)) void batched_eval_kernel(BatchedArgs b) {
+__global__ __launch_bounds__((Geo<M, RBV>::NT)) __attribute__((amdgpu_waves_per_eu(Geo<M, RBV>::WAVES_PER_EU)))
+void batched_eval_kernel(BatchedArgs b) {
     using G = Geo<M, RBV>;
     __shared__ Smem<M, RBV> sm;
     __shared__ int chunk_sh;
@@ -449,6 +455,7 @@ hipError_t TileOps<M>::launch(int mode, int grid, const TileArgs& a, hipStream_t
         if (v == 1) return launch_eval_v<M, 1>(grid, a, s);
         if (v == 2) return launch_eval_v<M, 2>(grid, a, s);
         if (v == 3) return launch_eval_v<M, 4>(grid, a, s);
+        if (v == 4) return launch_eval_v<M, 17>(grid, a, s);
         return launch_eval_v<M, 9>(grid, a, s);
     }
     return hipErrorInvalidValue;
@@ -461,6 +468,7 @@ hipError_t TileOps<M>::launch_batched(int grid, const BatchedArgs& b, hipStream_
         if (v == 1) return launch_bv<M, 1>(grid, b, s);
         if (v == 2) return launch_bv<M, 2>(grid, b, s);
         if (v == 3) return launch_bv<M, 4>(grid, b, s);
+        if (v == 4) return launch_bv<M, 17>(grid, b, s);
         return launch_bv<M, 9>(grid, b, s);
     }
     return hipErrorInvalidValue;
@@ -473,6 +481,7 @@ int TileOps<M>::occupancy(int v, bool batched) {
         if (v == 1) return occupancy_for<M, 1>(batched);
         if (v == 2) return occupancy_for<M, 2>(batched);
         if (v == 3) return occupancy_for<M, 4>(batched);
+        if (v == 4) return occupancy_for<M, 17>(batched);
         return occupancy_for<M, 9>(batched);
     }
     return 1;

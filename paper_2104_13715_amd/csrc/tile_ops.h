@@ -13,8 +13,10 @@ struct HasVariants {
 };
 
 // Variant v -> the Geo parameter: forward rows per thread requested (0 = automatic; variant 3 asks
-// for 4), and variant 4 the narrow shape with one row.
-constexpr int variant_rbv(int v) { return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : (v == 4 ? 9 : 0))); }
+// for 4), variant 4 two thread sets of one row, variant 5 the narrow shape with one row.
+constexpr int variant_rbv(int v) {
+    return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : (v == 4 ? 17 : (v == 5 ? 9 : 0))));
+}
 
 template <int M>
 struct TileOps {

@@ -106,7 +106,7 @@ def test_loss_grad_batched_pinned_tile_shapes_agree(dia, small_batch, monkeypatc
     o, _ = objs(dia, b)
     th = np.stack([oracle.init_theta(e.I, m) for e in b.epochs]).astype(np.float32)
     grads = []
-    for v in ("1", "2", "3"):  # the narrow shape (4) is a single-pair shape
+    for v in ("1", "2", "3", "4"):  # the narrow shape (5) is a single-pair shape
         monkeypatch.setenv("DIA_TILE_VARIANT", v)
         _, g = dia.loss_grad_batched(gpu(b.R), epochs_gpu(dia, b), gpu(th), m, o)
         grads.append(g.cpu().double().numpy())

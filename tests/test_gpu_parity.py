@@ -193,7 +193,7 @@ def test_loss_grad_kernel_sizes_and_ragged_tiles(dia, m, H, W):
     check_grad(g, g_ref, m, (R, I, theta, o_or))
 
 
-@pytest.mark.parametrize("variant", ["1", "2", "3", "4"])
+@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5"])
 @pytest.mark.parametrize("m,H,W", [(9, 130, 301), (17, 200, 170), (19, 300, 250), (25, 170, 151)])
 def test_loss_grad_pinned_tile_shapes(dia, monkeypatch, m, H, W, variant):
     # every compiled tile shape
@@ -313,10 +313,10 @@ def test_fit_config1_chi2(dia, c1, init):
     assert abs(res.P - ref[:p.m ** 2].sum()) <= 1e-4 * abs(ref[:p.m ** 2].sum())
 
 
-@pytest.mark.parametrize("variant", ["0", "4"])
+@pytest.mark.parametrize("variant", ["0", "4", "5"])
 def test_fit_config1_pinned_tile_shape(dia, c1, monkeypatch, variant):
-    # the wide default and the narrow shape chosen for small images (19 x 24 outputs per workgroup
-    # at m = 9 ... 25) drive the whole fit, Newton polish included
+    # the wide default, the two-thread-set shape and the narrow shape chosen for small images (19 x 24
+    # outputs per workgroup at m = 9 ... 25) drive the whole fit, Newton polish included
     monkeypatch.setenv("DIA_TILE_VARIANT", variant)
     p = c1
     o_or, o_gpu = to_objs(dia, "huber", "ccd_model", p.sigma0_adu, p.gain)
