@@ -572,6 +572,7 @@ def main() -> int:
         "fused_pass_us": round(1e6 * t_launch, 2),
         "kernel_gtaps": round(taps_per_eval / t_launch / 1e9, 1),
         "fit_stop": results[-1].stop,
+        "tile_shape": dict(zip(("variant", "rows", "cols"), dia.tile_shape(m, H, W))),
         "fit_counts": {"n_adam": results[-1].n_adam, "n_lbfgs": results[-1].n_lbfgs,
                        "n_newton": results[-1].n_newton, "n_hessian": results[-1].n_hessian,
                        "first_order_stop": results[-1].first_order_stop},

@@ -192,6 +192,13 @@ int dia_loss_grad64(dia_image R, dia_image I, const dia_objective* obj, const do
 int dia_loss_grad_noalloc(dia_image R, dia_image I, const dia_objective* obj, const float* theta, int32_t m,
                           double* loss, float* grad, void* stream);
 
+/* The tile shape a single-pair call uses for an m x m kernel on a rows x cols
+ * image (host): the autotuner's choice for that kernel size and image-size
+ * class if it has been made in this process (or pinned by DIA_TILE_VARIANT),
+ * else the default shape (variant 0).  variant is the shape's index (see
+ * dia_loss_grad), tile_rows x tile_cols the valid outputs per workgroup. */
+int dia_tile_shape(int32_t m, int32_t rows, int32_t cols, int32_t* variant, int32_t* tile_rows, int32_t* tile_cols);
+
 /* Observed Fisher information (Section 2.5): the Hessian of L at theta,
  *   H[i * n + j] = d2L / dtheta_i dtheta_j,   n = m*m + 1 (m*m + (d+1)(d+2)/2
  * with a polynomial background of degree d),

@@ -90,6 +90,7 @@ _lib.dia_model_bg.argtypes = [_Image, _vp, _i32, _i32, _vp, _i64, _vp]
 _lib.dia_loss_grad.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_loss_grad64.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_loss_grad_noalloc.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _vp]
+_lib.dia_tile_shape.argtypes = [_i32, _i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
 _lib.dia_hessian.argtypes = [_Image, _Image, ctypes.POINTER(_Objective), _vp, _i32, _vp, _vp, _sz, _vp]
 _lib.dia_covariance.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
 _lib.dia_covariance_bg.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
@@ -104,7 +105,7 @@ _lib.dia_loss_grad_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i3
 _lib.dia_fit_batched.argtypes = [_Image, ctypes.POINTER(_Epoch), _i32, _i32, ctypes.POINTER(_Objective),
                                  ctypes.POINTER(_FitOpts), _i32, _vp, ctypes.POINTER(_FitResult), _vp, _sz, _vp]
 for _f in ("dia_workspace_size", "dia_model", "dia_model_bg", "dia_loss_grad", "dia_loss_grad64",
-           "dia_loss_grad_noalloc", "dia_hessian", "dia_covariance_bg", "dia_covariance", "dia_fit",
+           "dia_loss_grad_noalloc", "dia_hessian", "dia_covariance_bg", "dia_tile_shape", "dia_covariance", "dia_fit",
            "dia_batched_workspace_size", "dia_loss_grad_batched", "dia_fit_batched"):
     getattr(_lib, _f).restype = ctypes.c_int
 
@@ -112,7 +113,7 @@ for _f in ("dia_workspace_size", "dia_model", "dia_model_bg", "dia_loss_grad", "
 PREC = {"fp32": 0, "plain": 0, "bf16x3": 1}
 
 EXPORTS = ("dia_version", "dia_status_string", "dia_workspace_size", "dia_model", "dia_model_bg", "dia_loss_grad",
-           "dia_loss_grad64", "dia_loss_grad_noalloc", "dia_hessian", "dia_covariance_bg",
+           "dia_loss_grad64", "dia_loss_grad_noalloc", "dia_hessian", "dia_covariance_bg", "dia_tile_shape",
            "dia_covariance", "dia_fit_opts_default", "dia_fit", "dia_batched_workspace_size",
            "dia_loss_grad_batched", "dia_fit_batched")
 
@@ -278,6 +279,14 @@ def loss_grad64(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, o
     _check(_lib.dia_loss_grad64(Ri, Ii, ctypes.byref(obj), theta.data_ptr(), m, loss.data_ptr(), grad.data_ptr(),
                                 p, nb, _stream(R.device)), "dia_loss_grad64")
     return loss, grad
+
+
+def tile_shape(m: int, rows: int, cols: int):
+    """(variant, tile rows, tile cols) that single-pair calls use for this kernel and image size (the
+    autotuner's choice once made, else the default)."""
+    v, ty, tx = _i32(0), _i32(0), _i32(0)
+    _check(_lib.dia_tile_shape(m, rows, cols, ctypes.byref(v), ctypes.byref(ty), ctypes.byref(tx)), "dia_tile_shape")
+    return v.value, ty.value, tx.value
 
 
 def loss_grad_noalloc(R: torch.Tensor, I: torch.Tensor, theta: torch.Tensor, m: int, objective: Objective,

@@ -319,30 +319,40 @@ struct Autotuner {
             if (it != cache.end() && it->second < n_variants && tile_variant_rb(m, it->second) != 0) return it->second;
         }
         if (!may_time) return 0;
-        // distinct effective shapes (tile height and width) only
+        // distinct effective shapes only: the same tile (height, width) with the same forward rows per
+        // thread is the same kernel (a variant whose requested rows do not fit the LDS budget falls back
+        // to the default's); the two-thread-set shape has the default's tile with other rows per thread
         std::vector<int> cand;
-        std::vector<std::pair<int, int>> seen;
+        std::vector<std::tuple<int, int, int>> seen;
         for (int v = 0; v < n_variants; ++v) {
             int ty = 0, tx = 0;
             if (tile_dims(m, v, &ty, &tx) != 0) continue;
+            const auto key = std::make_tuple(ty, tx, tile_variant_rb(m, v));
             bool dup = false;
-            for (const auto& d : seen) dup |= (d.first == ty && d.second == tx);
+            for (const auto& d : seen) dup |= (d == key);
             if (dup) continue;
-            seen.emplace_back(ty, tx);
+            seen.push_back(key);
             cand.push_back(v);
         }
+        // kRounds rounds over the candidates, each candidate's fastest time kept: the clock drifts while
+        // the candidates run one after another, and interleaving them keeps that drift from picking one
+        constexpr int kRounds = 3;
         int best = 0;
         float best_ms = 1e30f;
         bool all_timed = true;
         if (cand.size() > 1) {
-            for (int v : cand) {
-                const float ms = time_fn(v);
-                all_timed = all_timed && ms >= 0.0f;
-                if (ms >= 0.0f && ms < best_ms) {
-                    best_ms = ms;
-                    best = v;
+            std::vector<float> fastest(cand.size(), 1e30f);
+            for (int r = 0; r < kRounds; ++r)
+                for (size_t i = 0; i < cand.size(); ++i) {
+                    const float ms = time_fn(cand[i]);
+                    all_timed = all_timed && ms >= 0.0f;
+                    if (ms >= 0.0f && ms < fastest[i]) fastest[i] = ms;
                 }
-            }
+            for (size_t i = 0; i < cand.size(); ++i)
+                if (fastest[i] < best_ms) {
+                    best_ms = fastest[i];
+                    best = cand[i];
+                }
         }
         if (!all_timed) return best;
         std::lock_guard<std::mutex> lk(mu);

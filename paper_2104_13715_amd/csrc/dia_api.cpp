@@ -467,6 +467,22 @@ int dia_covariance(const double* F, int32_t m, double* cov, double* sigma, doubl
     return dia_covariance_bg(F, m, 0, cov, sigma, sigma_P, info, ws, ws_bytes, stream);
 }
 
+int dia_tile_shape(int32_t m, int32_t rows, int32_t cols, int32_t* variant, int32_t* tile_rows, int32_t* tile_cols) {
+    if (variant == nullptr || tile_rows == nullptr || tile_cols == nullptr) return DIA_E_ARG;
+    if (rows < 1 || cols < 1) return DIA_E_SIZE;
+    const int c = check_m(m, rows, cols);
+    if (c != DIA_OK) return c;
+    const int sc = size_class((double)(rows - m + 1) * (cols - m + 1));
+    int v = 0;
+    if (!autotuner().settled(m, sc, /*kind=*/0, kNumVariants, &v)) v = 0;
+    int ty = 0, tx = 0;
+    if (tile_dims(m, v, &ty, &tx) != 0) return DIA_E_ARG;
+    *variant = v;
+    *tile_rows = ty;
+    *tile_cols = tx;
+    return DIA_OK;
+}
+
 void dia_fit_opts_default(dia_fit_opts* o) {
     if (o == nullptr) return;
     std::memset(o, 0, sizeof(*o));

@@ -188,3 +188,14 @@ def test_struct_layouts_match_the_header(dia, tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert int(got[f"{cname}.{fname}"]) == getattr(py, fname).offset, (cname, fname)
+
+
+def test_tile_shape_query(dia, monkeypatch):
+    # the default shape before any tuning, and every pinned variant's geometry (m = 19: 13 strips of 8
+    # columns; the wide default has two forward rows per thread, the two-set shape two sets of one row)
+    assert dia.tile_shape(19, 4096, 4096) == (0, 38, 104)
+    for v, ty, tx in ((1, 19, 104), (2, 38, 104), (4, 38, 104), (5, 19, 24)):
+        monkeypatch.setenv("DIA_TILE_VARIANT", str(v))
+        assert dia.tile_shape(19, 4096, 4096) == (v, ty, tx)
+    with pytest.raises(dia.DIAError):
+        dia.tile_shape(18, 100, 100)
