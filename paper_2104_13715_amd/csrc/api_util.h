@@ -214,11 +214,14 @@ inline int resident_blocks(int m, int variant, bool batched) {
     return c;
 }
 
-// Persistent grid for a single pair: as many workgroups as are resident, balanced so
-// every workgroup walks the same number of tiles.
+// Persistent grid for a single pair: as many workgroups as are resident.  One-set shapes are
+// balanced so every workgroup walks the same number of tiles; two-set shapes keep every resident
+// workgroup, since the kernel splits the tiles of a short last round into half tiles (so that no CU
+// holds more than its share of the work, whichever workgroups it runs).
 inline int eval_grid(int m, int ntiles, int variant = 0) {
     const int cap = resident_blocks(m, variant, false);
     if (ntiles <= cap) return ntiles;
+    if (tile_variant_sets(m, variant) == 2) return cap;
     const int waves = (ntiles + cap - 1) / cap;
     return (ntiles + waves - 1) / waves;
 }

@@ -317,6 +317,7 @@ __device__ __forceinline__ float model_variance(const ObjParams& o, float M, flo
 // Launchers for the tiled kernels (tile_kernels.hip).  Return hipError_t.
 constexpr int kNumVariants = 6;  // tile-shape variants: RB = auto, 1, 2, 4; two thread sets of RB = 1; narrow RB = 1
 int tile_variant_rb(int m, int variant);               // effective RB of a variant (0 = not compiled)
+int tile_variant_sets(int m, int variant);             // thread sets of a variant (0 = not compiled)
 int tile_dims(int m, int variant, int* ty, int* tx);   // tile height / width of a variant
 int tile_grid_tiles(int m, int rows, int cols, int variant = 0);  // tiles of the valid region
 hipError_t launch_tile(int mode, int m, int grid, const TileArgs& a, hipStream_t s, int variant = 0);

@@ -66,6 +66,31 @@ int tile_dims(int m, int variant, int* ty, int* tx) {
     return 0;
 }
 
+template <int M>
+static int variant_sets_m(int v) {
+    if (tile_variant_rb(M, v) == 0) return 0;
+    switch (v) {
+        case 0: return Geo<M, 0>::TS;
+        case 1: return Geo<M, 1>::TS;
+        case 2: return Geo<M, 2>::TS;
+        case 3: return Geo<M, 4>::TS;
+        case 4: return Geo<M, 17>::TS;
+        default: return Geo<M, 9>::TS;
+    }
+}
+
+int tile_variant_sets(int m, int variant) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return variant_sets_m<MM>(variant);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return 0;
+    }
+}
+
 int tile_grid_tiles(int m, int rows, int cols, int variant) {
     int ty = 0, tx = 0;
     if (tile_dims(m, variant, &ty, &tx) != 0) return -1;

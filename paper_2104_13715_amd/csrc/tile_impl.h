@@ -86,13 +86,14 @@ __device__ __forceinline__ void stage_tile(const TileArgs& a, int ty0, int tx0, 
 }
 
 // One tile whose reference window is already staged in LDS: forward, per-pixel step, and
-// (MODE_EVAL / MODE_CURV) backward into dk64.
+// (MODE_EVAL / MODE_CURV) backward into dk64.  With two thread sets, nsets = 1 runs a half tile: the
+// first set's rows only, the second set's threads idle.
 // FP32 data (exactly widened), FP64 products and sums: on gfx950 an FP64 FMA issues at the
 // rate of a non-packed FP32 FMA.
 template <int M, int RBV, int MODE, bool POLY = false>
 __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0, int tx0, float* Rs, double* gs,
                                           double (&dk64)[M], double& loss64, double& db064,
-                                          double (&bg)[kMaxBgTerms]) {
+                                          double (&bg)[kMaxBgTerms], int nsets = Geo<M, RBV>::TS) {
     using G = Geo<M, RBV>;
     constexpr int S = G::S, NS = G::NS, RB = G::RB;
     constexpr int TY = G::TY, RS = G::RS, SP = G::SP, GP = G::GP;
@@ -102,7 +103,7 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
     const int tid = threadIdx.x;
     const int q = tid / NS;   // forward: row group; backward: kernel row a
     const int cs = tid % NS;  // column strip
-    const bool active = tid < G::NA;
+    const bool active = tid < G::NA && q / M < nsets;  // q / M: the thread's set
     const int Hv = a.rows - M + 1, Wv = a.cols - M + 1;
 
     if (active) {
@@ -341,11 +342,24 @@ void tile_kernel(TileArgs a) {
 #pragma unroll
     for (int k = 0; k < kMaxBgTerms; ++k) bg[k] = 0.0;
 
-    for (int t = t_begin + mem; t < t_end; t += nmem) {
-        const int ty0 = (t / ntx) * G::TY, tx0 = (t % ntx) * G::TX;
+    // Each member takes every nmem-th tile of its band.  With two thread sets, when the band's last
+    // round leaves at least half of the members idle, its tiles are split into half tiles (the rows of
+    // one set each), so that the round takes about half as long.
+    const int rounds = (t_end - t_begin) / nmem;
+    const int rest = t_end - t_begin - rounds * nmem;
+    const bool halves = G::TS == 2 && 2 * rest <= nmem;
+    const int n_items = rounds + ((halves ? mem < 2 * rest : mem < rest) ? 1 : 0);
+    for (int k = 0; k < n_items; ++k) {
+        int t = t_begin + mem + k * nmem, row_shift = 0, nsets = G::TS;
+        if (k == rounds) {  // the last, partial round
+            t = t_begin + rounds * nmem + (halves ? mem / 2 : mem);
+            row_shift = halves ? (mem % 2) * G::TYS : 0;
+            nsets = halves ? 1 : G::TS;
+        }
+        const int ty0 = (t / ntx) * G::TY + row_shift, tx0 = (t % ntx) * G::TX;
         stage_tile<M, RBV>(a, ty0, tx0, sm.Rs);
         __syncthreads();
-        tile_body<M, RBV, MODE, POLY>(a, B0, ty0, tx0, sm.Rs, sm.gs, dk64, loss64, db064, bg);
+        tile_body<M, RBV, MODE, POLY>(a, B0, ty0, tx0, sm.Rs, sm.gs, dk64, loss64, db064, bg, nsets);
     }
 
     if (MODE == MODE_EVAL || MODE == MODE_CURV) {

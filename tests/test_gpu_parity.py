@@ -206,6 +206,20 @@ def test_loss_grad_pinned_tile_shapes(dia, monkeypatch, m, H, W, variant):
     check_grad(g, g_ref, m, (R, I, theta, o_or))
 
 
+@pytest.mark.parametrize("m,H,W", [(9, 1500, 1500), (19, 1600, 3000), (19, 1700, 3000), (25, 1500, 2000)])
+def test_loss_grad_two_set_shape_more_tiles_than_workgroups(dia, monkeypatch, m, H, W):
+    # the two-thread-set shape with more tiles than resident workgroups: on a 256-CU device the last
+    # round of (9, 1500^2), (19, 1600 x 3000) and (25, 1500 x 2000) is split into half tiles, and that of
+    # (19, 1700 x 3000) is too long to split and runs as whole tiles
+    monkeypatch.setenv("DIA_TILE_VARIANT", "4")
+    R, I, theta, _ = random_problem(300 + m, H, W, m)
+    o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", sigma0=8.0, gain=1.5)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    check_loss(L, L_ref, R, I, theta, m, o_or)
+    check_grad(g, g_ref, m, (R, I, theta, o_or))
+
+
 def test_loss_grad_valid_region_of_one_pixel(dia):
     m = 9
     R, I, theta, _ = random_problem(3, 9, 9, m)
