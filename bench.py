@@ -430,6 +430,25 @@ def main() -> int:
     torch.cuda.synchronize()
     t_gauss = time.time() - gi0
 
+    # accuracy of the timed fit, and of the same schedule without the Newton polish (the Adam -> L-BFGS
+    # point the polish starts from), against the oracle's minimiser of this pair (tests/golden/make_c3_fit.py)
+    fit_err = first_order_err = None
+    gpath = os.path.join(ROOT, "tests", "golden", "c3_chi2_oracle_theta.txt")
+    if args.size == 4096 and os.path.exists(gpath):
+        ref = np.loadtxt(gpath)
+
+        def rel_errors(r):
+            th = r.theta.cpu().double().numpy()
+            Kr = ref[:m * m]
+            return {"K_rel": float(f"{np.linalg.norm(th[:m * m] - Kr) / np.linalg.norm(Kr):.3g}"),
+                    "P_rel": float(f"{abs(r.P - Kr.sum()) / abs(Kr.sum()):.3g}"),
+                    "B0_rel": float(f"{abs(r.B0 - ref[-1]) / max(abs(ref[-1]), 1.0):.3g}")}
+
+        fit_err = rel_errors(results[-1])
+        r1 = dia.fit(R, I, m, obj, workspace=ws, max_newton=0, **fit_kw)
+        first_order_err = dict(rel_errors(r1), n_adam=r1.n_adam, n_lbfgs=r1.n_lbfgs, stop=r1.stop)
+        print(f"# fit error {fit_err}, before the polish {first_order_err}", file=sys.stderr, flush=True)
+
     # the same pair fitted on the exact-Hessian schedule: Adam to a looser switch (1e-4), no L-BFGS phase,
     # then Newton steps (eq. newtonupdate with the exact FP64 Hessian) to convergence, chi-squared and
     # Cauchy, each against the oracle's minimiser (tests/golden/make_c3_fit.py)
@@ -572,6 +591,8 @@ def main() -> int:
         "fused_pass_us": round(1e6 * t_launch, 2),
         "kernel_gtaps": round(taps_per_eval / t_launch / 1e9, 1),
         "fit_stop": results[-1].stop,
+        "fit_error_vs_oracle": fit_err,
+        "first_order_error_vs_oracle": first_order_err,
         "tile_shape": dict(zip(("variant", "rows", "cols"), dia.tile_shape(m, H, W))),
         "fit_counts": {"n_adam": results[-1].n_adam, "n_lbfgs": results[-1].n_lbfgs,
                        "n_newton": results[-1].n_newton, "n_hessian": results[-1].n_hessian,
