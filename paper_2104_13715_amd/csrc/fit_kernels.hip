@@ -224,8 +224,134 @@ __device__ void write_theta(const FitState* st, const double* u, float* theta, i
     __syncthreads();
 }
 
+// Sums over the workgroup of NV per-thread values, each summed in the same order as block_sum
+// (wave sums, then the four wave totals in order); sh holds 4 * NV doubles.
+template <int NV>
+__device__ void block_sums(double (&v)[NV], double* sh) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[wave * NV + k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < kReduceThreads / 64; ++w) s += sh[w * NV + k];
+        v[k] = s;
+    }
+}
+
+// One Adam iteration that does not switch to L-BFGS, in two passes over the vectors and one
+// workgroup reduction: the same arithmetic, in the same order, as the general path (non-finite check,
+// gradient in u, the curvature pair of the last step, the Adam update, the new theta), which would take
+// about eight dependent passes.  Returns false, having changed nothing, when this evaluation ends the
+// Adam phase.
+__device__ bool adam_iteration(const ReduceArgs& ra, double* sh) {
+    FitState* st = ra.st;
+    const FitVecs& v = ra.v;
+    const FitOptsDev& o = ra.o;
+    const int n = ra.n;
+    const double* gt = ra.gt;
+    const double Lt = gt[n], Lprev = st->L;
+    const double rel = fabs(Lprev - Lt) / fmax(fabs(Lprev), 1e-300);
+    if (rel < o.tol_switch || st->n_adam >= o.max_adam) return false;
+    const int nk = st->nk;
+    const double gB = gt[nk], sft = st->ref_shift, c = st->ref_scale, inv_c = 1.0 / c;
+    const int t = st->adam_t + 1;
+    const double bc1 = 1.0 - pow(o.beta1, (double)t);
+    const double bc2 = 1.0 - pow(o.beta2, (double)t);
+    // element i of: the gradient in u, the last step's pair (s, y), and the Adam update
+    auto grad_u = [&](int i) { return i < nk ? (gt[i] - sft * gB) * inv_c : gt[i]; };
+    auto x_new = [&](int i, double gi, double& m1, double& v1) {
+        m1 = o.beta1 * v.m1[i] + (1.0 - o.beta1) * gi;
+        v1 = o.beta2 * v.v1[i] + (1.0 - o.beta2) * gi * gi;
+        const double lr = (i >= nk) ? o.lr_B0 : o.lr_K * c;
+        return v.x[i] - lr * (m1 / bc1) / (sqrt(v1 / bc2) + o.eps);
+    };
+    // pass 1: non-finite flag, s.y, s.s, y.y and the sum of the new kernel values
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+        int bad = 0;
+        for (int i = threadIdx.x; i <= n; i += kReduceThreads) bad |= !isfinite(gt[i]);
+        acc[0] = (double)bad;
+        double sy = 0.0, ss = 0.0, yy = 0.0, ks = 0.0;
+        for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+            const double gi = grad_u(i);
+            const double si = v.x[i] - v.xp[i], yi = gi - v.gp[i];
+            sy += si * yi;
+            ss += si * si;
+            yy += yi * yi;
+        }
+        for (int i = threadIdx.x; i < nk; i += kReduceThreads) {
+            double m1, v1;
+            ks += x_new(i, grad_u(i), m1, v1) / c;
+        }
+        acc[1] = sy, acc[2] = ss, acc[3] = yy, acc[4] = ks;
+    }
+    block_sums(acc, sh);
+    if (acc[0] > 0.0) {
+        finish(st, ra.n_done, STOP_NONE, DIA_E_NONFINITE);
+        return true;
+    }
+    const double sy = acc[1], ss = acc[2], yy = acc[3], ks = acc[4];
+    const bool keep = (sy > 1e-12 * sqrt(ss * yy)) && (sy > 0.0);
+    const int H = o.history, slot = st->hist_head;
+    double* Sd = v.S + (long long)slot * v.ld;
+    double* Yd = v.Y + (long long)slot * v.ld;
+    __syncthreads();  // every thread has read the state it needs before any of it changes
+    // pass 2: the pair into the history, the Adam moments and point, the new theta
+    for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+        const double gi = grad_u(i);
+        const double xi = v.x[i];
+        if (keep) {
+            Sd[i] = xi - v.xp[i];
+            Yd[i] = gi - v.gp[i];
+        }
+        double m1, v1;
+        const double xn = x_new(i, gi, m1, v1);
+        v.m1[i] = m1;
+        v.v1[i] = v1;
+        v.xp[i] = xi;
+        v.gp[i] = gi;
+        v.g[i] = gi;
+        v.x[i] = xn;
+        if (i < nk) {
+            const float kf = (float)(xn / c);
+            v.theta_eval[i] = kf;
+            v.theta_eval64[i] = (double)kf;
+        } else if (i == nk) {
+            const float bf = (float)(xn - sft * ks);
+            v.theta_eval[i] = bf;
+            v.theta_eval64[i] = (double)bf;
+        } else {
+            const float bf = (float)xn;
+            v.theta_eval[i] = bf;
+            v.theta_eval64[i] = (double)bf;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->n_eval += 1;
+        if (keep) {
+            v.rh[slot] = 1.0 / sy;
+            st->hist_head = (slot + 1) % H;
+            st->hist_n = st->hist_n < H ? st->hist_n + 1 : H;
+        }
+        st->L = Lt;
+        st->adam_t = t;
+        st->n_adam += 1;
+    }
+    __syncthreads();
+    if (st->n_eval >= o.max_eval) finish(st, ra.n_done, STOP_CAP, DIA_W_NOT_CONVERGED);
+    return true;
+}
+
 // One optimiser step, run by a single workgroup once the full gradient gt (and loss gt[n]) is known.
 __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
+    if (ra.st->phase == PH_ADAM && adam_iteration(ra, sh)) return;
     FitState* st = ra.st;
     const FitVecs& v = ra.v;
     const FitOptsDev& o = ra.o;
@@ -421,7 +547,7 @@ __device__ __forceinline__ double lap2_apply(const double* t, int u, int m) {
 
 __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
     __shared__ double red[kReducePhases][kReduceCols];
-    __shared__ double sh[16];
+    __shared__ double sh[32];
     __shared__ int last;
     if (ra.done != nullptr && *ra.done != 0) return;
     const int tid = threadIdx.x;
@@ -475,7 +601,7 @@ hipError_t launch_reduce(const ReduceArgs& ra, hipStream_t s) {
 // in fit mode the last workgroup of each epoch runs that epoch's optimiser step.
 __global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchReduceArgs br) {
     __shared__ double red[kReducePhases][kReduceCols];
-    __shared__ double sh[16];
+    __shared__ double sh[32];
     __shared__ int last;
     const int e = blockIdx.y;
     const int tid = threadIdx.x;
