@@ -25,7 +25,7 @@ struct FitOptsDev {
 struct FitState {
     int phase, done, status, stop;
     int n_eval, n_adam, n_lbfgs, ls_iter;
-    int hist_n, hist_head, counter, adam_t;
+    int hist_n, hist_head, adam_t;
     int small_steps;  // consecutive accepted L-BFGS steps with relative change below tol_change
     int nk, n;        // kernel taps (m*m; the scalar background or b_00 sits at index nk) and parameters
     double L;        // loss at the current point (Adam) or the accepted point (L-BFGS)
