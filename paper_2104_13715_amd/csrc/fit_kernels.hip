@@ -275,23 +275,24 @@ __device__ bool adam_iteration(const ReduceArgs& ra, double* sh) {
         return v.x[i] - lr * (m1 / bc1) / (sqrt(v1 / bc2) + o.eps);
     };
     // pass 1: non-finite flag, s.y, s.s, y.y and the sum of the new kernel values
+    // (one loop, so that every load of an element is in flight at once; each sum keeps its element order)
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     {
-        int bad = 0;
-        for (int i = threadIdx.x; i <= n; i += kReduceThreads) bad |= !isfinite(gt[i]);
-        acc[0] = (double)bad;
+        int bad = (threadIdx.x == n % kReduceThreads) ? !isfinite(Lt) : 0;
         double sy = 0.0, ss = 0.0, yy = 0.0, ks = 0.0;
         for (int i = threadIdx.x; i < n; i += kReduceThreads) {
+            bad |= !isfinite(gt[i]);
             const double gi = grad_u(i);
             const double si = v.x[i] - v.xp[i], yi = gi - v.gp[i];
             sy += si * yi;
             ss += si * si;
             yy += yi * yi;
+            if (i < nk) {
+                double m1, v1;
+                ks += x_new(i, gi, m1, v1) / c;
+            }
         }
-        for (int i = threadIdx.x; i < nk; i += kReduceThreads) {
-            double m1, v1;
-            ks += x_new(i, grad_u(i), m1, v1) / c;
-        }
+        acc[0] = (double)bad;
         acc[1] = sy, acc[2] = ss, acc[3] = yy, acc[4] = ks;
     }
     block_sums(acc, sh);
