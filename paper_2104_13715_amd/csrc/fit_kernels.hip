@@ -146,18 +146,38 @@ __device__ void finish(FitState* st, int* n_done, int stop, int status) {
 }
 
 // Start the L-BFGS phase (or a new search direction) from the accepted point x with gradient g.
-__device__ void new_direction(FitState* st, const FitVecs& v, const FitOptsDev& o, int n, double* sh) {
+// lds (or null): room for the history S, Y (H slots of ld each) and the direction d, in which the
+// two-loop recursion then runs: its dot products depend on each other, and read from LDS each costs
+// a fraction of a round trip to L2.  The arithmetic and its order are the same either way.
+__device__ void new_direction(FitState* st, const FitVecs& v, const FitOptsDev& o, int n, double* sh,
+                              double* lds) {
     const int H = o.history;
-    lbfgs_direction(st, v, v.g, n, H, sh);
-    double gtd = dot(v.g, v.d, n, sh);
+    FitVecs w = v;
+    if (lds != nullptr) {
+        const long long hl = (long long)H * v.ld;
+        for (long long k = threadIdx.x; k < hl; k += kReduceThreads) {
+            lds[k] = v.S[k];
+            lds[hl + k] = v.Y[k];
+        }
+        __syncthreads();
+        w.S = lds;
+        w.Y = lds + hl;
+        w.d = lds + 2 * hl;
+    }
+    lbfgs_direction(st, w, v.g, n, H, sh);
+    double gtd = dot(v.g, w.d, n, sh);
     if (!(gtd < 0.0)) {  // not a descent direction: drop the history, use the scaled gradient
         if (threadIdx.x == 0) {
             st->hist_n = 0;
             st->hist_head = 0;
         }
         __syncthreads();
-        lbfgs_direction(st, v, v.g, n, H, sh);
-        gtd = dot(v.g, v.d, n, sh);
+        lbfgs_direction(st, w, v.g, n, H, sh);
+        gtd = dot(v.g, w.d, n, sh);
+    }
+    if (lds != nullptr) {
+        for (int i = threadIdx.x; i < n; i += kReduceThreads) v.d[i] = w.d[i];
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
         st->gtd = gtd;
@@ -353,8 +373,9 @@ __device__ bool adam_iteration(const ReduceArgs& ra, double* sh) {
     return true;
 }
 
-// One optimiser step, run by a single workgroup once the full gradient gt (and loss gt[n]) is known.
-__device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
+// One optimiser step, run by a single workgroup once the full gradient gt (and loss gt[n]) is known
+// (lds: as in new_direction).
+__device__ void optimiser_step(const ReduceArgs& ra, double* sh, double* lds) {
     if (ra.st->phase == PH_ADAM && adam_iteration(ra, sh)) return;
     FitState* st = ra.st;
     const FitVecs& v = ra.v;
@@ -421,7 +442,7 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
                 finish(st, ra.n_done, capped ? STOP_CAP : STOP_CHANGE, capped ? DIA_W_NOT_CONVERGED : DIA_OK);
                 return;
             }
-            new_direction(st, v, o, n, sh);
+            new_direction(st, v, o, n, sh, lds);
         }
     } else if (phase == PH_LSEARCH) {
         const double L0 = st->L;
@@ -470,7 +491,7 @@ __device__ void optimiser_step(const ReduceArgs& ra, double* sh) {
                 finish(st, ra.n_done, STOP_CAP, DIA_W_NOT_CONVERGED);
                 return;
             }
-            new_direction(st, v, o, n, sh);
+            new_direction(st, v, o, n, sh, lds);
         } else {
             // backtrack: minimiser of the quadratic through L0, slope gtd and L0 + dL, kept in [0.1, 0.5] alpha
             const int it = st->ls_iter + 1;
@@ -583,8 +604,29 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_kernel(ReduceArgs ra) {
 // One optimiser step of a single fit on the reduced gradient and loss gt (one workgroup).
 __global__ __launch_bounds__(kReduceThreads) void step_kernel(ReduceArgs ra) {
     __shared__ double sh[32];
+    extern __shared__ double step_lds[];
     if (ra.done != nullptr && *ra.done != 0) return;
-    optimiser_step(ra, sh);
+    optimiser_step(ra, sh, ra.lds_hist ? step_lds : nullptr);
+}
+
+// Dynamic LDS of a step kernel: the L-BFGS history (S and Y, H slots of ld doubles each) and the
+// direction, or 0 when that exceeds what one workgroup may hold (the recursion then reads L2).
+constexpr size_t kStepLdsMax = 144 * 1024;
+size_t step_lds_bytes(int history, int ld) {
+    const size_t b = sizeof(double) * ((size_t)2 * history * ld + ld);
+    return b <= kStepLdsMax ? b : 0;
+}
+
+__global__ void step_batched_kernel(BatchReduceArgs br);
+
+// Raise the step kernels' dynamic-LDS limit once (beyond the default a launch may not ask for more).
+bool step_lds_ready() {
+    static const bool ok =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(step_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kStepLdsMax) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(step_batched_kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStepLdsMax) == hipSuccess;
+    return ok;
 }
 
 hipError_t launch_reduce(const ReduceArgs& ra, hipStream_t s) {
@@ -592,7 +634,10 @@ hipError_t launch_reduce(const ReduceArgs& ra, hipStream_t s) {
     hipLaunchKernelGGL(reduce_kernel, dim3(grid), dim3(kReduceThreads), 0, s, ra);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ra.st == nullptr) return e;
-    hipLaunchKernelGGL(step_kernel, dim3(1), dim3(kReduceThreads), 0, s, ra);
+    ReduceArgs r = ra;
+    const size_t lds = step_lds_ready() ? step_lds_bytes(ra.o.history, ra.v.ld) : 0;
+    r.lds_hist = lds > 0 ? 1 : 0;
+    hipLaunchKernelGGL(step_kernel, dim3(1), dim3(kReduceThreads), lds, s, r);
     return hipGetLastError();
 }
 
@@ -620,6 +665,7 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_batched_kernel(BatchRed
 // The optimiser step of epoch blockIdx.x of a batched fit (one workgroup per epoch).
 __global__ __launch_bounds__(kReduceThreads) void step_batched_kernel(BatchReduceArgs br) {
     __shared__ double sh[32];
+    extern __shared__ double step_lds[];
     const int e = blockIdx.x;
     const long long off = (long long)e * br.stride;
     FitState* st = reinterpret_cast<FitState*>(reinterpret_cast<char*>(br.st) + off);
@@ -641,7 +687,8 @@ __global__ __launch_bounds__(kReduceThreads) void step_batched_kernel(BatchReduc
     ra.n_done = br.n_done;
     ra.reg = 0.0;
     ra.th64 = nullptr;
-    optimiser_step(ra, sh);
+    ra.lds_hist = br.lds_hist;
+    optimiser_step(ra, sh, br.lds_hist ? step_lds : nullptr);
 }
 
 hipError_t launch_reduce_batched(const BatchReduceArgs& ra, int n_epochs, hipStream_t s) {
@@ -649,7 +696,10 @@ hipError_t launch_reduce_batched(const BatchReduceArgs& ra, int n_epochs, hipStr
     hipLaunchKernelGGL(reduce_batched_kernel, dim3(gx, n_epochs), dim3(kReduceThreads), 0, s, ra);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || ra.st == nullptr) return e;
-    hipLaunchKernelGGL(step_batched_kernel, dim3(n_epochs), dim3(kReduceThreads), 0, s, ra);
+    BatchReduceArgs r = ra;
+    const size_t lds = step_lds_ready() ? step_lds_bytes(ra.o.history, ra.v.ld) : 0;
+    r.lds_hist = lds > 0 ? 1 : 0;
+    hipLaunchKernelGGL(step_batched_kernel, dim3(n_epochs), dim3(kReduceThreads), lds, s, r);
     return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct ReduceArgs {
     int* n_done;            // incremented once when the fit finishes (batched polling)
     double reg;             // lambda N_data of the kernel-smoothness penalty (0 = none)
     const double* th64;     // the FP64 parameters the pass evaluated (read when reg > 0)
+    int lds_hist;           // step kernel: its dynamic LDS holds a copy of the L-BFGS history (step_lds_bytes)
 };
 
 // Batched fits: epoch e's FitState, SelectState, vectors and theta_eval sit at byte offset
@@ -94,6 +95,7 @@ struct BatchReduceArgs {
     int n, m;
     int* queue;             // work-queue head of the batched eval kernel, reset here
     int* n_done;
+    int lds_hist;           // as in ReduceArgs
 };
 
 __host__ __device__ inline FitVecs offset_vecs(FitVecs v, long long bytes) {
