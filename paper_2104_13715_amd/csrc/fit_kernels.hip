@@ -9,6 +9,9 @@
 // sums over inside one kernel takes a device-scope fence in every workgroup, and on a device whose L2
 // is split over several XCDs each such fence writes back its XCD's L2 (measured at 36 us per
 // iteration for a 32-epoch batch, against a few us for a kernel boundary).
+#include <map>
+#include <mutex>
+
 #include "fit_state.h"
 
 namespace dia {
@@ -619,13 +622,23 @@ size_t step_lds_bytes(int history, int ld) {
 
 __global__ void step_batched_kernel(BatchReduceArgs br);
 
-// Raise the step kernels' dynamic-LDS limit once (beyond the default a launch may not ask for more).
+// Raise the step kernels' dynamic-LDS limit once per device (beyond the default a launch may not ask
+// for more); false: launch them without the LDS copy.
 bool step_lds_ready() {
-    static const bool ok =
+    static std::mutex mu;
+    static std::map<int, bool> ready;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = ready.find(dev);
+    if (it != ready.end()) return it->second;
+    const bool ok =
         hipFuncSetAttribute(reinterpret_cast<const void*>(step_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)kStepLdsMax) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(step_batched_kernel),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStepLdsMax) == hipSuccess;
+    if (!ok) (void)hipGetLastError();  // a refused attribute is not the launch's error
+    ready[dev] = ok;
     return ok;
 }
 
