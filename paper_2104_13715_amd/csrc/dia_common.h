@@ -245,11 +245,12 @@ __device__ __forceinline__ void pixel_objective_d(const ObjParams& o, double Iv,
     const double X = model ? M : Iv;
     const double Fd = (double)F;
     double raw, slope;
+    // F = 1 (no flat field): the divisions by F are exact, so they are skipped
     if (o.var == DIA_VAR_CCD_DATA || o.var == DIA_VAR_CCD_MODEL) {
-        slope = o.inv_gain / Fd;
-        raw = o.s0sq / (Fd * Fd) + fmax(X, 0.0) * slope;
+        slope = F == 1.0f ? o.inv_gain : o.inv_gain / Fd;
+        raw = (F == 1.0f ? o.s0sq : o.s0sq / (Fd * Fd)) + fmax(X, 0.0) * slope;
     } else {
-        slope = o.excess * o.inv_gain / Fd;
+        slope = F == 1.0f ? o.excess * o.inv_gain : o.excess * o.inv_gain / Fd;
         raw = fmax(X, 0.0) * slope;
     }
     const double v = fmax(raw, o.var_floor);
