@@ -9,6 +9,7 @@
 // sums over inside one kernel takes a device-scope fence in every workgroup, and on a device whose L2
 // is split over several XCDs each such fence writes back its XCD's L2 (measured at 36 us per
 // iteration for a 32-epoch batch, against a few us for a kernel boundary).
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -623,8 +624,11 @@ size_t step_lds_bytes(int history, int ld) {
 __global__ void step_batched_kernel(BatchReduceArgs br);
 
 // Raise the step kernels' dynamic-LDS limit once per device (beyond the default a launch may not ask
-// for more); false: launch them without the LDS copy.
+// for more); false: launch them without the LDS copy.  DIA_STEP_LDS=0 keeps every step on the L2 path
+// (the two paths give bitwise the same results).
 bool step_lds_ready() {
+    const char* e = std::getenv("DIA_STEP_LDS");  // read at every launch (cheap), so a process can switch
+    if (e != nullptr && e[0] == '0') return false;
     static std::mutex mu;
     static std::map<int, bool> ready;
     int dev = 0;

@@ -190,3 +190,23 @@ def test_no_lbfgs_phase_hands_over_to_newton(dia, rho, var):
     assert eK <= 1e-4 and eP <= 1e-4 and eB <= 1e-4, (eK, eP, eB)
     # the Adam phase ended on the switch rule, not on its cap
     assert res.n_adam < 5000
+
+
+def test_step_lds_and_l2_paths_agree_bitwise(dia, monkeypatch):
+    # the step kernels run the L-BFGS two-loop recursion on an LDS copy of the history when it fits
+    # (the default) or on the history in global memory (DIA_STEP_LDS=0, and any history too large for
+    # LDS): the same arithmetic in the same order, so whole fits agree to the bit, single and batched
+    p = sf.config1()
+    o = dia.Objective(rho="cauchy", var="ccd_data", sigma0=p.sigma0_adu, gain=p.gain, c=2.3849)
+    b = sf.batched(40, 4, 9, 256, 600, (120, 200))
+    Rb = gpu(b.R)
+    eps = [dia.Epoch(I=gpu(e.I), ref_row0=e.row0, ref_col0=e.col0) for e in b.epochs]
+    runs = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("DIA_STEP_LDS", flag)
+        r = dia.fit(gpu(p.R), gpu(p.I), p.m, o, max_newton=0)
+        th, res, st = dia.fit_batched(Rb, eps, b.m, o, max_newton=0)
+        runs.append((r.theta.cpu().numpy().tobytes(), th.cpu().numpy().tobytes(), r.n_eval, r.n_lbfgs,
+                     [x.n_lbfgs for x in res]))
+    assert runs[0][3] > 0 and min(runs[0][4]) > 0, "the fits should reach the L-BFGS phase"
+    assert runs[0] == runs[1]
