@@ -318,7 +318,9 @@ typedef struct {
  * if clip_kappa > 0, drop pixels with |I - M_prev| / sigma > clip_kappa
  * (masks accumulate); the loop ends early when the mask stops changing.
  * Optimiser state lives in the workspace; each optimiser step is a captured
- * hipGraph replay with no host synchronisation.  Returns after the work on
+ * hipGraph replay with no host synchronisation (the L-BFGS recursion runs on
+ * an LDS copy of its history where it fits; DIA_STEP_LDS=0 keeps it in global
+ * memory, with bitwise the same results).  Returns after the work on
  * stream has completed.  res (host) may be NULL. */
 int dia_fit(dia_image R, dia_image I, const dia_objective* obj, int32_t m, const dia_fit_opts* opts,
             float* theta, dia_fit_result* res, void* ws, size_t ws_bytes, void* stream);
