@@ -89,9 +89,13 @@ struct Geo {
     // RBV >= 8 asks for the narrow shape (RBV - 8 forward rows per thread): about one wave of column
     // strips per workgroup, so that images too small to fill the chip with wide tiles still do
     static constexpr bool NARROW = RBV >= 8 && RBV < 16;
+    // RBV >= 32: two thread sets of one forward row and RBV - 32 column strips (a short tile of fewer
+    // threads, for images too small to keep the chip busy with the wide two-set shape)
+    static constexpr bool EXPLICIT_NS = RBV >= 32;
     static constexpr int TS = RBV >= 16 ? 2 : 1;         // thread sets
-    static constexpr int RBR = NARROW ? RBV - 8 : (TS == 2 ? RBV - 16 : RBV);
-    static constexpr int NS = NARROW ? ((64 / M) > 1 ? (64 / M) : 1) : ((256 / M) < 32 ? (256 / M) : 32);
+    static constexpr int RBR = EXPLICIT_NS ? 1 : (NARROW ? RBV - 8 : (TS == 2 ? RBV - 16 : RBV));
+    static constexpr int NS = EXPLICIT_NS ? RBV - 32
+                            : (NARROW ? ((64 / M) > 1 ? (64 / M) : 1) : ((256 / M) < 32 ? (256 / M) : 32));
     static constexpr int NA = TS * M * NS;               // active threads
     static constexpr int NT = ((NA + 63) / 64) * 64;     // launched threads (whole waves)
     static constexpr int TX = NS * S;
@@ -107,7 +111,8 @@ struct Geo {
     static constexpr int TYS = M * RB;                   // g rows of one thread set
     static constexpr int RH = TY + M - 1;                // reference tile height
     // waves per SIMD that the LDS allows (160 KB per CU); the kernels are compiled for it
-    static constexpr int WAVES_PER_EU0 = ((160 * 1024) / lds_bytes(RB)) * (NT / 64) / 4;
+    // (rounded up for the explicit-strip shapes, whose workgroups need not divide evenly over the SIMDs)
+    static constexpr int WAVES_PER_EU0 = (((160 * 1024) / lds_bytes(RB)) * (NT / 64) + (EXPLICIT_NS ? 3 : 0)) / 4;
     static constexpr int WAVES_PER_EU = WAVES_PER_EU0 < 1 ? 1 : (WAVES_PER_EU0 > 8 ? 8 : WAVES_PER_EU0);
     // word offset of column c within a reference row / double offset within a g row
     static __host__ __device__ constexpr int rcol(int c) { return (c >> 3) * SP + (c & 7); }
@@ -316,7 +321,8 @@ __device__ __forceinline__ float model_variance(const ObjParams& o, float M, flo
 }
 
 // Launchers for the tiled kernels (tile_kernels.hip).  Return hipError_t.
-constexpr int kNumVariants = 6;  // tile-shape variants: RB = auto, 1, 2, 4; two thread sets of RB = 1; narrow RB = 1
+constexpr int kNumVariants = 7;  // tile-shape variants: RB = auto, 1, 2, 4; two thread sets of RB = 1; narrow RB = 1;
+                                 // two thread sets of a few strips
 int tile_variant_rb(int m, int variant);               // effective RB of a variant (0 = not compiled)
 int tile_variant_sets(int m, int variant);             // thread sets of a variant (0 = not compiled)
 int tile_dims(int m, int variant, int* ty, int* tx);   // tile height / width of a variant

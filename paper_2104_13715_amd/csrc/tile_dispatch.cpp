@@ -21,6 +21,7 @@ static int variant_rb_m(int v) {
         case 2: return Geo<M, 2>::RB;
         case 3: return Geo<M, 4>::RB;
         case 4: return Geo<M, 17>::RB;
+        case 6: return Geo<M, variant_rbv<M>(6)>::RB;
         default: return Geo<M, 9>::RB;
     }
 }
@@ -34,6 +35,7 @@ static void variant_dims_m(int v, int* ty, int* tx) {
         case 2: *ty = Geo<M, 2>::TY, *tx = Geo<M, 2>::TX; break;
         case 3: *ty = Geo<M, 4>::TY, *tx = Geo<M, 4>::TX; break;
         case 4: *ty = Geo<M, 17>::TY, *tx = Geo<M, 17>::TX; break;
+        case 6: *ty = Geo<M, variant_rbv<M>(6)>::TY, *tx = Geo<M, variant_rbv<M>(6)>::TX; break;
         default: *ty = Geo<M, 9>::TY, *tx = Geo<M, 9>::TX; break;
     }
 }
@@ -75,6 +77,7 @@ static int variant_sets_m(int v) {
         case 2: return Geo<M, 2>::TS;
         case 3: return Geo<M, 4>::TS;
         case 4: return Geo<M, 17>::TS;
+        case 6: return Geo<M, variant_rbv<M>(6)>::TS;
         default: return Geo<M, 9>::TS;
     }
 }

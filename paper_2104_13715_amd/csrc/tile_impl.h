@@ -416,12 +416,14 @@ void batched_eval_kernel(BatchedArgs b) {
 }
 
 // ---------------------------------------------------------------------------- per-size entry points
-template <int M, int RBV>
-static int occupancy_for(bool batched) {
+template <int M, int RBV, bool BATCHED>
+static int occupancy_for() {
     int n = 0;
-    hipError_t e = batched
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batched_eval_kernel<M, RBV>, Geo<M, RBV>::NT, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tile_kernel<M, MODE_EVAL, RBV>, Geo<M, RBV>::NT, 0);
+    hipError_t e;
+    if constexpr (BATCHED)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batched_eval_kernel<M, RBV>, Geo<M, RBV>::NT, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, tile_kernel<M, MODE_EVAL, RBV>, Geo<M, RBV>::NT, 0);
     if (e != hipSuccess) return 1;
     return n > 0 ? n : 1;
 }
@@ -470,6 +472,7 @@ hipError_t TileOps<M>::launch(int mode, int grid, const TileArgs& a, hipStream_t
         if (v == 2) return launch_eval_v<M, 2>(grid, a, s);
         if (v == 3) return launch_eval_v<M, 4>(grid, a, s);
         if (v == 4) return launch_eval_v<M, 17>(grid, a, s);
+        if (v == 6) return launch_eval_v<M, variant_rbv<M>(6)>(grid, a, s);
         return launch_eval_v<M, 9>(grid, a, s);
     }
     return hipErrorInvalidValue;
@@ -483,20 +486,30 @@ hipError_t TileOps<M>::launch_batched(int grid, const BatchedArgs& b, hipStream_
         if (v == 2) return launch_bv<M, 2>(grid, b, s);
         if (v == 3) return launch_bv<M, 4>(grid, b, s);
         if (v == 4) return launch_bv<M, 17>(grid, b, s);
-        return launch_bv<M, 9>(grid, b, s);
     }
-    return hipErrorInvalidValue;
+    return hipErrorInvalidValue;  // the batched forms use the wide shapes, variants 0 - 4
 }
 
 template <int M>
 int TileOps<M>::occupancy(int v, bool batched) {
-    if (v == 0) return occupancy_for<M, 0>(batched);
+    if (batched) {
+        if (v == 0) return occupancy_for<M, 0, true>();
+        if constexpr (HasVariants<M>::value) {
+            if (v == 1) return occupancy_for<M, 1, true>();
+            if (v == 2) return occupancy_for<M, 2, true>();
+            if (v == 3) return occupancy_for<M, 4, true>();
+            if (v == 4) return occupancy_for<M, 17, true>();
+        }
+        return 1;
+    }
+    if (v == 0) return occupancy_for<M, 0, false>();
     if constexpr (HasVariants<M>::value) {
-        if (v == 1) return occupancy_for<M, 1>(batched);
-        if (v == 2) return occupancy_for<M, 2>(batched);
-        if (v == 3) return occupancy_for<M, 4>(batched);
-        if (v == 4) return occupancy_for<M, 17>(batched);
-        return occupancy_for<M, 9>(batched);
+        if (v == 1) return occupancy_for<M, 1, false>();
+        if (v == 2) return occupancy_for<M, 2, false>();
+        if (v == 3) return occupancy_for<M, 4, false>();
+        if (v == 4) return occupancy_for<M, 17, false>();
+        if (v == 6) return occupancy_for<M, variant_rbv<M>(6), false>();
+        return occupancy_for<M, 9, false>();
     }
     return 1;
 }

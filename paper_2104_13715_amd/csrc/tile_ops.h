@@ -12,10 +12,19 @@ struct HasVariants {
     static constexpr bool value = (M == 9 || M == 17 || M == 19 || M == 25);
 };
 
-// Variant v -> the Geo parameter: forward rows per thread requested (0 = automatic; variant 3 asks
-// for 4), variant 4 two thread sets of one row, variant 5 the narrow shape with one row.
+// Column strips of variant 6 (two thread sets of one row): whole waves mostly full (2 waves at
+// m = 9, 5 at m = 17 ... 25), tiles narrow enough that a small image still has a few hundred.
+template <int M>
+struct ShortStrips {
+    static constexpr int value = M == 9 ? 7 : (M == 17 ? 9 : (M == 19 ? 8 : (M == 25 ? 6 : 8)));
+};
+
+// Variant v -> the Geo parameter for kernel size M: forward rows per thread requested (0 = automatic;
+// variant 3 asks for 4), variant 4 two thread sets of one row, variant 5 the narrow shape with one
+// row, variant 6 two thread sets of ShortStrips<M> strips.
+template <int M>
 constexpr int variant_rbv(int v) {
-    return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : (v == 4 ? 17 : (v == 5 ? 9 : 0))));
+    return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : (v == 4 ? 17 : (v == 5 ? 9 : (v == 6 ? 32 + ShortStrips<M>::value : 0)))));
 }
 
 template <int M>

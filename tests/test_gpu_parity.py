@@ -193,7 +193,7 @@ def test_loss_grad_kernel_sizes_and_ragged_tiles(dia, m, H, W):
     check_grad(g, g_ref, m, (R, I, theta, o_or))
 
 
-@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5"])
+@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5", "6"])
 @pytest.mark.parametrize("m,H,W", [(9, 130, 301), (17, 200, 170), (19, 300, 250), (25, 170, 151)])
 def test_loss_grad_pinned_tile_shapes(dia, monkeypatch, m, H, W, variant):
     # every compiled tile shape
@@ -206,12 +206,14 @@ def test_loss_grad_pinned_tile_shapes(dia, monkeypatch, m, H, W, variant):
     check_grad(g, g_ref, m, (R, I, theta, o_or))
 
 
-@pytest.mark.parametrize("m,H,W", [(9, 1500, 1500), (19, 1600, 3000), (19, 1700, 3000), (25, 1500, 2000)])
-def test_loss_grad_two_set_shape_more_tiles_than_workgroups(dia, monkeypatch, m, H, W):
-    # the two-thread-set shape with more tiles than resident workgroups: on a 256-CU device the last
-    # round of (9, 1500^2), (19, 1600 x 3000) and (25, 1500 x 2000) is split into half tiles, and that of
-    # (19, 1700 x 3000) is too long to split and runs as whole tiles
-    monkeypatch.setenv("DIA_TILE_VARIANT", "4")
+@pytest.mark.parametrize("variant,m,H,W", [("4", 9, 1500, 1500), ("4", 19, 1600, 3000), ("4", 19, 1700, 3000),
+                                           ("4", 25, 1500, 2000), ("6", 9, 1500, 1500), ("6", 17, 1500, 1500),
+                                           ("6", 19, 1800, 1800), ("6", 25, 1400, 2000)])
+def test_loss_grad_two_set_shape_more_tiles_than_workgroups(dia, monkeypatch, variant, m, H, W):
+    # the two-thread-set shapes with more tiles than resident workgroups: on a 256-CU device the last
+    # round is split into half tiles for every case but (19, 1700 x 3000) of the wide shape (4) and
+    # (19, 1800^2) of the short one (6), whose last rounds are too long to split and run as whole tiles
+    monkeypatch.setenv("DIA_TILE_VARIANT", variant)
     R, I, theta, _ = random_problem(300 + m, H, W, m)
     o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", sigma0=8.0, gain=1.5)
     L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
@@ -327,10 +329,11 @@ def test_fit_config1_chi2(dia, c1, init):
     assert abs(res.P - ref[:p.m ** 2].sum()) <= 1e-4 * abs(ref[:p.m ** 2].sum())
 
 
-@pytest.mark.parametrize("variant", ["0", "4", "5"])
+@pytest.mark.parametrize("variant", ["0", "4", "5", "6"])
 def test_fit_config1_pinned_tile_shape(dia, c1, monkeypatch, variant):
-    # the wide default, the two-thread-set shape and the narrow shape chosen for small images (19 x 24
-    # outputs per workgroup at m = 9 ... 25) drive the whole fit, Newton polish included
+    # the wide default, the two-thread-set shape, the narrow shape (19 x 24 outputs per workgroup at
+    # m = 9 ... 25) and the short two-set shape, both for small images, drive the whole fit, Newton
+    # polish included
     monkeypatch.setenv("DIA_TILE_VARIANT", variant)
     p = c1
     o_or, o_gpu = to_objs(dia, "huber", "ccd_model", p.sigma0_adu, p.gain)
