@@ -79,6 +79,23 @@ def oracle_golden(name, b, np):
     return out
 
 
+def emccd_golden(b, np):
+    """The oracle's minimisers for the targets of the many-small-pairs batch
+    (tests/golden/make_emccd_oracle.py: 482^2, m = 19, lambda 0 and 1), as ({target: theta},
+    {target: theta at lambda = 1}), keeping only targets whose image sums match the stored ones."""
+    path = os.path.join(ROOT, "tests", "golden", "emccd_oracle_thetas.npz")
+    if not os.path.exists(path):
+        return {}, {}
+    z = np.load(path)
+    if int(z["size"]) != b.R.shape[0]:
+        return {}, {}
+    g0, g1 = {}, {}
+    for k, sm in enumerate(z["target_sum"]):
+        if k < len(b.epochs) and float(np.sum(b.epochs[k].I, dtype=np.float64)) == float(sm):
+            g0[k], g1[k] = z["theta"][k], z["theta_lam1"][k]
+    return g0, g1
+
+
 def fit_errors(theta, res, gold, m, np):
     """Per-fit error against the oracle's minimiser for the epochs in gold: ||dK||/||K||, |dP|/|P| (P of
     the fit's FP64 iterate), |dB0|/max(|B0|, 1); max and median over those epochs."""
@@ -196,6 +213,8 @@ def emccd_section(args, b, dia, torch, dev, np):
     # the Gaussian start's standard deviation from the FWHM difference sqrt(phi_I^2 - phi_R^2)
     phi_K = np.sqrt(np.maximum(phi_I ** 2 - b.meta["phi_R"] ** 2, 0.25)) / sf_fwhm_per_sigma()
     ws = dia.Workspace(dev)
+    gold0, gold1 = emccd_golden(b, np)
+    gold_m = 19
     out = {"workload": (f"{len(b.epochs)} targets of one {full}x{full} field (2000 stars, Gaussian PSF of FWHM "
                         f"{b.meta['phi_R']}) and the shared flat, Huber loss with EMCCD model variance "
                         f"(E = {b.meta['excess']}, G = {b.gain})"), "cases": []}
@@ -211,11 +230,13 @@ def emccd_section(args, b, dia, torch, dev, np):
                              lam=args.emccd_lambda)
         for m in [int(x) for x in args.emccd_m.split(",")]:
             case = {"size": size, "m": m}
+            # errors against the oracle's minimisers where they exist (the full field at m = 19)
+            g0, g1 = (gold0, gold1) if size == full and m == gold_m else ({}, {})
             dia.fit(R, Is[0], m, obj, workspace=ws)  # warm the tile-shape choice and the workspace
             torch.cuda.synchronize()
             if args.emccd_lambda > 0:
                 # the Laplacian-regularised (MAP) fit of Section 2.7 from the box-car start
-                t_ms, n_ev, knorm = [], [], []
+                t_ms, n_ev, knorm, rs = [], [], [], []
                 for k, I in enumerate(Is):
                     a, z = ev()
                     a.record()
@@ -225,12 +246,16 @@ def emccd_section(args, b, dia, torch, dev, np):
                     t_ms.append(a.elapsed_time(z))
                     n_ev.append(r.n_eval)
                     knorm.append(float(r.theta[:m * m].norm()))
+                    rs.append(r)
                 case["single_flat_lambda"] = {"lambda": args.emccd_lambda, "median_ms": round(_pct(t_ms, 50), 2),
                                               "p16_ms": round(_pct(t_ms, 16), 2), "p84_ms": round(_pct(t_ms, 84), 2),
                                               "evals_median": int(_pct(n_ev, 50)),
                                               "kernel_norm_median": round(_pct(knorm, 50), 4)}
+                if args.emccd_lambda == 1.0 and g1:
+                    case["single_flat_lambda"]["error_vs_oracle"] = fit_errors(
+                        torch.stack([r.theta for r in rs]), rs, g1, m, np)
             for init in ("flat", "gauss"):
-                t_ms, n_ev, knorm = [], [], []
+                t_ms, n_ev, knorm, rs = [], [], [], []
                 for k, I in enumerate(Is):
                     a, z = ev()
                     a.record()
@@ -240,12 +265,16 @@ def emccd_section(args, b, dia, torch, dev, np):
                     t_ms.append(a.elapsed_time(z))
                     n_ev.append(r.n_eval)
                     knorm.append(float(r.theta[:m * m].norm()))
+                    rs.append(r)
                 rho_s = spearmanr(t_ms, phi_I).statistic
                 case[f"single_{init}"] = {"median_ms": round(_pct(t_ms, 50), 2), "p16_ms": round(_pct(t_ms, 16), 2),
                                           "p84_ms": round(_pct(t_ms, 84), 2),
                                           "evals_median": int(_pct(n_ev, 50)), "evals_p16": int(_pct(n_ev, 16)),
                                           "evals_p84": int(_pct(n_ev, 84)), "spearman_time_phi_I": round(float(rho_s), 2),
                                           "kernel_norm_median": round(_pct(knorm, 50), 4)}
+                if g0:
+                    case[f"single_{init}"]["error_vs_oracle"] = fit_errors(torch.stack([r.theta for r in rs]), rs,
+                                                                           g0, m, np)
             eps = [dia.Epoch(I=I, flat=Fc) for I in Is]
             n = len(eps)
             yy, xx = np.mgrid[:m, :m] - (m - 1) / 2.0
@@ -270,6 +299,8 @@ def emccd_section(args, b, dia, torch, dev, np):
                     case[f"batched_{prec}_{init}"] = {"fits_per_s": round(n / t, 1), "fit_s": round(t, 3),
                                                       "evals_median": int(_pct(e_, 50)), "evals_max": int(max(e_)),
                                                       "status": st, "stops": stops}
+                    if g0:
+                        case[f"batched_{prec}_{init}"]["error_vs_oracle"] = fit_errors(th, res, g0, m, np)
             out["cases"].append(case)
             print(f"# emccd {case}", file=sys.stderr, flush=True)
     return out

@@ -323,14 +323,15 @@ struct Autotuner {
         }
         if (!may_time) return 0;
         // distinct effective shapes only: the same tile (height, width) with the same forward rows per
-        // thread is the same kernel (a variant whose requested rows do not fit the LDS budget falls back
-        // to the default's); the two-thread-set shape has the default's tile with other rows per thread
+        // thread and threads per workgroup is the same kernel (a variant whose requested rows do not fit
+        // the LDS budget falls back to the default's); the two-thread-set shape has the default's tile
+        // with other rows per thread, the split-kernel-row shapes twice the threads of a one-row tile
         std::vector<int> cand;
-        std::vector<std::tuple<int, int, int>> seen;
+        std::vector<std::tuple<int, int, int, int>> seen;
         for (int v = 0; v < n_variants; ++v) {
             int ty = 0, tx = 0;
             if (tile_dims(m, v, &ty, &tx) != 0) continue;
-            const auto key = std::make_tuple(ty, tx, tile_variant_rb(m, v));
+            const auto key = std::make_tuple(ty, tx, tile_variant_rb(m, v), tile_variant_threads(m, v));
             bool dup = false;
             for (const auto& d : seen) dup |= (d == key);
             if (dup) continue;

@@ -90,13 +90,20 @@ struct Geo {
     // strips per workgroup, so that images too small to fill the chip with wide tiles still do
     static constexpr bool NARROW = RBV >= 8 && RBV < 16;
     // RBV >= 32: two thread sets of one forward row and RBV - 32 column strips (a short tile of fewer
-    // threads, for images too small to keep the chip busy with the wide two-set shape)
+    // threads, for images too small to keep the chip busy with the wide two-set shape).
+    // RBV >= 64: one forward row and RBV - 64 column strips, with the kernel rows split over two halves
+    // of the threads (KS = 2): each half forms the forward sums over its kernel rows and correlates
+    // its half of the g rows, so a thread does half the work of the unsplit shape (for small images,
+    // whose passes are bound by the latency of one tile)
     static constexpr bool EXPLICIT_NS = RBV >= 32;
-    static constexpr int TS = RBV >= 16 ? 2 : 1;         // thread sets
+    static constexpr bool KSPLIT = RBV >= 64;
+    static constexpr int KS = KSPLIT ? 2 : 1;            // kernel-row halves
+    static constexpr int TS = (RBV >= 16 && !KSPLIT) ? 2 : 1;  // thread sets
     static constexpr int RBR = EXPLICIT_NS ? 1 : (NARROW ? RBV - 8 : (TS == 2 ? RBV - 16 : RBV));
-    static constexpr int NS = EXPLICIT_NS ? RBV - 32
+    static constexpr int NS = EXPLICIT_NS ? RBV - (KSPLIT ? 64 : 32)
                             : (NARROW ? ((64 / M) > 1 ? (64 / M) : 1) : ((256 / M) < 32 ? (256 / M) : 32));
-    static constexpr int NA = TS * M * NS;               // active threads
+    static constexpr int KA0 = (M + 1) / 2;              // kernel rows of the first half (KS = 2)
+    static constexpr int NA = KS * TS * M * NS;          // active threads
     static constexpr int NT = ((NA + 63) / 64) * 64;     // launched threads (whole waves)
     static constexpr int TX = NS * S;
     static constexpr int RW = TX + M - 1;                // reference tile width (columns)
@@ -113,7 +120,9 @@ struct Geo {
     // waves per SIMD that the LDS allows (160 KB per CU); the kernels are compiled for it
     // (rounded up for the explicit-strip shapes, whose workgroups need not divide evenly over the SIMDs)
     static constexpr int WAVES_PER_EU0 = (((160 * 1024) / lds_bytes(RB)) * (NT / 64) + (EXPLICIT_NS ? 3 : 0)) / 4;
-    static constexpr int WAVES_PER_EU = WAVES_PER_EU0 < 1 ? 1 : (WAVES_PER_EU0 > 8 ? 8 : WAVES_PER_EU0);
+    // (at most 4 for the explicit-strip shapes: their loops need about 128 registers)
+    static constexpr int WAVES_PER_EU1 = EXPLICIT_NS && WAVES_PER_EU0 > (KSPLIT ? 3 : 4) ? (KSPLIT ? 3 : 4) : WAVES_PER_EU0;
+    static constexpr int WAVES_PER_EU = WAVES_PER_EU1 < 1 ? 1 : (WAVES_PER_EU1 > 8 ? 8 : WAVES_PER_EU1);
     // word offset of column c within a reference row / double offset within a g row
     static __host__ __device__ constexpr int rcol(int c) { return (c >> 3) * SP + (c & 7); }
     static __host__ __device__ constexpr int gcol(int c) { return (c >> 3) * GP + (c & 7); }
@@ -321,10 +330,11 @@ __device__ __forceinline__ float model_variance(const ObjParams& o, float M, flo
 }
 
 // Launchers for the tiled kernels (tile_kernels.hip).  Return hipError_t.
-constexpr int kNumVariants = 7;  // tile-shape variants: RB = auto, 1, 2, 4; two thread sets of RB = 1; narrow RB = 1;
-                                 // two thread sets of a few strips
+constexpr int kNumVariants = 9;  // tile-shape variants: RB = auto, 1, 2, 4; two thread sets of RB = 1; narrow RB = 1;
+                                 // two thread sets of a few strips; kernel rows split, a few strips / narrow
 int tile_variant_rb(int m, int variant);               // effective RB of a variant (0 = not compiled)
 int tile_variant_sets(int m, int variant);             // thread sets of a variant (0 = not compiled)
+int tile_variant_threads(int m, int variant);          // threads per workgroup of a variant (0 = not compiled)
 int tile_dims(int m, int variant, int* ty, int* tx);   // tile height / width of a variant
 int tile_grid_tiles(int m, int rows, int cols, int variant = 0);  // tiles of the valid region
 hipError_t launch_tile(int mode, int m, int grid, const TileArgs& a, hipStream_t s, int variant = 0);

@@ -22,6 +22,8 @@ static int variant_rb_m(int v) {
         case 3: return Geo<M, 4>::RB;
         case 4: return Geo<M, 17>::RB;
         case 6: return Geo<M, variant_rbv<M>(6)>::RB;
+        case 7: return Geo<M, variant_rbv<M>(7)>::RB;
+        case 8: return Geo<M, variant_rbv<M>(8)>::RB;
         default: return Geo<M, 9>::RB;
     }
 }
@@ -36,6 +38,8 @@ static void variant_dims_m(int v, int* ty, int* tx) {
         case 3: *ty = Geo<M, 4>::TY, *tx = Geo<M, 4>::TX; break;
         case 4: *ty = Geo<M, 17>::TY, *tx = Geo<M, 17>::TX; break;
         case 6: *ty = Geo<M, variant_rbv<M>(6)>::TY, *tx = Geo<M, variant_rbv<M>(6)>::TX; break;
+        case 7: *ty = Geo<M, variant_rbv<M>(7)>::TY, *tx = Geo<M, variant_rbv<M>(7)>::TX; break;
+        case 8: *ty = Geo<M, variant_rbv<M>(8)>::TY, *tx = Geo<M, variant_rbv<M>(8)>::TX; break;
         default: *ty = Geo<M, 9>::TY, *tx = Geo<M, 9>::TX; break;
     }
 }
@@ -78,6 +82,8 @@ static int variant_sets_m(int v) {
         case 3: return Geo<M, 4>::TS;
         case 4: return Geo<M, 17>::TS;
         case 6: return Geo<M, variant_rbv<M>(6)>::TS;
+        case 7: return Geo<M, variant_rbv<M>(7)>::TS;
+        case 8: return Geo<M, variant_rbv<M>(8)>::TS;
         default: return Geo<M, 9>::TS;
     }
 }
@@ -87,6 +93,34 @@ int tile_variant_sets(int m, int variant) {
 #define X(MM) \
     case MM:  \
         return variant_sets_m<MM>(variant);
+        DIA_FOR_EACH_M(X)
+#undef X
+        default:
+            return 0;
+    }
+}
+
+template <int M>
+static int variant_threads_m(int v) {
+    if (tile_variant_rb(M, v) == 0) return 0;
+    switch (v) {
+        case 0: return Geo<M, 0>::NT;
+        case 1: return Geo<M, 1>::NT;
+        case 2: return Geo<M, 2>::NT;
+        case 3: return Geo<M, 4>::NT;
+        case 4: return Geo<M, 17>::NT;
+        case 6: return Geo<M, variant_rbv<M>(6)>::NT;
+        case 7: return Geo<M, variant_rbv<M>(7)>::NT;
+        case 8: return Geo<M, variant_rbv<M>(8)>::NT;
+        default: return Geo<M, 9>::NT;
+    }
+}
+
+int tile_variant_threads(int m, int variant) {
+    switch (m) {
+#define X(MM) \
+    case MM:  \
+        return variant_threads_m<MM>(variant);
         DIA_FOR_EACH_M(X)
 #undef X
         default:

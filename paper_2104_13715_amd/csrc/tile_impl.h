@@ -85,9 +85,88 @@ __device__ __forceinline__ void stage_tile(const TileArgs& a, int ty0, int tx0, 
     }
 }
 
+// 3. The per-pixel step on a thread's RB x 8 model values: the objective's l and g = dl/dM (FP64
+// running sums of l and g, g into the LDS tile), the curvature, the model image or the clip test.
+template <int M, int RBV, int MODE, bool POLY>
+__device__ __forceinline__ void tile_pixels(const TileArgs& a, const double (&acc)[Geo<M, RBV>::RB][Geo<M, RBV>::S],
+                                            int q, int cs, int ty0, int tx0, double* gs, double& loss64,
+                                            double& db064, double (&bg)[kMaxBgTerms]) {
+    using G = Geo<M, RBV>;
+    constexpr int S = G::S, RB = G::RB, GS = G::GS, GP = G::GP;
+    constexpr int H = (M - 1) / 2;
+    const int Hv = a.rows - M + 1, Wv = a.cols - M + 1;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int ly = q * RB + i;
+        const int oy = ty0 + ly;
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+            const int lx = cs * S + j;
+            const int ox = tx0 + lx;
+            const bool valid = (oy < Hv) && (ox < Wv);
+            const long long pix = (long long)(oy + H) * a.ldI + (ox + H);
+            if (MODE == MODE_MODEL) {
+                if (valid) a.out[(long long)oy * a.ld_out + ox] = (float)acc[i][j];
+            } else if (MODE == MODE_EVAL) {
+                double g = 0.0;
+                if (valid) {
+                    const bool use = (a.obj.mask == nullptr) || (a.obj.mask[pix] != 0);
+                    if (use) {
+                        const float w = a.obj.weights ? a.obj.weights[pix] : 1.0f;
+                        const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
+                        double l;
+                        pixel_objective_d(a.obj, (double)a.I[pix], acc[i][j], w, F, l, g);
+                        loss64 += l;
+                        if constexpr (POLY)
+                            bg_accumulate(bg, g, a.eta0 + (double)ox * a.deta, a.xi0 + (double)oy * a.dxi,
+                                          a.bg_deg);
+                        else
+                            db064 += g;
+                    }
+                }
+                gs[ly * GS + cs * GP + j] = g;
+            } else if (MODE == MODE_CURV) {
+                double hh = 0.0;
+                if (valid) {
+                    const bool use = (a.obj.mask == nullptr) || (a.obj.mask[pix] != 0);
+                    if (use) {
+                        const float w = a.obj.weights ? a.obj.weights[pix] : 1.0f;
+                        const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
+                        hh = pixel_curvature_d(a.obj, (double)a.I[pix], acc[i][j], w, F, a.curv_exact != 0);
+                    }
+                    if constexpr (POLY) {
+                        if (a.curv_a == 0 && a.curv_b == 0) a.h_out[(long long)oy * Wv + ox] = hh;
+                        const double eta = a.eta0 + (double)ox * a.deta, xi = a.xi0 + (double)oy * a.dxi;
+                        hh *= ipow(eta, a.curv_a) * ipow(xi, a.curv_b);
+                        bg_accumulate(bg, hh, eta, xi, a.bg_deg);
+                    } else {
+                        a.h_out[(long long)oy * Wv + ox] = hh;
+                        db064 += hh;
+                    }
+                }
+                gs[ly * GS + cs * GP + j] = hh;
+            } else {  // MODE_CLIP
+                if (valid) {
+                    const uint8_t old = a.obj.mask ? a.obj.mask[pix] : (uint8_t)1;
+                    const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
+                    const float Mf = (float)acc[i][j];
+                    const float v = model_variance(a.obj, Mf, F);
+                    const float z = (float)((double)a.I[pix] - acc[i][j]) / sqrtf(v);
+                    const uint8_t keep = (a.kappa > 0.0f && fabsf(z) > a.kappa) ? (uint8_t)0 : old;
+                    a.w_out[pix] = 1.0f / v;
+                    a.mask_out[pix] = keep;
+                    if (old && !keep) atomicAdd(a.clip_count, 1);
+                }
+            }
+        }
+    }
+}
+
 // One tile whose reference window is already staged in LDS: forward, per-pixel step, and
 // (MODE_EVAL / MODE_CURV) backward into dk64.  With two thread sets, nsets = 1 runs a half tile: the
-// first set's rows only, the second set's threads idle.
+// first set's rows only, the second set's threads idle.  With the kernel rows split (KS = 2), the
+// second half of the threads hands its forward sums to the first through the g tile; the first half
+// runs the per-pixel step; each half correlates its own g rows in the backward pass.
 // FP32 data (exactly widened), FP64 products and sums: on gfx950 an FP64 FMA issues at the
 // rate of a non-packed FP32 FMA.
 template <int M, int RBV, int MODE, bool POLY = false>
@@ -96,18 +175,21 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                                           double (&bg)[kMaxBgTerms], int nsets = Geo<M, RBV>::TS) {
     using G = Geo<M, RBV>;
     constexpr int S = G::S, NS = G::NS, RB = G::RB;
-    constexpr int TY = G::TY, RS = G::RS, SP = G::SP, GP = G::GP;
+    constexpr int RS = G::RS, SP = G::SP, GP = G::GP;
     constexpr int GS = G::GS;
     constexpr int SEG = S + M - 1;
-    constexpr int H = (M - 1) / 2;
     const int tid = threadIdx.x;
-    const int q = tid / NS;   // forward: row group; backward: kernel row a
-    const int cs = tid % NS;  // column strip
+    const int ks = G::KSPLIT ? tid / (M * NS) : 0;  // kernel-row half
+    const int tk = G::KSPLIT ? tid - ks * (M * NS) : tid;
+    const int q = tk / NS;   // forward: row group; backward: kernel row a
+    const int cs = tk % NS;  // column strip
     const bool active = tid < G::NA && q / M < nsets;  // q / M: the thread's set
-    const int Hv = a.rows - M + 1, Wv = a.cols - M + 1;
+    // kernel rows of this thread's forward sums
+    const int klo = G::KSPLIT ? (ks == 0 ? 0 : G::KA0) : 0;
+    const int khi = G::KSPLIT ? (ks == 0 ? G::KA0 : M) : M;
 
+    double acc[RB][S];
     if (active) {
-        double acc[RB][S];
         // 2. forward: acc[i][j] = B0 + sum_{ka,b} K[ka][b] * R[row + i + ka][col + j + b]
 #pragma unroll
         for (int i = 0; i < RB; ++i)
@@ -116,20 +198,20 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                 if constexpr (POLY) {
                     const double xi = a.xi0 + (double)(ty0 + q * RB + i) * a.dxi;
                     const double eta = a.eta0 + (double)(tx0 + cs * S + j) * a.deta;
-                    acc[i][j] = bg_value<M, MODE>(a, eta, xi);
+                    acc[i][j] = ks == 0 ? bg_value<M, MODE>(a, eta, xi) : 0.0;
                 } else {
-                    acc[i][j] = B0;
+                    acc[i][j] = ks == 0 ? B0 : 0.0;
                 }
             }
         const float* rbase = Rs + (q * RB) * RS + cs * SP;
-        for (int r = 0; r < RB + M - 1; ++r) {
+        for (int r = klo; r < khi + RB - 1; ++r) {
             double seg[SEG];
 #pragma unroll
             for (int k = 0; k < SEG; ++k) seg[k] = (double)rbase[r * RS + G::rcol(k)];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 const int ka = r - i;
-                if (ka >= 0 && ka < M) {
+                if (ka >= klo && ka < khi) {
 #pragma unroll
                     for (int b = 0; b < M; ++b) {
                         const double kv = ktap<MODE>(a, ka * M + b);
@@ -139,72 +221,21 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
                 }
             }
         }
-
-        // 3. per-pixel step
+        if constexpr (!G::KSPLIT) tile_pixels<M, RBV, MODE, POLY>(a, acc, q, cs, ty0, tx0, gs, loss64, db064, bg);
+    }
+    if constexpr (G::KSPLIT) {
+        if (active && ks == 1)
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int ly = q * RB + i;
-            const int oy = ty0 + ly;
+            for (int i = 0; i < RB; ++i)
 #pragma unroll
-            for (int j = 0; j < S; ++j) {
-                const int lx = cs * S + j;
-                const int ox = tx0 + lx;
-                const bool valid = (oy < Hv) && (ox < Wv);
-                const long long pix = (long long)(oy + H) * a.ldI + (ox + H);
-                if (MODE == MODE_MODEL) {
-                    if (valid) a.out[(long long)oy * a.ld_out + ox] = (float)acc[i][j];
-                } else if (MODE == MODE_EVAL) {
-                    double g = 0.0;
-                    if (valid) {
-                        const bool use = (a.obj.mask == nullptr) || (a.obj.mask[pix] != 0);
-                        if (use) {
-                            const float w = a.obj.weights ? a.obj.weights[pix] : 1.0f;
-                            const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
-                            double l;
-                            pixel_objective_d(a.obj, (double)a.I[pix], acc[i][j], w, F, l, g);
-                            loss64 += l;
-                            if constexpr (POLY)
-                                bg_accumulate(bg, g, a.eta0 + (double)ox * a.deta, a.xi0 + (double)oy * a.dxi,
-                                              a.bg_deg);
-                            else
-                                db064 += g;
-                        }
-                    }
-                    gs[ly * GS + cs * GP + j] = g;
-                } else if (MODE == MODE_CURV) {
-                    double hh = 0.0;
-                    if (valid) {
-                        const bool use = (a.obj.mask == nullptr) || (a.obj.mask[pix] != 0);
-                        if (use) {
-                            const float w = a.obj.weights ? a.obj.weights[pix] : 1.0f;
-                            const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
-                            hh = pixel_curvature_d(a.obj, (double)a.I[pix], acc[i][j], w, F, a.curv_exact != 0);
-                        }
-                        if constexpr (POLY) {
-                            if (a.curv_a == 0 && a.curv_b == 0) a.h_out[(long long)oy * Wv + ox] = hh;
-                            const double eta = a.eta0 + (double)ox * a.deta, xi = a.xi0 + (double)oy * a.dxi;
-                            hh *= ipow(eta, a.curv_a) * ipow(xi, a.curv_b);
-                            bg_accumulate(bg, hh, eta, xi, a.bg_deg);
-                        } else {
-                            a.h_out[(long long)oy * Wv + ox] = hh;
-                            db064 += hh;
-                        }
-                    }
-                    gs[ly * GS + cs * GP + j] = hh;
-                } else {  // MODE_CLIP
-                    if (valid) {
-                        const uint8_t old = a.obj.mask ? a.obj.mask[pix] : (uint8_t)1;
-                        const float F = a.obj.flat ? a.obj.flat[pix] : 1.0f;
-                        const float Mf = (float)acc[i][j];
-                        const float v = model_variance(a.obj, Mf, F);
-                        const float z = (float)((double)a.I[pix] - acc[i][j]) / sqrtf(v);
-                        const uint8_t keep = (a.kappa > 0.0f && fabsf(z) > a.kappa) ? (uint8_t)0 : old;
-                        a.w_out[pix] = 1.0f / v;
-                        a.mask_out[pix] = keep;
-                        if (old && !keep) atomicAdd(a.clip_count, 1);
-                    }
-                }
-            }
+                for (int j = 0; j < S; ++j) gs[(q * RB + i) * GS + cs * GP + j] = acc[i][j];
+        __syncthreads();
+        if (active && ks == 0) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < S; ++j) acc[i][j] += gs[(q * RB + i) * GS + cs * GP + j];
+            tile_pixels<M, RBV, MODE, POLY>(a, acc, q, cs, ty0, tx0, gs, loss64, db064, bg);
         }
     }
 
@@ -212,12 +243,14 @@ __device__ __forceinline__ void tile_body(const TileArgs& a, double B0, int ty0,
         __syncthreads();
         if (active) {
             // 4. backward: dk[b] += sum_i sum_j g[i][j] * R[i + a][j + b] over this strip, thread q = (set, a)
-            // taking the g rows of its set
+            // taking the g rows of its set (of its half of them with the kernel rows split)
             constexpr int TYS = G::TYS;
             const int set = q / M, ka = q - set * M;
+            const int ilo = G::KSPLIT ? (ks == 0 ? 0 : TYS - TYS / 2) : set * TYS;
+            const int ihi = G::KSPLIT ? (ks == 0 ? TYS - TYS / 2 : TYS) : (set + 1) * TYS;
             const double* gb = gs + cs * GP;
             const float* rbase = Rs + ka * RS + cs * SP;
-            for (int i = set * TYS; i < (set + 1) * TYS; ++i) {
+            for (int i = ilo; i < ihi; ++i) {
                 double gv[S];
 #pragma unroll
                 for (int j = 0; j < S; ++j) gv[j] = gb[i * GS + j];
@@ -256,7 +289,7 @@ __device__ __forceinline__ void write_partials(const double (&dk64)[M], double l
         for (int o = tid; o < M * nbr; o += NT) {
             const int ka = o / nbr, kb = o - ka * nbr;
             double s = 0.0;
-            for (int set = 0; set < G::TS; ++set)
+            for (int set = 0; set < G::TS * G::KS; ++set)  // thread sets, or kernel-row halves
                 for (int c = 0; c < NS; ++c) s += red[kb * NT + (set * M + ka) * NS + c];
             prow[ka * M + b0 + kb] = s;
         }
@@ -473,6 +506,8 @@ hipError_t TileOps<M>::launch(int mode, int grid, const TileArgs& a, hipStream_t
         if (v == 3) return launch_eval_v<M, 4>(grid, a, s);
         if (v == 4) return launch_eval_v<M, 17>(grid, a, s);
         if (v == 6) return launch_eval_v<M, variant_rbv<M>(6)>(grid, a, s);
+        if (v == 7) return launch_eval_v<M, variant_rbv<M>(7)>(grid, a, s);
+        if (v == 8) return launch_eval_v<M, variant_rbv<M>(8)>(grid, a, s);
         return launch_eval_v<M, 9>(grid, a, s);
     }
     return hipErrorInvalidValue;
@@ -509,6 +544,8 @@ int TileOps<M>::occupancy(int v, bool batched) {
         if (v == 3) return occupancy_for<M, 4, false>();
         if (v == 4) return occupancy_for<M, 17, false>();
         if (v == 6) return occupancy_for<M, variant_rbv<M>(6), false>();
+        if (v == 7) return occupancy_for<M, variant_rbv<M>(7), false>();
+        if (v == 8) return occupancy_for<M, variant_rbv<M>(8), false>();
         return occupancy_for<M, 9, false>();
     }
     return 1;

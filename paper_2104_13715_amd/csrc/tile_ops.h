@@ -21,10 +21,19 @@ struct ShortStrips {
 
 // Variant v -> the Geo parameter for kernel size M: forward rows per thread requested (0 = automatic;
 // variant 3 asks for 4), variant 4 two thread sets of one row, variant 5 the narrow shape with one
-// row, variant 6 two thread sets of ShortStrips<M> strips.
+// row, variant 6 two thread sets of ShortStrips<M> strips, variants 7 and 8 one row with the kernel
+// rows split over two halves of the threads, ShortStrips<M> strips or the narrow shape's.
 template <int M>
 constexpr int variant_rbv(int v) {
-    return v == 1 ? 1 : (v == 2 ? 2 : (v == 3 ? 4 : (v == 4 ? 17 : (v == 5 ? 9 : (v == 6 ? 32 + ShortStrips<M>::value : 0)))));
+    return v == 1 ? 1
+         : v == 2 ? 2
+         : v == 3 ? 4
+         : v == 4 ? 17
+         : v == 5 ? 9
+         : v == 6 ? 32 + ShortStrips<M>::value
+         : v == 7 ? 64 + ShortStrips<M>::value
+         : v == 8 ? 64 + ((64 / M) > 1 ? (64 / M) : 1)
+         : 0;
 }
 
 template <int M>

@@ -193,9 +193,9 @@ def test_struct_layouts_match_the_header(dia, tmp_path):
 def test_tile_shape_query(dia, monkeypatch):
     # the default shape before any tuning, and every pinned variant's geometry (m = 19: 13 strips of 8
     # columns; the wide default has two forward rows per thread, the two-set shape two sets of one row,
-    # the short two-set shape 8 strips)
+    # the short two-set shape 8 strips, the split-kernel-row shapes 8 and 3)
     assert dia.tile_shape(19, 4096, 4096) == (0, 38, 104)
-    for v, ty, tx in ((1, 19, 104), (2, 38, 104), (4, 38, 104), (5, 19, 24), (6, 38, 64)):
+    for v, ty, tx in ((1, 19, 104), (2, 38, 104), (4, 38, 104), (5, 19, 24), (6, 38, 64), (7, 19, 64), (8, 19, 24)):
         monkeypatch.setenv("DIA_TILE_VARIANT", str(v))
         assert dia.tile_shape(19, 4096, 4096) == (v, ty, tx)
     with pytest.raises(dia.DIAError):

@@ -193,7 +193,7 @@ def test_loss_grad_kernel_sizes_and_ragged_tiles(dia, m, H, W):
     check_grad(g, g_ref, m, (R, I, theta, o_or))
 
 
-@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5", "6"])
+@pytest.mark.parametrize("variant", ["1", "2", "3", "4", "5", "6", "7", "8"])
 @pytest.mark.parametrize("m,H,W", [(9, 130, 301), (17, 200, 170), (19, 300, 250), (25, 170, 151)])
 def test_loss_grad_pinned_tile_shapes(dia, monkeypatch, m, H, W, variant):
     # every compiled tile shape
@@ -216,6 +216,20 @@ def test_loss_grad_two_set_shape_more_tiles_than_workgroups(dia, monkeypatch, va
     monkeypatch.setenv("DIA_TILE_VARIANT", variant)
     R, I, theta, _ = random_problem(300 + m, H, W, m)
     o_or, o_gpu = to_objs(dia, "gauss", "ccd_data", sigma0=8.0, gain=1.5)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    check_loss(L, L_ref, R, I, theta, m, o_or)
+    check_grad(g, g_ref, m, (R, I, theta, o_or))
+
+
+@pytest.mark.parametrize("variant,m,H,W", [("7", 19, 1500, 1500), ("8", 19, 900, 1100), ("7", 25, 1000, 1300),
+                                           ("8", 17, 700, 1500)])
+def test_loss_grad_split_kernel_rows_more_tiles_than_workgroups(dia, monkeypatch, variant, m, H, W):
+    # the shapes with the kernel rows split over two halves of the threads, each workgroup running
+    # several tiles
+    monkeypatch.setenv("DIA_TILE_VARIANT", variant)
+    R, I, theta, _ = random_problem(400 + m, H, W, m)
+    o_or, o_gpu = to_objs(dia, "cauchy", "ccd_model", sigma0=8.0, gain=1.5)
     L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
     L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
     check_loss(L, L_ref, R, I, theta, m, o_or)
@@ -329,11 +343,11 @@ def test_fit_config1_chi2(dia, c1, init):
     assert abs(res.P - ref[:p.m ** 2].sum()) <= 1e-4 * abs(ref[:p.m ** 2].sum())
 
 
-@pytest.mark.parametrize("variant", ["0", "4", "5", "6"])
+@pytest.mark.parametrize("variant", ["0", "4", "5", "6", "7"])
 def test_fit_config1_pinned_tile_shape(dia, c1, monkeypatch, variant):
     # the wide default, the two-thread-set shape, the narrow shape (19 x 24 outputs per workgroup at
-    # m = 9 ... 25) and the short two-set shape, both for small images, drive the whole fit, Newton
-    # polish included
+    # m = 9 ... 25), the short two-set shape and the split-kernel-row shape, the last three for small
+    # images, drive the whole fit, Newton polish included
     monkeypatch.setenv("DIA_TILE_VARIANT", variant)
     p = c1
     o_or, o_gpu = to_objs(dia, "huber", "ccd_model", p.sigma0_adu, p.gain)
