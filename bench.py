@@ -234,6 +234,7 @@ def emccd_section(args, b, dia, torch, dev, np):
             g0, g1 = (gold0, gold1) if size == full and m == gold_m else ({}, {})
             dia.fit(R, Is[0], m, obj, workspace=ws)  # warm the tile-shape choice and the workspace
             torch.cuda.synchronize()
+            case["tile_shape"] = dict(zip(("variant", "rows", "cols"), dia.tile_shape(m, size, size)))
             if args.emccd_lambda > 0:
                 # the Laplacian-regularised (MAP) fit of Section 2.7 from the box-car start
                 t_ms, n_ev, knorm, rs = [], [], [], []

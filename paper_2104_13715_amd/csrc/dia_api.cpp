@@ -57,11 +57,19 @@ Layout make_layout(int op, int rows, int cols, long long ld, int m) {
 // Tile-shape variant for a single-pair evaluation, timed on the caller's data once per
 // (kernel size, size class); the timing passes write only the workspace's partial rows.
 // s must be a stream this library owns (the timing waits on it).
+// Each timing covers kTuneBurst passes back to back: a small image's pass (tens of us) is then not
+// lost in the launch and event overheads of one.
+constexpr int kTuneBurst = 4;
+
 int choose_variant(const TileArgs& a, int m, hipStream_t s) {
     const int sc = size_class((double)(a.rows - m + 1) * (a.cols - m + 1));
     return autotuner().pick(m, sc, /*kind=*/0, [&](int v) -> float {
         const int grid = eval_grid(m, tile_grid_tiles(m, a.rows, a.cols, v), v);
-        return time_launches(s, [&]() { return launch_tile(MODE_EVAL, m, grid, a, s, v) == hipSuccess; });
+        return time_launches(s, [&]() {
+            for (int k = 0; k < kTuneBurst; ++k)
+                if (launch_tile(MODE_EVAL, m, grid, a, s, v) != hipSuccess) return false;
+            return true;
+        });
     });
 }
 

@@ -357,14 +357,18 @@ void tile_kernel(TileArgs a) {
 
     // Workgroups are dispatched round-robin over the 8 XCDs, so workgroup b runs on
     // XCD b % 8; each XCD gets a contiguous band of tiles (neighbouring tiles share
-    // halo rows in that XCD's L2).
+    // halo rows in that XCD's L2), as many as its share of the workgroups (when the grid is
+    // not a multiple of 8 the first nb % 8 XCDs have one workgroup more; equal bands would then
+    // give some workgroup of the others a second tile while workgroups elsewhere have one).
     const int nb = gridDim.x;
     const int ngrp = nb < 8 ? nb : 8;
     const int grp = blockIdx.x % ngrp;
     const int mem = blockIdx.x / ngrp;
-    const int nmem = (nb - grp + ngrp - 1) / ngrp;
-    const int t_begin = (int)((long long)ntiles * grp / ngrp);
-    const int t_end = (int)((long long)ntiles * (grp + 1) / ngrp);
+    const int q8 = nb / ngrp, r8 = nb - q8 * ngrp;
+    const int nmem = q8 + (grp < r8 ? 1 : 0);
+    const long long w0 = (long long)grp * q8 + (grp < r8 ? grp : r8);  // workgroups of the XCDs before
+    const int t_begin = (int)((long long)ntiles * w0 / nb);
+    const int t_end = (int)((long long)ntiles * (w0 + nmem) / nb);
 
     const double B0 = POLY ? 0.0 : ktap<MODE>(a, M * M);
     double dk64[M];
