@@ -120,7 +120,8 @@ struct Geo {
     // waves per SIMD that the LDS allows (160 KB per CU); the kernels are compiled for it
     // (rounded up for the explicit-strip shapes, whose workgroups need not divide evenly over the SIMDs)
     static constexpr int WAVES_PER_EU0 = (((160 * 1024) / lds_bytes(RB)) * (NT / 64) + (EXPLICIT_NS ? 3 : 0)) / 4;
-    // (at most 4 for the explicit-strip shapes: their loops need about 128 registers)
+    // (at most 4 for the explicit-strip shapes, 3 with the kernel rows split: their loops need about 128
+    // and 168 registers)
     static constexpr int WAVES_PER_EU1 = EXPLICIT_NS && WAVES_PER_EU0 > (KSPLIT ? 3 : 4) ? (KSPLIT ? 3 : 4) : WAVES_PER_EU0;
     static constexpr int WAVES_PER_EU = WAVES_PER_EU1 < 1 ? 1 : (WAVES_PER_EU1 > 8 ? 8 : WAVES_PER_EU1);
     // word offset of column c within a reference row / double offset within a g row
