@@ -13,6 +13,9 @@
 //   4. backward: dL/dK_ab = sum g_ij R_(i+a)(j+b) — thread (a, strip) correlates the
 //      g tile with the same LDS reference tile into m FP64 accumulators that persist
 //      across the workgroup's tiles.
+// The shapes for small images that split the kernel rows (Geo::KSPLIT) give steps 2 and 4 to two
+// halves of the threads: the second half's forward sums reach the first through the g tile, the
+// first half runs step 3, and each half correlates half of the g rows.
 // A workgroup reduces its m*m + nb + 1 sums in a fixed order and writes one row of
 // partials; a separate kernel adds the rows in FP64.  With a polynomial background
 // (POLY, Section 2.6) the forward starts each pixel at B(eta, xi) and the objective step
