@@ -5,7 +5,7 @@
 
 namespace dia {
 
-constexpr int kMaxTheta = DIA_MAX_M * DIA_MAX_M + 1;
+constexpr int kMaxTheta = DIA_MAX_M * DIA_MAX_M + kMaxBgTerms;  // parameters: the taps and the largest background
 
 // reg = lambda N_data adds the smoothness penalty's Hessian 2 reg L L (Section 2.7) to the kernel block;
 // damp scales the diagonal by 1 + damp (Levenberg-Marquardt damping of a numerically singular H).

@@ -176,3 +176,33 @@ def test_polynomial_background_options_are_checked(dia, vb):
     with pytest.raises(dia.DIAError):  # batched fits have the scalar background
         dia.loss_grad_batched(R, [dia.Epoch(I=I)], torch.zeros((1, m * m + 1), device=DEV), m,
                               dia.Objective(bg_degree=1, sigma0=5.0))
+
+
+def test_hessian_and_covariance_at_the_largest_parameter_count(dia):
+    # m = 49 with a degree-1 background: 2401 taps + 3 background terms, beyond m*m + 1, so the
+    # solver's and the inverse's per-parameter arrays must hold the background terms too.  A zero-mean
+    # reference keeps the Fisher information well conditioned (about 1e8 here): a positive one makes
+    # the constant term and the kernel sum nearly collinear.
+    m, d = 49, 1
+    rng = np.random.default_rng(49)
+    R = rng.normal(0.0, 1000.0, (170, 170)).astype(np.float32)
+    K = rng.uniform(0.0, 1.0, (m, m))
+    K /= K.sum()
+    th = np.concatenate([K.ravel(), [5.0, 3.0, -2.0]])
+    M = oracle.model_poly(R, th, m, d)
+    I = R.copy()
+    h = (m - 1) // 2
+    I[h:170 - h, h:170 - h] = M + rng.normal(0.0, 10.0, M.shape)
+    kw = dict(rho="gauss", var="ccd_data", sigma0=10.0, gain=1.0)
+    o_or, o_gpu = oracle.Objective(**kw), dia.Objective(bg_degree=d, **kw)
+    th32 = th.astype(np.float32)
+    F_ref = oracle.hessian_poly(R, I, th32.astype(np.float64), m, o_or, d)
+    H = dia.hessian(gpu(R), gpu(I), gpu(th32), m, o_gpu).cpu().numpy()
+    assert H.shape == (m * m + 3, m * m + 3)
+    assert np.max(np.abs(H - F_ref)) <= 1e-9 * np.abs(F_ref).max()
+    cv = dia.uncertainty(gpu(R), gpu(I), gpu(th32), m, o_gpu)
+    ref = oracle.covariance(F_ref)
+    assert cv.valid == ref["valid"]
+    C = cv.cov.cpu().numpy()
+    cond = np.linalg.cond(F_ref)
+    assert np.max(np.abs(C - ref["cov"])) <= 1e-14 * cond * np.abs(ref["cov"]).max()
