@@ -100,10 +100,9 @@ def test_emccd_single_fit_matches_oracle(dia, case, init):
         check(r, r.theta.cpu().numpy(), refs[k], losses[k], f"single {init} target {k}")
 
 
-@pytest.mark.parametrize("form", ["single_flat", "single_gauss", "batched_fp32", "batched_bf16x3"])
-def test_emccd_full_size_target_matches_oracle(dia, form):
-    # target 0 of the seeded workload at full size (482^2, m = 19) against the oracle's minimiser
-    # (tests/golden/make_emccd_target0.py), in every fit form
+def target0(dia):
+    """Target 0 of the seeded workload at full size (482^2, m = 19), the oracle's minimiser and loss
+    (tests/golden/make_emccd_target0.py), the objective and the device images."""
     import importlib.util
     import os
     here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
@@ -111,12 +110,18 @@ def test_emccd_full_size_target_matches_oracle(dia, form):
     mod = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(mod)
     b, e = mod.target()
-    m = mod.M
     ref = np.loadtxt(os.path.join(here, "emccd_target0_oracle_theta.txt"))
     with open(os.path.join(here, "emccd_target0_oracle_theta.txt")) as f:
         L_ref = float(f.readline().rsplit("loss", 1)[1])
     Fd = gpu(b.meta["flat"])
     o = dia.Objective(rho="huber", var="emccd_model", gain=b.gain, excess=b.meta["excess"], flat=Fd)
+    return b, e, mod.M, ref, L_ref, Fd, o
+
+
+@pytest.mark.parametrize("form", ["single_flat", "single_gauss", "batched_fp32", "batched_bf16x3"])
+def test_emccd_full_size_target_matches_oracle(dia, form):
+    # target 0 against the oracle's minimiser in every fit form
+    b, e, m, ref, L_ref, Fd, o = target0(dia)
     R, I = gpu(b.R), gpu(e.I)
     if form.startswith("single"):
         phi = np.sqrt(b.meta["phi_I"][0] ** 2 - b.meta["phi_R"] ** 2) / sf.FWHM_PER_SIGMA
@@ -126,3 +131,12 @@ def test_emccd_full_size_target_matches_oracle(dia, form):
         theta, res, st = dia.fit_batched(R, [dia.Epoch(I=I, flat=Fd)], m, o, precision=form.split("_")[1])
         r, th = res[0], theta[0].cpu().numpy()
     check(r, th, ref, L_ref, form)
+
+
+@pytest.mark.parametrize("variant", ["5", "6", "7", "8"])
+def test_emccd_full_size_target_single_fit_every_small_image_shape(dia, monkeypatch, variant):
+    # the single-pair fit of target 0 from the box-car start with each shape for small images pinned
+    monkeypatch.setenv("DIA_TILE_VARIANT", variant)
+    b, e, m, ref, L_ref, Fd, o = target0(dia)
+    r = dia.fit(gpu(b.R), gpu(e.I), m, o)
+    check(r, r.theta.cpu().numpy(), ref, L_ref, f"single flat, tile shape {variant}")

@@ -236,6 +236,23 @@ def test_loss_grad_split_kernel_rows_more_tiles_than_workgroups(dia, monkeypatch
     check_grad(g, g_ref, m, (R, I, theta, o_or))
 
 
+@pytest.mark.parametrize("variant", ["5", "7", "8"])
+@pytest.mark.parametrize("rho,var", [("huber", "emccd_model"), ("gauss", "emccd_data"), ("cauchy", "ccd_data")])
+@pytest.mark.parametrize("m,H,W", [(19, 300, 250), (25, 170, 151)])
+def test_loss_grad_small_image_shapes_with_flat_and_mask(dia, monkeypatch, variant, rho, var, m, H, W):
+    # the shapes for small images (narrow, split-kernel-row) on the many-small-pairs objectives, with a
+    # flat field and a mask
+    monkeypatch.setenv("DIA_TILE_VARIANT", variant)
+    R, I, theta, rng = random_problem(500 + m, H, W, m)
+    flat = rng.uniform(0.8, 1.2, (H, W)).astype(np.float32)
+    mask = (rng.uniform(size=(H, W)) > 0.1).astype(np.uint8)
+    o_or, o_gpu = to_objs(dia, rho, var, sigma0=6.0, gain=1.5, flat=flat, mask=mask)
+    L, g = run_loss_grad(dia, R, I, theta, m, o_gpu)
+    L_ref, g_ref = oracle.loss_grad(R, I, theta, m, o_or)
+    check_loss(L, L_ref, R, I, theta, m, o_or)
+    check_grad(g, g_ref, m, (R, I, theta, o_or))
+
+
 def test_loss_grad_valid_region_of_one_pixel(dia):
     m = 9
     R, I, theta, _ = random_problem(3, 9, 9, m)
