@@ -137,8 +137,14 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
     if (!read_back(&L, gt + n, sizeof(double), s)) return DIA_E_HIP;
     if (!std::isfinite(L)) return DIA_E_NONFINITE;
     int form0 = quadratic ? 1 : 0;  // the first Hessian form to try; later steps start at the last that factored
+    // Chord steps: a quadratic loss keeps its first factor throughout (its Hessian is constant).  For
+    // the others, after a full step (alpha = 1) the next step reuses the factor of the point before;
+    // a reused factor is kept while its full steps shrink the decrement at least fourfold each, and
+    // is replaced by a fresh one as soon as a step falls short of that.
+    bool reuse_next = false;
+    double dec_prev = 0.0;
     for (int it = 0; it < max_steps; ++it) {
-        const bool factor = (it == 0) || !quadratic;
+        const bool factor = (it == 0) || (!quadratic && !reuse_next);
         double hinfo[4];
         // The exact Hessian (quadratic convergence; a Huber or model-variance loss makes the
         // Gauss-Newton form only linearly convergent); where it is not positive definite, the
@@ -165,6 +171,8 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
         }
         if (hinfo[0] != 0.0) break;  // not positive definite: keep the current point
         const double dec = hinfo[1];
+        const bool fast = factor || dec <= 0.25 * dec_prev;  // (a chord step's progress)
+        dec_prev = dec;
         // a negligible predicted decrease ends the polish at once
         if (!(dec > 2e-12 * (std::fabs(L) + 1.0))) {
             out->converged = 1;
@@ -195,12 +203,22 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
             }
         }
         if (!accepted) {
+            if (!factor && !quadratic) {
+                // a reused factor whose step no trial accepts: a fresh one from the same point (this
+                // try does not count as a step)
+                if (launch_newton_trial(th, d, 0.0, v.theta_eval, v.theta_eval64, n, s) != hipSuccess)
+                    return DIA_E_HIP;
+                reuse_next = false;
+                --it;
+                continue;
+            }
             // no trial point lowers the loss: at the resolution of FP32 parameters when the predicted
             // decrease is already tiny against the loss
             if (last || dec <= 1e-10 * (std::fabs(L) + 1.0)) out->converged = 1;
             if (launch_newton_trial(th, d, 0.0, v.theta_eval, v.theta_eval64, n, s) != hipSuccess) return DIA_E_HIP;
             break;
         }
+        reuse_next = alpha == 1.0 && fast;
         ++out->steps;
         if (last) out->converged = 1;
         if (out->converged) break;
