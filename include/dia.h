@@ -280,7 +280,10 @@ int dia_covariance_bg(const double* F, int32_t m, int32_t bg_degree, double* cov
  * exact per-pixel curvature; where that H is not positive definite, the
  * Gauss-Newton / IRLS weight) by Cholesky, with a backtracking
  * line search on the loss (trial points evaluated at their unrounded FP64
- * values); it stops when the Newton decrement -g.d is below
+ * values).  A quadratic loss factors H once; for the others a step taken in
+ * full lets the next reuse the factor of the point before, for as long as
+ * each such step shrinks -g.d fourfold (n_hessian counts the factors
+ * formed).  The polish stops when the Newton decrement -g.d is below
  * the FP64 resolution of the loss, the step below the FP32 resolution of
  * theta, or an accepted step lowers the loss by no more than 1e-13 |L| (the
  * rounding level of the loss summed over millions of pixels: the gradient
