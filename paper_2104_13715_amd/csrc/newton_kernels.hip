@@ -222,13 +222,28 @@ hipError_t launch_chol_factor(double* A, int n, double* flag, hipStream_t s) {
     return hipGetLastError();
 }
 
+// A double from lane l of the wave (l the same in every lane).
+__device__ __forceinline__ double lane_value(double v, int l) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffu), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Newton step d = -A^-1 g from the factor in A (launch_chol_factor), with info[0] its flag:
 // info = [not positive definite, decrement -g.d, max |d| / max |th|, max |d| in FP32 spacings of th].
+// Blocked substitutions, kSolveBlock rows at a time: the first wave solves the block's triangle (lane j
+// holding row j of it in registers, each step's quotient passed to the other lanes by readlane), then
+// every thread updates its rows outside the block with the block's solved values.
+constexpr int kSolveBlock = 32;
+
 __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(const double* A, int n, const double* g,
                                                                   const double* th, double* d, double* info) {
-    __shared__ double col[kMaxTheta];
+    constexpr int B = kSolveBlock;
+    __shared__ double col[kMaxTheta];  // the right-hand side being reduced
+    __shared__ double sol[kMaxTheta];  // y, then x
     __shared__ double sh[32];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     if (info[0] != 0.0) {
         __syncthreads();
         if (tid == 0) {
@@ -239,24 +254,76 @@ __global__ __launch_bounds__(kCholThreads) void chol_solve_kernel(const double* 
         }
         return;
     }
-    // forward: L y = -g (column-oriented), y kept in col[]
+    // forward: L y = -g, blocks top down (column k of L is row k of A: L[i][k] = A[k*n + i], i >= k)
     for (int i = tid; i < n; i += kCholThreads) col[i] = -g[i];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double yk = col[k] / A[(long long)k * n + k];
+    for (int k0 = 0; k0 < n; k0 += B) {
+        const int bs = n - k0 < B ? n - k0 : B;
+        if (tid < 64) {
+            double lr[B];  // lane j: L[k0 + j][k0 + k], k <= j
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < B; ++k) lr[k] = 0.0;
+            if (lane < bs) {
+                v = col[k0 + lane];
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    if (k <= lane) lr[k] = A[(long long)(k0 + k) * n + k0 + lane];
+            }
+#pragma unroll
+            for (int k = 0; k < B; ++k) {
+                if (k < bs) {
+                    const double yk = lane_value(v, k) / lane_value(lr[k], k);
+                    if (lane == k) sol[k0 + k] = yk;
+                    if (lane > k && lane < bs) v -= lr[k] * yk;
+                }
+            }
+        }
         __syncthreads();
-        if (tid == 0) col[k] = yk;
-        for (int i = k + 1 + tid; i < n; i += kCholThreads) col[i] -= A[(long long)k * n + i] * yk;
+        for (int i = k0 + bs + tid; i < n; i += kCholThreads) {
+            double s = col[i];
+            for (int k = 0; k < bs; ++k) s -= A[(long long)(k0 + k) * n + i] * sol[k0 + k];
+            col[i] = s;
+        }
         __syncthreads();
     }
-    // backward: L^T x = y, with L[k][i] = A[i*n + k]
-    for (int k = n - 1; k >= 0; --k) {
-        const double xk = col[k] / A[(long long)k * n + k];
+    // backward: L^T x = y, blocks bottom up (L[k][i] = A[i*n + k], i <= k), y reduced in col[], x into sol[]
+    for (int i = tid; i < n; i += kCholThreads) col[i] = sol[i];
+    __syncthreads();
+    for (int k0 = ((n - 1) / B) * B; k0 >= 0; k0 -= B) {
+        const int bs = n - k0 < B ? n - k0 : B;
+        if (tid < 64) {
+            double lr[B];  // lane j: L[k0 + k][k0 + j] = A[(k0 + j)*n + k0 + k], k >= j
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < B; ++k) lr[k] = 0.0;
+            if (lane < bs) {
+                v = col[k0 + lane];
+                const double* row = A + (long long)(k0 + lane) * n + k0;
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    if (k >= lane && k < bs) lr[k] = row[k];
+            }
+#pragma unroll
+            for (int k = B - 1; k >= 0; --k) {
+                if (k < bs) {
+                    const double xk = lane_value(v, k) / lane_value(lr[k], k);
+                    if (lane == k) sol[k0 + k] = xk;
+                    if (lane < k) v -= lr[k] * xk;
+                }
+            }
+        }
         __syncthreads();
-        if (tid == 0) col[k] = xk;
-        for (int i = tid; i < k; i += kCholThreads) col[i] -= A[(long long)i * n + k] * xk;
+        for (int i = tid; i < k0; i += kCholThreads) {
+            const double* row = A + (long long)i * n + k0;
+            double s = col[i];
+            for (int k = 0; k < bs; ++k) s -= row[k] * sol[k0 + k];
+            col[i] = s;
+        }
         __syncthreads();
     }
+    for (int i = tid; i < n; i += kCholThreads) col[i] = sol[i];
+    __syncthreads();
     double dec = 0.0, dmax = 0.0, tmax = 0.0, qmax = 0.0;
     for (int i = tid; i < n; i += kCholThreads) {
         d[i] = col[i];
