@@ -205,9 +205,13 @@ int newton_polish(const dia_image& R, const dia_image& I, const ObjParams& obj, 
         if (!accepted) {
             if (!factor && !quadratic) {
                 // a reused factor whose step no trial accepts: a fresh one from the same point (this
-                // try does not count as a step)
+                // try does not count as a step); the trials overwrote gt, so the gradient there is
+                // evaluated again
                 if (launch_newton_trial(th, d, 0.0, v.theta_eval, v.theta_eval64, n, s) != hipSuccess)
                     return DIA_E_HIP;
+                if (!eval_into(R, I, obj, reg, m, bg_deg, grid, variant, v.theta_eval, v.theta_eval64, partial, gt, s))
+                    return DIA_E_HIP;
+                ++out->evals;
                 reuse_next = false;
                 --it;
                 continue;
